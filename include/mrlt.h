@@ -1,0 +1,160 @@
+/* mrlt.h -- C ABI of the MI355X (gfx950) library for one local-time-stepping
+ * macro step of the space-time adaptive multiresolution finite-volume method
+ * with NERK synchronisation (MRLT/NERK3), arXiv:1905.08717.
+ *
+ * Problem (Sec. 2, eq. pde): dQ/dt = -div F(Q, grad Q) + S(Q) on a box in
+ * d = 1, 2, 3 dimensions, discretised by cell averages on a dynamic graded
+ * dyadic tree of levels l0..L (Sec. 2), advanced by compact RK3 (Sec. 3)
+ * with level-dependent steps dt_l = 2^{L-l} dt_L (Sec. 4, eq. dt) and NERK
+ * synchronisation between levels (Sec. 4.1-4.3, appendix algorithms).
+ *
+ * Conventions for every call:
+ *  - Return value: mr_status, 0 = MR_OK, negative = error.  No exception or
+ *    abort crosses the interface; mr_last_error() describes the last error.
+ *  - All floating point data are FP64.
+ *  - "device" pointers are HIP device memory (e.g. a torch tensor's
+ *    data_ptr()); "host" pointers are ordinary host memory.
+ *  - The context owns all of its device memory; input buffers are borrowed
+ *    (copied in), output buffers are allocated by the caller.
+ *  - Work is queued on the stream given to mr_set_stream / mr_load_finest
+ *    (default: the null stream).  mr_lt_step, mr_reconstruct,
+ *    mr_max_wavespeed, mr_get_leaves, mr_stats synchronise that stream
+ *    before returning.
+ *  - One host thread per context at a time.
+ *  - A batch context holds n_inst independent solves with the same dim, L,
+ *    scheme and per-instance eps; every kernel launch advances all of them.
+ *    The single-solve calls act on a batch of one.
+ *  - Errors are sticky: after MR_ENONFINITE or MR_ESTATE the context refuses
+ *    mr_lt_step until mr_load_finest or mr_set_leaves resets it.
+ */
+#ifndef MRLT_H
+#define MRLT_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mr_ctx mr_ctx;
+
+typedef enum {
+  MR_OK = 0,
+  MR_EINVAL = -1,      /* bad argument */
+  MR_ENOMEM = -2,      /* device allocation failed */
+  MR_EDEVICE = -3,     /* HIP runtime error */
+  MR_ESTATE = -4,      /* tree invariant violated or context in error state */
+  MR_ENONFINITE = -5,  /* a cell average became NaN / Inf */
+  MR_ECAPACITY = -6    /* output buffer too small */
+} mr_status;
+
+enum { MR_PDE_ADVECTION = 0, MR_PDE_BURGERS = 1, MR_PDE_NAGUMO = 2, MR_PDE_EULER = 3, MR_PDE_LINEAR = 4 };
+enum { MR_BC_PERIODIC = 0, MR_BC_NEUMANN = 1 };
+
+#define MR_MAXLEV 24
+
+/* Scheme description (Sec. 2 and Sec. 5 of the paper for the PDEs):
+ *  pde     advection (m=1, flux a.q), Burgers (m=1, u^2/2 - nu u_x, exact
+ *          Godunov advective flux), Nagumo (m=1, -nu grad u, source
+ *          k u (1-u)(u-a)), Euler (m=d+2: rho, rho u_i, E; AUSM+), linear
+ *          (m=1, -nu grad u, source k u)
+ *  rk      3 (compact RK3 with NERK partials, Sec. 3)
+ *  lt      1 (local time stepping, Sec. 4)
+ *  l0      coarsest level, >= 2
+ *  recon   0 first order, 1 MUSCL-minmod, 2 centred (advection only)
+ *  thresh  1: eps_l = 2^{d(l-L)} eps for details of level l, 0: fixed eps
+ *  reflux  1: conservative correction of coarse leaves at level interfaces
+ *  remesh  1: remesh the evolved levels every iteration, 0: frozen tree
+ *  bc      per dimension, low/high side: periodic or homogeneous Neumann
+ *          (even reflection); periodic must be set on both sides
+ *  lo, hi  box, per dimension
+ *  detail_scale  per component divisor in the detail norm (0 -> 1.0)     */
+typedef struct {
+  int32_t pde, rk, lt, l0, recon, thresh, reflux, remesh;
+  int32_t bc[3][2];
+  double lo[3], hi[3];
+  double nu, k_react, a_react, gamma, adv_vel[3];
+  double detail_scale[5];
+} mr_scheme;
+
+typedef struct {
+  double t;                        /* time of the instance */
+  int64_t leaves[MR_MAXLEV + 1];   /* leaves per level */
+  int64_t leaf_updates;            /* cumulative, one per leaf per full RK step */
+  int64_t near_threshold;          /* cumulative |detail - eps_l| <= 1e-12 eps_l decisions */
+  int64_t iterations;              /* cumulative fine iterations */
+  double mass[5];                  /* sum over leaves of |cell| q, per component */
+} mr_stats_t;
+
+/* Create a single solve (Sec. 2: the IVP on a box; Alg. waveletThres takes
+ * the finest level L, the level-L solution and the threshold eps).
+ * dim in 1..3, l0 >= 2, l0 <= L, L - l0 <= 20, dim*L <= 3*MR_MAXLEV,
+ * eps >= 0 (eps = 0 keeps the full tree).  *out receives the context.      */
+mr_status mr_init(int dim, int L, double eps, const mr_scheme* s, mr_ctx** out);
+
+/* Create a batch of n_inst independent solves sharing dim, L and scheme;
+ * eps is a host array of n_inst thresholds.                                */
+mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_scheme* s, mr_ctx** out);
+
+/* Stream (hipStream_t, may be NULL) on which later work is queued. */
+mr_status mr_set_stream(mr_ctx* c, void* hip_stream);
+
+/* Number of conserved fields m of the scheme. */
+int mr_ncomp(const mr_ctx* c);
+
+/* Load finest-level cell averages and build the adapted tree: all levels
+ * below L internal, projection bottom-up (Sec. 2), then mr_adapt.
+ * q0: device, [n_inst][m][2^{dL}], x fastest (index x + n(y + n z)).      */
+mr_status mr_load_finest(mr_ctx* c, const double* q0, void* hip_stream);
+
+/* Full remesh at the current synchronised time (Alg. AdaptiveMesh with
+ * Alg. waveletThres; no level frozen).                                     */
+mr_status mr_adapt(mr_ctx* c);
+
+/* One macro step of 2^{L-l0} fine iterations of Alg. alg-LTS with finest
+ * step dt_L > 0: all instances use dt_L.  Synchronises the stream and
+ * returns MR_ENONFINITE if a value became NaN/Inf.                         */
+mr_status mr_lt_step(mr_ctx* c, double dt_L);
+
+/* Same, with a per-instance finest step (host array of n_inst values).    */
+mr_status mr_lt_step_batch(mr_ctx* c, const double* dt_L);
+
+/* Dense finest-level averages from the tree: projection, then prediction
+ * coarse to fine where cells are absent (the inverse MR transform, Sec. 2).
+ * q_out: device, [n_inst][m][2^{dL}], x fastest.                          */
+mr_status mr_reconstruct(mr_ctx* c, double* q_out);
+
+/* CFL helper: per instance the maximum over leaves of |u| (Burgers),
+ * sum_i (|u_i| + c) (Euler), sum_i |a_i| (advection), 0 otherwise.
+ * out: host array of n_inst values.                                        */
+mr_status mr_max_wavespeed(mr_ctx* c, double* out);
+
+/* Leaves of instance 0 (or `inst`) sorted by (level, Morton key):
+ * key = level << 56 | morton, values q[k * n + i] (host buffers).  With
+ * keys == NULL only *n is set.  MR_ECAPACITY if cap < number of leaves.    */
+mr_status mr_get_leaves(mr_ctx* c, uint64_t* keys, double* q, int64_t cap, int64_t* n);
+mr_status mr_get_leaves_inst(mr_ctx* c, int inst, uint64_t* keys, double* q, int64_t cap, int64_t* n);
+
+/* Replace the tree of instance 0 (or `inst`) by the given leaves (same key
+ * and value layout, host buffers) at time t.  The leaves must form a
+ * complete tree over level l0 that is graded (every cell within distance 2
+ * of an internal node exists); MR_EINVAL otherwise.                        */
+mr_status mr_set_leaves(mr_ctx* c, const uint64_t* keys, const double* q, int64_t n, double t);
+mr_status mr_set_leaves_inst(mr_ctx* c, int inst, const uint64_t* keys, const double* q, int64_t n, double t);
+
+/* Statistics of instance 0 (or `inst`). */
+mr_status mr_stats(mr_ctx* c, mr_stats_t* out);
+mr_status mr_stats_inst(mr_ctx* c, int inst, mr_stats_t* out);
+
+/* Wait for all queued work of the context. */
+mr_status mr_synchronize(mr_ctx* c);
+
+/* Description of the last error of the context (never NULL). */
+const char* mr_last_error(const mr_ctx* c);
+
+/* Release the context and all of its device memory (NULL is ignored). */
+void mr_destroy(mr_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,1199 @@
+// kernels.hip -- HIP kernels of the MRLT/NERK3 macro step for gfx950.
+//
+// Every kernel walks one level of every instance of a batch with a
+// grid-stride loop over the level's Morton-indexed cells (instance in the
+// high bits of the loop index).  FP64 throughout; the library is built with
+// -ffp-contract=off so each expression rounds exactly as written.
+//
+// Method: arXiv:1905.08717 (Lopes, Domingues, Mendes, Schneider), Secs. 2-4
+// and the appendix algorithms; readings where the paper is silent are noted
+// where they are used.
+#include "mrlt_internal.h"
+
+#define GSL(t, N) \
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (N); \
+       t += (int64_t)gridDim.x * blockDim.x)
+
+static constexpr int TPB = 256;
+
+int blocks_for(int64_t n) {
+  int64_t b = (n + TPB - 1) / TPB;
+  if (b < 1) b = 1;
+  if (b > 8192) b = 8192;
+  return (int)b;
+}
+
+// ---------------------------------------------------------------------------
+// Morton keys and boundary maps
+
+__device__ __forceinline__ uint64_t part1by1(uint64_t x) {
+  x &= 0xffffffffull;
+  x = (x | (x << 16)) & 0x0000ffff0000ffffull;
+  x = (x | (x << 8)) & 0x00ff00ff00ff00ffull;
+  x = (x | (x << 4)) & 0x0f0f0f0f0f0f0f0full;
+  x = (x | (x << 2)) & 0x3333333333333333ull;
+  x = (x | (x << 1)) & 0x5555555555555555ull;
+  return x;
+}
+__device__ __forceinline__ uint64_t compact1by1(uint64_t x) {
+  x &= 0x5555555555555555ull;
+  x = (x | (x >> 1)) & 0x3333333333333333ull;
+  x = (x | (x >> 2)) & 0x0f0f0f0f0f0f0f0full;
+  x = (x | (x >> 4)) & 0x00ff00ff00ff00ffull;
+  x = (x | (x >> 8)) & 0x0000ffff0000ffffull;
+  x = (x | (x >> 16)) & 0x00000000ffffffffull;
+  return x;
+}
+__device__ __forceinline__ uint64_t part1by2(uint64_t x) {
+  x &= 0x1fffffull;
+  x = (x | (x << 32)) & 0x1f00000000ffffull;
+  x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+  x = (x | (x << 8)) & 0x100f00f00f00f00full;
+  x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+  x = (x | (x << 2)) & 0x1249249249249249ull;
+  return x;
+}
+__device__ __forceinline__ uint64_t compact1by2(uint64_t x) {
+  x &= 0x1249249249249249ull;
+  x = (x | (x >> 2)) & 0x10c30c30c30c30c3ull;
+  x = (x | (x >> 4)) & 0x100f00f00f00f00full;
+  x = (x | (x >> 8)) & 0x1f0000ff0000ffull;
+  x = (x | (x >> 16)) & 0x1f00000000ffffull;
+  x = (x | (x >> 32)) & 0x1fffffull;
+  return x;
+}
+
+template <int D>
+__device__ __forceinline__ uint64_t menc(const int* x) {
+  if (D == 1) return (uint64_t)x[0];
+  if (D == 2) return part1by1((uint64_t)x[0]) | (part1by1((uint64_t)x[1]) << 1);
+  return part1by2((uint64_t)x[0]) | (part1by2((uint64_t)x[1]) << 1) | (part1by2((uint64_t)x[2]) << 2);
+}
+
+template <int D>
+__device__ __forceinline__ void mdec(uint64_t k, int* x) {
+  x[1] = x[2] = 0;
+  if (D == 1) {
+    x[0] = (int)k;
+  } else if (D == 2) {
+    x[0] = (int)compact1by1(k);
+    x[1] = (int)compact1by1(k >> 1);
+  } else {
+    x[0] = (int)compact1by2(k);
+    x[1] = (int)compact1by2(k >> 1);
+    x[2] = (int)compact1by2(k >> 2);
+  }
+}
+
+// stencil coordinate: periodic wraps, homogeneous Neumann reflects evenly
+__device__ __forceinline__ int map_st(int i, int n, int per) {
+  if (i < 0) return per ? i + n : -1 - i;
+  if (i >= n) return per ? i - n : 2 * n - 1 - i;
+  return i;
+}
+// neighbourhood coordinate: wraps when periodic, -1 outside otherwise
+__device__ __forceinline__ int map_nb(int i, int n, int per) {
+  if (i < 0) return per ? i + n : -1;
+  if (i >= n) return per ? i - n : -1;
+  return i;
+}
+
+__device__ __forceinline__ void flag_bad(const Dev& p, int64_t inst, unsigned long long code) {
+  atomicOr(&p.cnt[inst * CNT_PER_INST + CNT_BAD], code);
+}
+
+// ---------------------------------------------------------------------------
+// prediction (Sec. 2): 1D q -/+ (q_{i+1}-q_{i-1})/8, tensor product in
+// multi-D.  Terms T: q, qx, qy, qz, qxy, qxz, qyz, qxyz; child c = a|b<<1|e<<2.
+
+template <int D>
+__device__ __forceinline__ void pred_terms(const double* S, double* T) {
+#define P(ox, oy, oz) S[((ox) + 1) + 3 * ((oy) + 1) + 9 * ((oz) + 1)]
+  T[0] = P(0, 0, 0);
+  T[1] = (P(1, 0, 0) - P(-1, 0, 0)) * 0.125;
+  if (D >= 2) {
+    T[2] = (P(0, 1, 0) - P(0, -1, 0)) * 0.125;
+    T[4] = ((P(1, 1, 0) - P(1, -1, 0)) - (P(-1, 1, 0) - P(-1, -1, 0))) * 0.015625;
+  }
+  if (D == 3) {
+    T[3] = (P(0, 0, 1) - P(0, 0, -1)) * 0.125;
+    T[5] = ((P(1, 0, 1) - P(1, 0, -1)) - (P(-1, 0, 1) - P(-1, 0, -1))) * 0.015625;
+    T[6] = ((P(0, 1, 1) - P(0, 1, -1)) - (P(0, -1, 1) - P(0, -1, -1))) * 0.015625;
+    T[7] = (((P(1, 1, 1) - P(1, 1, -1)) - (P(1, -1, 1) - P(1, -1, -1))) -
+            ((P(-1, 1, 1) - P(-1, 1, -1)) - (P(-1, -1, 1) - P(-1, -1, -1)))) *
+           0.001953125;
+  }
+#undef P
+}
+
+template <int D>
+__device__ __forceinline__ double pred_child(const double* T, int cb) {
+  const int a = cb & 1, b = (cb >> 1) & 1, e = (cb >> 2) & 1;
+  double v = T[0];
+  v = a ? v + T[1] : v - T[1];
+  if (D == 1) return v;
+  v = b ? v + T[2] : v - T[2];
+  if (D == 2) return (a == b) ? v + T[4] : v - T[4];
+  v = e ? v + T[3] : v - T[3];
+  v = (a == b) ? v + T[4] : v - T[4];
+  v = (a == e) ? v + T[5] : v - T[5];
+  v = (b == e) ? v + T[6] : v - T[6];
+  v = ((a ^ b ^ e) == 1) ? v + T[7] : v - T[7];
+  return v;
+}
+
+// 3^D stencil of component k of `src` around x at level lev (mapped by the
+// boundary conditions); returns false when a stencil cell does not exist.
+template <int D>
+__device__ __forceinline__ bool gather27(const Geo& g, const Dev& p, const double* src, int lev,
+                                         int64_t ibase, const int* x, int k, double* S) {
+  const int n = 1 << lev;
+  bool ok = true;
+#pragma unroll
+  for (int oz = (D > 2 ? -1 : 0); oz <= (D > 2 ? 1 : 0); oz++)
+#pragma unroll
+    for (int oy = (D > 1 ? -1 : 0); oy <= (D > 1 ? 1 : 0); oy++)
+#pragma unroll
+      for (int ox = -1; ox <= 1; ox++) {
+        int y[3] = {map_st(x[0] + ox, n, g.periodic[0]), 0, 0};
+        if (D > 1) y[1] = map_st(x[1] + oy, n, g.periodic[1]);
+        if (D > 2) y[2] = map_st(x[2] + oz, n, g.periodic[2]);
+        const int64_t G = ibase + (int64_t)menc<D>(y);
+        ok = ok && (p.st[G] != ST_ABSENT);
+        S[(ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)] = src[(int64_t)k * g.Ntot + G];
+      }
+  return ok;
+}
+
+// ---------------------------------------------------------------------------
+// numerical fluxes (Sec. 5 of the paper names AUSM+; readings: MUSCL-minmod
+// reconstruction, exact Godunov flux for the scalar Burgers law, centred
+// two-point diffusion, interface sound speed = mean of the two sides)
+
+__device__ __forceinline__ double minmod(double a, double b) {
+  if (a > 0.0 && b > 0.0) return a < b ? a : b;
+  if (a < 0.0 && b < 0.0) return a > b ? a : b;
+  return 0.0;
+}
+
+__device__ __forceinline__ void recon4(int mode, double c0, double c1, double c2, double c3,
+                                       double& qL, double& qR) {
+  if (mode == 1) {
+    const double sl = minmod(c1 - c0, c2 - c1);
+    const double sr = minmod(c2 - c1, c3 - c2);
+    qL = c1 + 0.5 * sl;
+    qR = c2 - 0.5 * sr;
+  } else {
+    qL = c1;
+    qR = c2;
+  }
+}
+
+__device__ __forceinline__ double mach_plus(double M) {
+  if (fabs(M) < 1.0) {
+    const double t = M + 1.0, q = (M * M) - 1.0;
+    return (0.25 * (t * t)) + (0.125 * (q * q));
+  }
+  return 0.5 * (M + fabs(M));
+}
+__device__ __forceinline__ double mach_minus(double M) {
+  if (fabs(M) < 1.0) {
+    const double t = M - 1.0, q = (M * M) - 1.0;
+    return (-(0.25 * (t * t))) - (0.125 * (q * q));
+  }
+  return 0.5 * (M - fabs(M));
+}
+__device__ __forceinline__ double pres_plus(double M) {
+  if (fabs(M) < 1.0) {
+    const double t = M + 1.0, q = (M * M) - 1.0;
+    return ((0.25 * (t * t)) * (2.0 - M)) + ((0.1875 * M) * (q * q));
+  }
+  return M > 0.0 ? 1.0 : 0.0;
+}
+__device__ __forceinline__ double pres_minus(double M) {
+  if (fabs(M) < 1.0) {
+    const double t = M - 1.0, q = (M * M) - 1.0;
+    return ((0.25 * (t * t)) * (2.0 + M)) - ((0.1875 * M) * (q * q));
+  }
+  return M < 0.0 ? 1.0 : 0.0;
+}
+
+template <int D>
+__device__ __forceinline__ void euler_prim(double gm1, const double* q, double* w) {
+  const double rho = q[0];
+  double kin = 0.0;
+  w[0] = rho;
+#pragma unroll
+  for (int i = 0; i < D; i++) {
+    const double u = q[1 + i] / rho;
+    w[1 + i] = u;
+    kin = (i == 0) ? (u * u) : (kin + (u * u));
+  }
+  w[D + 1] = gm1 * (q[D + 1] - ((0.5 * rho) * kin));
+}
+
+template <int D>
+__device__ __forceinline__ void ausm_plus(int dir, double gamma, const double* wl, const double* wr,
+                                          double* F) {
+  const double gm1 = gamma - 1.0;
+  const double rl = wl[0], pl = wl[D + 1], rr = wr[0], pr = wr[D + 1];
+  const double al = sqrt((gamma * pl) / rl), ar = sqrt((gamma * pr) / rr);
+  const double ah = 0.5 * (al + ar);
+  const double ml = wl[1 + dir] / ah, mr = wr[1 + dir] / ah;
+  const double mh = mach_plus(ml) + mach_minus(mr);
+  const double ph = (pres_plus(ml) * pl) + (pres_minus(mr) * pr);
+  const double mp = 0.5 * (mh + fabs(mh)), mm = 0.5 * (mh - fabs(mh));
+  double kl = 0.0, kr = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; i++) {
+    kl = (i == 0) ? (wl[1] * wl[1]) : (kl + (wl[1 + i] * wl[1 + i]));
+    kr = (i == 0) ? (wr[1] * wr[1]) : (kr + (wr[1 + i] * wr[1 + i]));
+  }
+  const double hl = ((pl / gm1) + ((0.5 * rl) * kl)) + pl;
+  const double hr = ((pr / gm1) + ((0.5 * rr) * kr)) + pr;
+  F[0] = ah * ((mp * rl) + (mm * rr));
+#pragma unroll
+  for (int i = 0; i < D; i++) F[1 + i] = ah * ((mp * (rl * wl[1 + i])) + (mm * (rr * wr[1 + i])));
+  F[1 + dir] = F[1 + dir] + ph;
+  F[D + 1] = ah * ((mp * hl) + (mm * hr));
+}
+
+template <int D, int PDE>
+struct NC {
+  static constexpr int M = (PDE == PDE_EULER) ? D + 2 : 1;
+};
+
+// flux across the face between cells a and a+1 along dir; c holds a-1..a+2
+template <int D, int PDE>
+__device__ __forceinline__ void face_flux(const Geo& g, int lev, int dir,
+                                          const double (*c)[NC<D, PDE>::M], double* F) {
+  const double ix = g.invdx[lev][dir];
+  if (PDE == PDE_ADVECTION) {
+    const double vel = g.adv[dir];
+    if (g.recon == 2) {
+      F[0] = vel * (0.5 * (c[1][0] + c[2][0]));
+    } else {
+      double qL, qR;
+      recon4(g.recon, c[0][0], c[1][0], c[2][0], c[3][0], qL, qR);
+      F[0] = vel >= 0.0 ? vel * qL : vel * qR;
+    }
+  } else if (PDE == PDE_BURGERS) {
+    double uL, uR;
+    recon4(g.recon, c[0][0], c[1][0], c[2][0], c[3][0], uL, uR);
+    const double a = uL > 0.0 ? uL : 0.0;
+    const double b = uR < 0.0 ? uR : 0.0;
+    const double fa = 0.5 * (a * a), fb = 0.5 * (b * b);
+    const double fadv = fa > fb ? fa : fb;
+    const double nudx = g.nu * ix;
+    F[0] = fadv - (nudx * (c[2][0] - c[1][0]));
+  } else if (PDE == PDE_NAGUMO || PDE == PDE_LINEAR) {
+    const double nudx = g.nu * ix;
+    F[0] = -(nudx * (c[2][0] - c[1][0]));
+  } else {
+    constexpr int M = D + 2;
+    const double gm1 = g.gamma - 1.0;
+    double w[4][M], wl[M], wr[M];
+#pragma unroll
+    for (int j = 0; j < 4; j++) euler_prim<D>(gm1, c[j], w[j]);
+#pragma unroll
+    for (int k = 0; k < M; k++) recon4(g.recon, w[0][k], w[1][k], w[2][k], w[3][k], wl[k], wr[k]);
+    ausm_plus<D>(dir, g.gamma, wl, wr, F);
+  }
+}
+
+template <int PDE>
+__device__ __forceinline__ double source(const Geo& g, double u) {
+  if (PDE == PDE_NAGUMO) return ((g.k_react * u) * (1.0 - u)) * (u - g.a_react);
+  return g.k_react * u;
+}
+
+// ---------------------------------------------------------------------------
+// status fill, initial load, dense reconstruction
+
+__global__ void k_fill_status(uint8_t* st, int64_t base, int64_t n, uint8_t v) {
+  GSL(t, n) st[base + t] = v;
+}
+
+void launch_fill_status(const Geo& g, const Dev& p, int lev, uint8_t v, hipStream_t s) {
+  const int64_t n = g.B * g.n[lev];
+  k_fill_status<<<blocks_for(n), TPB, 0, s>>>(p.st, g.off[lev], n, v);
+}
+
+template <int D>
+__global__ void k_load_finest(Geo g, Dev p, const double* src) {
+  const int L = g.L;
+  const int64_t nl = g.n[L], N = g.B * nl;
+  const int n = 1 << L;
+  GSL(t, N) {
+    const int64_t inst = t >> (D * L);
+    int x[3];
+    mdec<D>((uint64_t)(t & (nl - 1)), x);
+    const int64_t r = x[0] + (int64_t)n * (x[1] + (int64_t)n * x[2]);
+    const int64_t G = g.off[L] + t;
+    for (int k = 0; k < g.m; k++) p.q[SL_Q0][(int64_t)k * g.Ntot + G] = src[(inst * g.m + k) * nl + r];
+    p.st[G] = ST_LEAF;
+  }
+}
+
+template <int D>
+__global__ void k_recon_level(Geo g, Dev p, int lev, double* dense) {
+  const int64_t nl = g.n[lev], N = g.B * nl;
+  GSL(t, N) {
+    const int64_t G = g.off[lev] + t;
+    if (lev == g.l0 || p.st[G] != ST_ABSENT) {
+      for (int k = 0; k < g.m; k++) dense[(int64_t)k * g.Ntot + G] = p.q[SL_Q0][(int64_t)k * g.Ntot + G];
+      continue;
+    }
+    const int64_t inst = t >> (D * lev);
+    int x[3];
+    mdec<D>((uint64_t)(t & (nl - 1)), x);
+    const int px[3] = {x[0] >> 1, x[1] >> 1, x[2] >> 1};
+    const int n = 1 << (lev - 1);
+    const int64_t ibp = g.off[lev - 1] + inst * g.n[lev - 1];
+    const int cb = (x[0] & 1) | ((x[1] & 1) << 1) | ((x[2] & 1) << 2);
+    for (int k = 0; k < g.m; k++) {
+      double S[27], T[8];
+#pragma unroll
+      for (int oz = (D > 2 ? -1 : 0); oz <= (D > 2 ? 1 : 0); oz++)
+#pragma unroll
+        for (int oy = (D > 1 ? -1 : 0); oy <= (D > 1 ? 1 : 0); oy++)
+#pragma unroll
+          for (int ox = -1; ox <= 1; ox++) {
+            int y[3] = {map_st(px[0] + ox, n, g.periodic[0]), 0, 0};
+            if (D > 1) y[1] = map_st(px[1] + oy, n, g.periodic[1]);
+            if (D > 2) y[2] = map_st(px[2] + oz, n, g.periodic[2]);
+            S[(ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)] = dense[(int64_t)k * g.Ntot + ibp + (int64_t)menc<D>(y)];
+          }
+      pred_terms<D>(S, T);
+      dense[(int64_t)k * g.Ntot + G] = pred_child<D>(T, cb);
+    }
+  }
+}
+
+template <int D>
+__global__ void k_to_rowmajor(Geo g, const double* dense, double* out) {
+  const int L = g.L;
+  const int64_t nl = g.n[L], N = g.B * nl;
+  const int n = 1 << L;
+  GSL(t, N) {
+    const int64_t inst = t >> (D * L);
+    int x[3];
+    mdec<D>((uint64_t)(t & (nl - 1)), x);
+    const int64_t r = x[0] + (int64_t)n * (x[1] + (int64_t)n * x[2]);
+    for (int k = 0; k < g.m; k++) out[(inst * g.m + k) * nl + r] = dense[(int64_t)k * g.Ntot + g.off[L] + t];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// projections: the parent value is the mean of its 2^d children, summed in
+// child order and scaled by 2^{-d} (Sec. 2).  The modes are the internal-
+// node synchronisation values of Sec. 4:
+//   PJ_Q0    Alg. alg-LTS: q^n of internal nodes
+//   PJ_CASEB Alg. alg-LTS / Sec. 4.3, level l_min - 1 at mid-step: the
+//            theta=1/2 value (into QH) and -2 q^n - q* + 4 q_{1/2} (into QE)
+//   PJ_REF2  Alg. refRK2: q(t + dt/2) from the children's q* (eq.
+//            refreshRk2 for internal children), then q* = 2 q(t+dt/2) - q^n
+//   PJ_RK2   Alg. projRK2: mean of the children's extrapolations to
+//            t + 2 dt_{l+1} (eqs. projleaf and projnode)
+//   PJ_REF3  Alg. refRK22: q_{1/4} from the children's q**, then
+//            eqs. ProjRK3equations1 / ProjRK3equations2
+//   PJ_RK3   Alg. projRK3: q** from the children's stage-3 values, then
+//            eq. rk3proj
+
+__global__ __launch_bounds__(TPB) void k_project(Geo g, Dev p, int lev, int mode) {
+  const int64_t N = g.B * g.n[lev];
+  const int nch = 1 << g.d;
+  const double sc = g.d == 1 ? 0.5 : (g.d == 2 ? 0.25 : 0.125);
+  const int64_t NT = g.Ntot;
+  GSL(t, N) {
+    const int64_t G = g.off[lev] + t;
+    if (p.st[G] != ST_INTERNAL) continue;
+    const int64_t C0 = g.off[lev + 1] + (t << g.d);
+    uint8_t cs[8];
+    for (int cb = 0; cb < nch; cb++) cs[cb] = p.st[C0 + cb];
+    for (int k = 0; k < g.m; k++) {
+      const int64_t kk = (int64_t)k * NT;
+      double s = 0.0;
+      for (int cb = 0; cb < nch; cb++) {
+        const int64_t C = kk + C0 + cb;
+        double v;
+        if (mode == PJ_Q0 || mode == PJ_CASEB) v = p.q[SL_Q0][C];
+        else if (mode == PJ_REF2) v = cs[cb] == ST_LEAF ? p.q[SL_Q1][C] : p.q[SL_Q1REF][C];
+        else if (mode == PJ_RK2) v = cs[cb] == ST_LEAF ? p.q[SL_X2][C] : (2.0 * p.q[SL_Q1][C]) - p.q[SL_Q0][C];
+        else if (mode == PJ_REF3) v = p.q[SL_QH][C];
+        else v = p.q[SL_QE][C];
+        s = (cb == 0) ? v : (s + v);
+      }
+      s = s * sc;
+      const int64_t I = kk + G;
+      if (mode == PJ_Q0) {
+        p.q[SL_Q0][I] = s;
+      } else if (mode == PJ_CASEB) {
+        p.q[SL_QH][I] = s;
+        p.q[SL_QE][I] = ((-2.0 * p.q[SL_Q0][I]) - p.q[SL_Q1REF][I]) + (4.0 * s);
+      } else if (mode == PJ_REF2) {
+        p.q[SL_H1][I] = s;
+        p.q[SL_Q1REF][I] = (2.0 * s) - p.q[SL_Q0][I];
+      } else if (mode == PJ_RK2) {
+        p.q[SL_Q1][I] = s;
+      } else if (mode == PJ_REF3) {
+        const double q0 = p.q[SL_Q0][I], qs = p.q[SL_Q1REF][I];
+        p.q[SL_N14][I] = s;
+        p.q[SL_N34][I] = ((-6.5 * q0) - (1.5 * qs)) + (9.0 * s);
+        p.q[SL_QH][I] = ((-5.5 * q0) - (1.5 * qs)) + (8.0 * s);
+      } else {
+        p.q[SL_QH][I] = s;
+        p.q[SL_QE][I] = p.q[SL_Q0][I] + (2.0 * (p.q[SL_N34][I] - p.q[SL_N14][I]));
+      }
+    }
+  }
+}
+
+void launch_project(const Geo& g, const Dev& p, int lev, int mode, hipStream_t s) {
+  const int64_t n = g.B * g.n[lev];
+  k_project<<<blocks_for(n), TPB, 0, s>>>(g, p, lev, mode);
+}
+
+// ---------------------------------------------------------------------------
+// virtual cells: absent cells read by a leaf stencil get the value predicted
+// from the parent level at the time the stage needs (Sec. 4):
+//   case A (parent level also starts at t^n): S1 q^n, S2 first-order
+//     theta=1/2 value, S3 theta=1/4 value (Alg. refRK22)
+//   case B (parent level l_min - 1 at mid-step): S1 q** / theta=1/2
+//     projection, S2 end value, S3 theta=3/4 value (Alg. refRK22, Sec. 4.3)
+
+template <int D>
+__global__ __launch_bounds__(TPB) void k_ghost(Geo g, Dev p, int lev, int src, int dst) {
+  const int64_t nl = g.n[lev], N = g.B * nl;
+  GSL(t, N) {
+    const int64_t G = g.off[lev] + t;
+    if (!p.gh[G]) continue;
+    const int64_t inst = t >> (D * lev);
+    int x[3];
+    mdec<D>((uint64_t)(t & (nl - 1)), x);
+    const int px[3] = {x[0] >> 1, x[1] >> 1, x[2] >> 1};
+    const int64_t ibp = g.off[lev - 1] + inst * g.n[lev - 1];
+    const int cb = (x[0] & 1) | ((x[1] & 1) << 1) | ((x[2] & 1) << 2);
+    for (int k = 0; k < g.m; k++) {
+      double S[27], T[8];
+      if (!gather27<D>(g, p, p.q[src], lev - 1, ibp, px, k, S)) flag_bad(p, inst, 1);
+      pred_terms<D>(S, T);
+      p.q[dst][(int64_t)k * g.Ntot + G] = pred_child<D>(T, cb);
+    }
+  }
+}
+
+void launch_ghost(const Geo& g, const Dev& p, int lev, int stage, int caseb, hipStream_t s) {
+  const int src = caseb ? (stage == 1 ? SL_QH : (stage == 2 ? SL_QE : SL_N34))
+                        : (stage == 1 ? SL_Q0 : (stage == 2 ? SL_H1 : SL_N14));
+  const int dst = stage == 1 ? SL_Q0 : (stage == 2 ? SL_Q1 : SL_QH);
+  const int64_t n = g.B * g.n[lev];
+  if (g.d == 1) k_ghost<1><<<blocks_for(n), TPB, 0, s>>>(g, p, lev, src, dst);
+  else if (g.d == 2) k_ghost<2><<<blocks_for(n), TPB, 0, s>>>(g, p, lev, src, dst);
+  else k_ghost<3><<<blocks_for(n), TPB, 0, s>>>(g, p, lev, src, dst);
+}
+
+// ---------------------------------------------------------------------------
+// one compact RK3 stage on the leaves of one level (Sec. 3, Algs. alg-LTS,
+// Steprk2, Steprk3) with the NERK partials and the flux registers
+
+__device__ __forceinline__ double* regc_at(const Geo& g, const Dev& p, int lev, int f, int k, int64_t t) {
+  const int64_t Nl = g.B * g.n[lev];
+  return p.regc + g.rc_off[lev] + (int64_t)(f * g.m + k) * Nl + t;
+}
+__device__ __forceinline__ double* regf_at(const Geo& g, const Dev& p, int lev, int f, int b, int k, int64_t t) {
+  const int64_t Nl = g.B * g.n[lev];
+  return p.regf + g.rf_off[lev] + (int64_t)((f * g.nsub + b) * g.m + k) * Nl + t;
+}
+
+template <int D>
+__device__ __forceinline__ void transverse(int dir, int& t0, int& t1) {
+  t0 = -1;
+  t1 = -1;
+  int j = 0;
+#pragma unroll
+  for (int a = 0; a < D; a++)
+    if (a != dir) {
+      if (j == 0) t0 = a; else t1 = a;
+      j++;
+    }
+}
+
+// Leaf / internal node face (Sec. 2): mean of the 2^{d-1} subface fluxes at
+// level lev+1, from the leaf's virtual children (predicted from level lev's
+// own stage state) and the neighbour's children (finer-side values: S1 q^n,
+// S2 eq. projleaf / projnode, S3 stage-3 or eq. rk3proj values).
+template <int D, int PDE>
+__device__ __noinline__ void refined_flux(const Geo& g, const Dev& p, int lev, int stage, int64_t inst,
+                                          const int* x, int dir, int side, int nbx, double* F) {
+  constexpr int M = NC<D, PDE>::M;
+  const double* cur = p.q[stage == 1 ? SL_Q0 : (stage == 2 ? SL_Q1 : SL_QH)];
+  const int64_t ib = g.off[lev] + inst * g.n[lev];
+  const int64_t ibf = g.off[lev + 1] + inst * g.n[lev + 1];
+  double T[M][8];
+  for (int k = 0; k < M; k++) {
+    double S[27];
+    if (!gather27<D>(g, p, cur, lev, ib, x, k, S)) flag_bad(p, inst, 2);
+    pred_terms<D>(S, T[k]);
+  }
+  int t0, t1;
+  transverse<D>(dir, t0, t1);
+  double Fs[M], Fb[M];
+  for (int b = 0; b < (1 << (D - 1)); b++) {
+    int fy[3] = {2 * x[0], 2 * x[1], 2 * x[2]};
+    int cbt = 0;
+    if (t0 >= 0) { fy[t0] += b & 1; cbt |= (b & 1) << t0; }
+    if (t1 >= 0) { fy[t1] += (b >> 1) & 1; cbt |= ((b >> 1) & 1) << t1; }
+    double own[2][M], fin[2][M];
+    for (int e = 0; e < 2; e++) {
+      const int cb = cbt | (e << dir);
+      for (int k = 0; k < M; k++) own[e][k] = pred_child<D>(T[k], cb);
+      int y[3] = {fy[0], fy[1], fy[2]};
+      y[dir] = 2 * nbx + e;
+      const int64_t Gf = ibf + (int64_t)menc<D>(y);
+      const uint8_t sf = p.st[Gf];
+      if (sf == ST_ABSENT) flag_bad(p, inst, 4);
+      for (int k = 0; k < M; k++) {
+        const int64_t I = (int64_t)k * g.Ntot + Gf;
+        if (stage == 1) fin[e][k] = p.q[SL_Q0][I];
+        else if (stage == 2) fin[e][k] = sf == ST_LEAF ? p.q[SL_X2][I] : (2.0 * p.q[SL_Q1][I]) - p.q[SL_Q0][I];
+        else fin[e][k] = p.q[SL_QE][I];
+      }
+    }
+    double c[4][M];
+    for (int k = 0; k < M; k++) {
+      if (side) {
+        c[0][k] = own[0][k]; c[1][k] = own[1][k]; c[2][k] = fin[0][k]; c[3][k] = fin[1][k];
+      } else {
+        c[0][k] = fin[0][k]; c[1][k] = fin[1][k]; c[2][k] = own[0][k]; c[3][k] = own[1][k];
+      }
+    }
+    face_flux<D, PDE>(g, lev + 1, dir, c, Fb);
+    for (int k = 0; k < M; k++) Fs[k] = (b == 0) ? Fb[k] : (Fs[k] + Fb[k]);
+  }
+  const double sc = D == 1 ? 1.0 : (D == 2 ? 0.5 : 0.25);
+  for (int k = 0; k < M; k++) F[k] = Fs[k] * sc;
+}
+
+template <int D, int PDE>
+__global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lev, int stage) {
+  constexpr int M = NC<D, PDE>::M;
+  constexpr double C_1_6 = 1.0 / 6.0, C_2_3 = 2.0 / 3.0, C_1_3 = 1.0 / 3.0;
+  const int64_t nl = g.n[lev], N = g.B * nl;
+  const int n = 1 << lev;
+  const int64_t NT = g.Ntot;
+  const double* cur = p.q[stage == 1 ? SL_Q0 : (stage == 2 ? SL_Q1 : SL_QH)];
+  const bool finest = lev == g.L;
+  GSL(t, N) {
+    const int64_t G = g.off[lev] + t;
+    const bool leaf = p.st[G] == ST_LEAF;
+    const int64_t inst = t >> (D * lev);
+    if (stage == 1) {
+      // one leaf-update per leaf and full RK step
+      if (nl >= 64) {
+        const unsigned long long bal = __ballot(leaf);
+        if ((threadIdx.x & 63) == 0 && bal)
+          atomicAdd(&p.cnt[inst * CNT_PER_INST + CNT_UPDATES], (unsigned long long)__popcll(bal));
+      } else if (leaf) {
+        atomicAdd(&p.cnt[inst * CNT_PER_INST + CNT_UPDATES], 1ull);
+      }
+    }
+    if (!leaf) continue;
+    int x[3];
+    mdec<D>((uint64_t)(t & (nl - 1)), x);
+    const int64_t ib = g.off[lev] + inst * nl;
+    const double h = ldexp(p.dt[inst], g.L - lev);
+    const double wh = (stage == 3 ? C_2_3 : C_1_6) * h;
+    double R[M];
+#pragma unroll
+    for (int dir = 0; dir < D; dir++) {
+      double c5[5][M];
+#pragma unroll
+      for (int o = -2; o <= 2; o++) {
+        int y[3] = {x[0], x[1], x[2]};
+        y[dir] = map_st(x[dir] + o, n, g.periodic[dir]);
+        const int64_t Gy = o == 0 ? G : ib + (int64_t)menc<D>(y);
+#pragma unroll
+        for (int k = 0; k < M; k++) c5[o + 2][k] = cur[(int64_t)k * NT + Gy];
+      }
+      double Fm[M], Fp[M];
+      int nbs[2];
+      uint8_t sts[2];
+#pragma unroll
+      for (int side = 0; side < 2; side++) {
+        const int nb = map_nb(x[dir] + (side ? 1 : -1), n, g.periodic[dir]);
+        nbs[side] = nb;
+        uint8_t s = 3;  // outside the domain
+        if (nb >= 0) {
+          int y[3] = {x[0], x[1], x[2]};
+          y[dir] = nb;
+          s = p.st[ib + (int64_t)menc<D>(y)];
+        }
+        sts[side] = s;
+        double* F = side ? Fp : Fm;
+        if (s == ST_INTERNAL && lev < g.L) refined_flux<D, PDE>(g, p, lev, stage, inst, x, dir, side, nb, F);
+        else face_flux<D, PDE>(g, lev, dir, c5 + side, F);
+      }
+#pragma unroll
+      for (int k = 0; k < M; k++) {
+        const double r = (Fm[k] - Fp[k]) * g.invdx[lev][dir];
+        R[k] = dir == 0 ? r : (R[k] + r);
+      }
+      if (g.reflux) {
+#pragma unroll
+        for (int side = 0; side < 2; side++) {
+          const double* F = side ? Fp : Fm;
+          if (sts[side] == ST_INTERNAL && lev < g.L) {
+            for (int k = 0; k < M; k++) {
+              double* r = regc_at(g, p, lev, 2 * dir + side, k, t);
+              *r = *r + (wh * F[k]);
+            }
+          } else if (sts[side] == ST_ABSENT) {
+            // fine side of a coarse leaf's refined face
+            int y[3] = {x[0] >> 1, x[1] >> 1, x[2] >> 1};
+            y[dir] = nbs[side] >> 1;
+            const int64_t tX = inst * g.n[lev - 1] + (int64_t)menc<D>(y);
+            if (p.st[g.off[lev - 1] + tX] != ST_LEAF) flag_bad(p, inst, 8);
+            int t0, t1;
+            transverse<D>(dir, t0, t1);
+            int b = 0;
+            if (t0 >= 0) b |= x[t0] & 1;
+            if (t1 >= 0) b |= (x[t1] & 1) << 1;
+            const int fX = 2 * dir + (side ? 0 : 1);
+            for (int k = 0; k < M; k++) {
+              double* r = regf_at(g, p, lev - 1, fX, b, k, tX);
+              *r = *r + (wh * F[k]);
+            }
+          }
+        }
+      }
+    }
+    if (PDE == PDE_NAGUMO || PDE == PDE_LINEAR) R[0] = R[0] + source<PDE>(g, cur[G]);
+#pragma unroll
+    for (int k = 0; k < M; k++) {
+      const int64_t I = (int64_t)k * NT + G;
+      const double q0 = p.q[SL_Q0][I];
+      const double r = R[k];
+      if (stage == 1) {
+        p.q[SL_Q1][I] = q0 + (h * r);
+        if (!finest) {
+          p.q[SL_H1][I] = q0 + ((0.5 * h) * r);
+          p.q[SL_N14][I] = q0 + (((7.0 / 32.0) * h) * r);
+          p.q[SL_N34][I] = q0 + (((15.0 / 32.0) * h) * r);
+        }
+      } else if (stage == 2) {
+        const double q1 = p.q[SL_Q1][I];
+        p.q[SL_QH][I] = ((0.75 * q0) + (0.25 * q1)) + ((0.25 * h) * r);
+        p.q[SL_X2][I] = q1 + (h * r);
+        if (!finest) {
+          p.q[SL_N14][I] = p.q[SL_N14][I] + (((1.0 / 32.0) * h) * r);
+          p.q[SL_N34][I] = p.q[SL_N34][I] + (((9.0 / 32.0) * h) * r);
+        }
+      } else {
+        const double qh = p.q[SL_QH][I];
+        const double qe = ((C_1_3 * q0) + (C_2_3 * qh)) + ((C_2_3 * h) * r);
+        p.q[SL_QE][I] = qe;
+        if (!isfinite(qe)) atomicOr(&p.cnt[inst * CNT_PER_INST + CNT_NONFINITE], 1ull);
+      }
+    }
+  }
+}
+
+template <int D>
+static void stage_d(const Geo& g, const Dev& p, int lev, int stage, hipStream_t s) {
+  const int64_t n = g.B * g.n[lev];
+  const int nb = blocks_for(n);
+  switch (g.pde) {
+    case PDE_ADVECTION: k_stage<D, PDE_ADVECTION><<<nb, TPB, 0, s>>>(g, p, lev, stage); break;
+    case PDE_BURGERS: k_stage<D, PDE_BURGERS><<<nb, TPB, 0, s>>>(g, p, lev, stage); break;
+    case PDE_NAGUMO: k_stage<D, PDE_NAGUMO><<<nb, TPB, 0, s>>>(g, p, lev, stage); break;
+    case PDE_EULER: k_stage<D, PDE_EULER><<<nb, TPB, 0, s>>>(g, p, lev, stage); break;
+    default: k_stage<D, PDE_LINEAR><<<nb, TPB, 0, s>>>(g, p, lev, stage); break;
+  }
+}
+
+void launch_stage(const Geo& g, const Dev& p, int lev, int stage, hipStream_t s) {
+  if (g.d == 1) stage_d<1>(g, p, lev, stage, s);
+  else if (g.d == 2) stage_d<2>(g, p, lev, stage, s);
+  else stage_d<3>(g, p, lev, stage, s);
+}
+
+// ---------------------------------------------------------------------------
+// end of the steps of a level: q^n <- stage-3 value, then on every refined
+// face the conservative correction sigma (A_c - A_f) / dx (faces x-, x+,
+// y-, y+, z-, z+), registers cleared after use
+
+template <int D>
+__global__ __launch_bounds__(TPB) void k_finalize(Geo g, Dev p, int lev) {
+  const int64_t nl = g.n[lev], N = g.B * nl;
+  const int n = 1 << lev;
+  const double sc = D == 1 ? 1.0 : (D == 2 ? 0.5 : 0.25);
+  GSL(t, N) {
+    const int64_t G = g.off[lev] + t;
+    if (p.st[G] != ST_LEAF) continue;
+    double q[5];
+    for (int k = 0; k < g.m; k++) q[k] = p.q[SL_QE][(int64_t)k * g.Ntot + G];
+    if (g.reflux && lev < g.L) {
+      const int64_t inst = t >> (D * lev);
+      const int64_t ib = g.off[lev] + inst * nl;
+      int x[3];
+      mdec<D>((uint64_t)(t & (nl - 1)), x);
+      for (int dir = 0; dir < D; dir++)
+        for (int side = 0; side < 2; side++) {
+          const int nb = map_nb(x[dir] + (side ? 1 : -1), n, g.periodic[dir]);
+          if (nb < 0) continue;
+          int y[3] = {x[0], x[1], x[2]};
+          y[dir] = nb;
+          if (p.st[ib + (int64_t)menc<D>(y)] != ST_INTERNAL) continue;
+          const int f = 2 * dir + side;
+          for (int k = 0; k < g.m; k++) {
+            double af = 0.0;
+            for (int b = 0; b < (1 << (D - 1)); b++) {
+              double* r = regf_at(g, p, lev, f, b, k, t);
+              af = (b == 0) ? *r : (af + *r);
+              *r = 0.0;
+            }
+            af = af * sc;
+            double* rc = regc_at(g, p, lev, f, k, t);
+            const double Dd = (*rc - af) * g.invdx[lev][dir];
+            *rc = 0.0;
+            q[k] = side ? q[k] + Dd : q[k] - Dd;
+          }
+        }
+    }
+    for (int k = 0; k < g.m; k++) p.q[SL_Q0][(int64_t)k * g.Ntot + G] = q[k];
+  }
+}
+
+void launch_finalize(const Geo& g, const Dev& p, int lev, hipStream_t s) {
+  const int64_t n = g.B * g.n[lev];
+  if (g.d == 1) k_finalize<1><<<blocks_for(n), TPB, 0, s>>>(g, p, lev);
+  else if (g.d == 2) k_finalize<2><<<blocks_for(n), TPB, 0, s>>>(g, p, lev);
+  else k_finalize<3><<<blocks_for(n), TPB, 0, s>>>(g, p, lev);
+}
+
+__global__ void k_zero(double* a, int64_t n) { GSL(t, n) a[t] = 0.0; }
+
+void launch_clear_regs(const Geo& g, const Dev& p, hipStream_t s) {
+  const int64_t nc = g.rc_off[g.L], nf = g.rf_off[g.L];
+  if (nc > 0) k_zero<<<blocks_for(nc), TPB, 0, s>>>(p.regc, nc);
+  if (nf > 0) k_zero<<<blocks_for(nf), TPB, 0, s>>>(p.regf, nf);
+}
+
+// ---------------------------------------------------------------------------
+// remesh (Alg. AdaptiveMesh, Alg. waveletThres; only scales evolved in the
+// current iteration may split or merge).  Levels below la are frozen.
+//   detail:  significant internal node: max_{c,k} |q_c - q~_c| / scale_k >
+//            eps_{l+1} (level-dependent 2^{d(l+1-L)} eps); eps = 0 keeps all
+//   seed:    significant nodes, existing nodes at distance 1 (space safety),
+//            children of significant nodes below L (scale safety)
+//   close:   least set with the tree rule and the radius-2 grading rule; all
+//            implications point one level down, so one fine-to-coarse sweep
+//   prune:   greatest subset still satisfying both rules with frozen
+//            existence at la; one coarse-to-fine sweep
+//   apply:   new status, new nodes predicted from the parent level
+
+template <int D>
+__global__ __launch_bounds__(TPB) void k_detail(Geo g, Dev p, int lev) {
+  const int64_t nl = g.n[lev], N = g.B * nl;
+  GSL(t, N) {
+    const int64_t G = g.off[lev] + t;
+    uint8_t sig = 0;
+    if (lev < g.L && p.st[G] == ST_INTERNAL) {
+      const int64_t inst = t >> (D * lev);
+      const double e0 = p.eps[inst];
+      if (e0 == 0.0) {
+        sig = 1;
+      } else {
+        const double e = g.thresh ? ldexp(e0, D * (lev + 1 - g.L)) : e0;
+        int x[3];
+        mdec<D>((uint64_t)(t & (nl - 1)), x);
+        const int64_t ib = g.off[lev] + inst * nl;
+        const int64_t C0 = g.off[lev + 1] + (t << D);
+        double Dm = 0.0;
+        for (int k = 0; k < g.m; k++) {
+          double S[27], T[8];
+          if (!gather27<D>(g, p, p.q[SL_Q0], lev, ib, x, k, S)) flag_bad(p, inst, 16);
+          pred_terms<D>(S, T);
+          for (int cb = 0; cb < (1 << D); cb++) {
+            const double det = fabs(p.q[SL_Q0][(int64_t)k * g.Ntot + C0 + cb] - pred_child<D>(T, cb)) / g.scale[k];
+            if (det > Dm) Dm = det;
+          }
+        }
+        sig = Dm > e;
+        if (fabs(Dm - e) <= 1e-12 * e) atomicAdd(&p.cnt[inst * CNT_PER_INST + CNT_NEAR], 1ull);
+      }
+    }
+    p.rf[G] = sig;
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(TPB) void k_seed(Geo g, Dev p, int lev, int la) {
+  const int64_t nl = g.n[lev], N = g.B * nl;
+  const int n = 1 << lev;
+  GSL(t, N) {
+    const int64_t G = g.off[lev] + t;
+    const uint8_t r = p.rf[G];
+    bool w = r & 1;
+    const int64_t inst = t >> (D * lev);
+    if (!w && p.st[G] != ST_ABSENT) {
+      int x[3];
+      mdec<D>((uint64_t)(t & (nl - 1)), x);
+      const int64_t ib = g.off[lev] + inst * nl;
+      for (int oz = (D > 2 ? -1 : 0); oz <= (D > 2 ? 1 : 0) && !w; oz++)
+        for (int oy = (D > 1 ? -1 : 0); oy <= (D > 1 ? 1 : 0) && !w; oy++)
+          for (int ox = -1; ox <= 1 && !w; ox++) {
+            int y[3] = {map_nb(x[0] + ox, n, g.periodic[0]), 0, 0};
+            if (D > 1) y[1] = map_nb(x[1] + oy, n, g.periodic[1]);
+            if (D > 2) y[2] = map_nb(x[2] + oz, n, g.periodic[2]);
+            if (y[0] < 0 || y[1] < 0 || y[2] < 0) continue;
+            if (p.rf[ib + (int64_t)menc<D>(y)] & 1) w = true;
+          }
+    }
+    if (!w && lev - 1 >= la && lev <= g.L - 1) w = p.rf[g.off[lev - 1] + (t >> D)] & 1;
+    if (w) p.rf[G] = r | 2;
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(TPB) void k_close(Geo g, Dev p, int lev) {
+  const int64_t nl = g.n[lev], N = g.B * nl;
+  const int nf = 1 << (lev + 1);
+  GSL(t, N) {
+    const int64_t G = g.off[lev] + t;
+    const uint8_t r = p.rf[G];
+    if (r & 2) continue;
+    const int64_t inst = t >> (D * lev);
+    int x[3];
+    mdec<D>((uint64_t)(t & (nl - 1)), x);
+    const int64_t ibf = g.off[lev + 1] + inst * g.n[lev + 1];
+    bool w = false;
+    for (int oz = (D > 2 ? -2 : 0); oz <= (D > 2 ? 3 : 0) && !w; oz++)
+      for (int oy = (D > 1 ? -2 : 0); oy <= (D > 1 ? 3 : 0) && !w; oy++)
+        for (int ox = -2; ox <= 3 && !w; ox++) {
+          int y[3] = {map_nb(2 * x[0] + ox, nf, g.periodic[0]), 0, 0};
+          if (D > 1) y[1] = map_nb(2 * x[1] + oy, nf, g.periodic[1]);
+          if (D > 2) y[2] = map_nb(2 * x[2] + oz, nf, g.periodic[2]);
+          if (y[0] < 0 || y[1] < 0 || y[2] < 0) continue;
+          if (p.rf[ibf + (int64_t)menc<D>(y)] & 2) w = true;
+        }
+    if (w) p.rf[G] = r | 2;
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(TPB) void k_prune(Geo g, Dev p, int lev, int la) {
+  const int64_t nl = g.n[lev], N = g.B * nl;
+  const int np = 1 << (lev - 1);
+  GSL(t, N) {
+    const int64_t G = g.off[lev] + t;
+    const uint8_t r = p.rf[G];
+    if (!(r & 2) || lev == g.l0) continue;
+    const int64_t inst = t >> (D * lev);
+    int x[3];
+    mdec<D>((uint64_t)(t & (nl - 1)), x);
+    const int px[3] = {x[0] >> 1, x[1] >> 1, x[2] >> 1};
+    const int64_t ibp = g.off[lev - 1] + inst * g.n[lev - 1];
+    bool ok = true;
+    for (int oz = (D > 2 ? -1 : 0); oz <= (D > 2 ? 1 : 0) && ok; oz++)
+      for (int oy = (D > 1 ? -1 : 0); oy <= (D > 1 ? 1 : 0) && ok; oy++)
+        for (int ox = -1; ox <= 1 && ok; ox++) {
+          int y[3] = {map_nb(px[0] + ox, np, g.periodic[0]), 0, 0};
+          if (D > 1) y[1] = map_nb(px[1] + oy, np, g.periodic[1]);
+          if (D > 2) y[2] = map_nb(px[2] + oz, np, g.periodic[2]);
+          if (y[0] < 0 || y[1] < 0 || y[2] < 0) continue;
+          const int64_t Gp = ibp + (int64_t)menc<D>(y);
+          ok = (lev - 1 >= la) ? ((p.rf[Gp] & 2) != 0) : (p.st[Gp] == ST_INTERNAL);
+        }
+    if (!ok) p.rf[G] = r & ~2;
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(TPB) void k_apply(Geo g, Dev p, int lev, int la) {
+  const int64_t nl = g.n[lev], N = g.B * nl;
+  GSL(t, N) {
+    const int64_t G = g.off[lev] + t;
+    const uint8_t old = p.st[G];
+    const bool w = (p.rf[G] & 2) != 0;
+    uint8_t nw;
+    if (lev == la) {
+      nw = old == ST_ABSENT ? ST_ABSENT : (w ? ST_INTERNAL : ST_LEAF);
+    } else {
+      const uint8_t ps = p.st[g.off[lev - 1] + (t >> D)];
+      nw = ps == ST_INTERNAL ? ((lev <= g.L - 1 && w) ? ST_INTERNAL : ST_LEAF) : ST_ABSENT;
+    }
+    p.st[G] = nw;
+    if (lev > la && old == ST_ABSENT && nw != ST_ABSENT) {
+      const int64_t inst = t >> (D * lev);
+      int x[3];
+      mdec<D>((uint64_t)(t & (nl - 1)), x);
+      const int px[3] = {x[0] >> 1, x[1] >> 1, x[2] >> 1};
+      const int64_t ibp = g.off[lev - 1] + inst * g.n[lev - 1];
+      const int cb = (x[0] & 1) | ((x[1] & 1) << 1) | ((x[2] & 1) << 2);
+      for (int k = 0; k < g.m; k++) {
+        double S[27], T[8];
+        if (!gather27<D>(g, p, p.q[SL_Q0], lev - 1, ibp, px, k, S)) flag_bad(p, inst, 32);
+        pred_terms<D>(S, T);
+        p.q[SL_Q0][(int64_t)k * g.Ntot + G] = pred_child<D>(T, cb);
+      }
+    }
+  }
+}
+
+// absent cells that a leaf stencil (normal offsets 1 and 2) reads; their
+// parent is then a leaf (grading), the virtual leaves of Fig. 1
+template <int D>
+__global__ __launch_bounds__(TPB) void k_ghost_flags(Geo g, Dev p, int lev) {
+  const int64_t nl = g.n[lev], N = g.B * nl;
+  const int n = 1 << lev;
+  GSL(t, N) {
+    const int64_t G = g.off[lev] + t;
+    uint8_t need = 0;
+    if (p.st[G] == ST_ABSENT && p.st[g.off[lev - 1] + (t >> D)] == ST_LEAF) {
+      const int64_t inst = t >> (D * lev);
+      const int64_t ib = g.off[lev] + inst * nl;
+      int x[3];
+      mdec<D>((uint64_t)(t & (nl - 1)), x);
+      for (int dir = 0; dir < D && !need; dir++)
+        for (int o = -2; o <= 2 && !need; o++) {
+          if (o == 0) continue;
+          const int u = map_nb(x[dir] - o, n, g.periodic[dir]);
+          if (u < 0) continue;
+          int y[3] = {x[0], x[1], x[2]};
+          y[dir] = u;
+          if (p.st[ib + (int64_t)menc<D>(y)] == ST_LEAF) need = 1;
+        }
+    }
+    p.gh[G] = need;
+  }
+}
+
+#define DISPATCH_D(kern, n, ...)                                                  \
+  do {                                                                            \
+    const int nb_ = blocks_for(n);                                                \
+    if (g.d == 1) kern<1><<<nb_, TPB, 0, s>>>(__VA_ARGS__);                       \
+    else if (g.d == 2) kern<2><<<nb_, TPB, 0, s>>>(__VA_ARGS__);                  \
+    else kern<3><<<nb_, TPB, 0, s>>>(__VA_ARGS__);                                \
+  } while (0)
+
+void launch_load_finest(const Geo& g, const Dev& p, const double* src, hipStream_t s) {
+  DISPATCH_D(k_load_finest, g.B * g.n[g.L], g, p, src);
+}
+void launch_recon_level(const Geo& g, const Dev& p, int lev, double* dense, hipStream_t s) {
+  DISPATCH_D(k_recon_level, g.B * g.n[lev], g, p, lev, dense);
+}
+void launch_to_rowmajor(const Geo& g, const double* dense, double* out, hipStream_t s) {
+  DISPATCH_D(k_to_rowmajor, g.B * g.n[g.L], g, dense, out);
+}
+void launch_detail(const Geo& g, const Dev& p, int lev, hipStream_t s) {
+  DISPATCH_D(k_detail, g.B * g.n[lev], g, p, lev);
+}
+void launch_seed(const Geo& g, const Dev& p, int lev, int la, hipStream_t s) {
+  DISPATCH_D(k_seed, g.B * g.n[lev], g, p, lev, la);
+}
+void launch_close(const Geo& g, const Dev& p, int lev, hipStream_t s) {
+  DISPATCH_D(k_close, g.B * g.n[lev], g, p, lev);
+}
+void launch_prune(const Geo& g, const Dev& p, int lev, int la, hipStream_t s) {
+  DISPATCH_D(k_prune, g.B * g.n[lev], g, p, lev, la);
+}
+void launch_apply(const Geo& g, const Dev& p, int lev, int la, hipStream_t s) {
+  DISPATCH_D(k_apply, g.B * g.n[lev], g, p, lev, la);
+}
+void launch_ghost_flags(const Geo& g, const Dev& p, int lev, hipStream_t s) {
+  DISPATCH_D(k_ghost_flags, g.B * g.n[lev], g, p, lev);
+}
+
+// ---------------------------------------------------------------------------
+// leaf lists of one instance and level in Morton order: wavefront ballot +
+// popcount, per-block counts, an exclusive scan of the block counts, then a
+// second pass that writes every leaf at its rank (order = Morton order)
+
+__global__ __launch_bounds__(TPB) void k_count(const uint8_t* st, int64_t base, int64_t n, uint8_t want,
+                                               int* blockcnt) {
+  __shared__ int wsum[TPB / 64];
+  const int64_t t = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  const bool hit = t < n && st[base + t] == want;
+  const unsigned long long bal = __ballot(hit);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = __popcll(bal);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int w = 0; w < TPB / 64; w++) s += wsum[w];
+    blockcnt[blockIdx.x] = s;
+  }
+}
+
+void launch_count(const Geo& g, const Dev& p, int lev, int inst, uint8_t want, int* blockcnt, int nblk,
+                  hipStream_t s) {
+  const int64_t base = g.off[lev] + (int64_t)inst * g.n[lev];
+  k_count<<<nblk, TPB, 0, s>>>(p.st, base, g.n[lev], want, blockcnt);
+}
+
+__global__ void k_scan_blocks(int* cnt, int n, long long* total) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  long long s = 0;
+  for (int i = 0; i < n; i++) {
+    const int c = cnt[i];
+    cnt[i] = (int)s;
+    s += c;
+  }
+  *total = s;
+}
+
+void launch_scan_blocks(int* blockcnt, int nblk, long long* total, hipStream_t s) {
+  k_scan_blocks<<<1, 64, 0, s>>>(blockcnt, nblk, total);
+}
+
+__global__ __launch_bounds__(TPB) void k_gather_leaves(Geo g, Dev p, int lev, int64_t base, int64_t n,
+                                                       const int* blockoff, long long out0,
+                                                       unsigned long long* keys, double* vals,
+                                                       long long vstride) {
+  __shared__ int wsum[TPB / 64];
+  const int64_t t = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  const bool hit = t < n && p.st[base + t] == ST_LEAF;
+  const unsigned long long bal = __ballot(hit);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) wsum[wv] = __popcll(bal);
+  __syncthreads();
+  if (!hit) return;
+  int off = blockoff[blockIdx.x];
+  for (int w = 0; w < wv; w++) off += wsum[w];
+  off += __popcll(bal & ((1ull << lane) - 1ull));
+  const long long o = out0 + off;
+  keys[o] = ((unsigned long long)lev << 56) | (unsigned long long)t;
+  for (int k = 0; k < g.m; k++) vals[(long long)k * vstride + o] = p.q[SL_Q0][(int64_t)k * g.Ntot + base + t];
+}
+
+void launch_gather_leaves(const Geo& g, const Dev& p, int lev, int inst, const int* blockoff, int nblk,
+                          long long base_out, unsigned long long* keys, double* vals, long long vstride,
+                          hipStream_t s) {
+  const int64_t base = g.off[lev] + (int64_t)inst * g.n[lev];
+  k_gather_leaves<<<nblk, TPB, 0, s>>>(g, p, lev, base, g.n[lev], blockoff, base_out, keys, vals, vstride);
+}
+
+__global__ void k_scatter_leaves(Geo g, Dev p, int64_t inst, const unsigned long long* keys,
+                                 const double* vals, long long n, int* err) {
+  GSL(r, n) {
+    const unsigned long long key = keys[r];
+    const int lev = (int)(key >> 56);
+    const unsigned long long mk = key & ((1ull << 56) - 1ull);
+    if (lev < g.l0 || lev > g.L || (mk >> (g.d * lev)) != 0) {
+      atomicOr(err, 1);
+      continue;
+    }
+    const int64_t G = g.off[lev] + inst * g.n[lev] + (int64_t)mk;
+    p.st[G] = ST_LEAF;
+    for (int k = 0; k < g.m; k++) p.q[SL_Q0][(int64_t)k * g.Ntot + G] = vals[(long long)k * n + r];
+  }
+}
+
+void launch_scatter_leaves(const Geo& g, const Dev& p, int inst, const unsigned long long* keys,
+                           const double* vals, long long n, int* err, hipStream_t s) {
+  if (n <= 0) return;
+  k_scatter_leaves<<<blocks_for(n), TPB, 0, s>>>(g, p, inst, keys, vals, n, err);
+}
+
+__global__ void k_mark_parents(Geo g, Dev p, int lev, int* err) {
+  const int64_t N = g.B * g.n[lev];
+  GSL(t, N) {
+    if (p.st[g.off[lev] + t] == ST_ABSENT) continue;
+    const int64_t P = g.off[lev - 1] + (t >> g.d);
+    if (p.st[P] == ST_LEAF) atomicOr(err, 2);
+    p.st[P] = ST_INTERNAL;
+  }
+}
+
+void launch_mark_parents(const Geo& g, const Dev& p, int lev, int* err, hipStream_t s) {
+  k_mark_parents<<<blocks_for(g.B * g.n[lev]), TPB, 0, s>>>(g, p, lev, err);
+}
+
+template <int D>
+__global__ void k_validate(Geo g, Dev p, int lev, int* err) {
+  const int64_t nl = g.n[lev], N = g.B * nl;
+  const int n = 1 << lev;
+  GSL(t, N) {
+    const int64_t G = g.off[lev] + t;
+    const uint8_t s = p.st[G];
+    if (lev == g.l0 && s == ST_ABSENT) atomicOr(err, 4);
+    if (s != ST_INTERNAL) continue;
+    if (lev == g.L) {
+      atomicOr(err, 32);
+      continue;
+    }
+    const int64_t C0 = g.off[lev + 1] + (t << D);
+    for (int cb = 0; cb < (1 << D); cb++)
+      if (p.st[C0 + cb] == ST_ABSENT) atomicOr(err, 8);
+    const int64_t inst = t >> (D * lev);
+    const int64_t ib = g.off[lev] + inst * nl;
+    int x[3];
+    mdec<D>((uint64_t)(t & (nl - 1)), x);
+    for (int oz = (D > 2 ? -2 : 0); oz <= (D > 2 ? 2 : 0); oz++)
+      for (int oy = (D > 1 ? -2 : 0); oy <= (D > 1 ? 2 : 0); oy++)
+        for (int ox = -2; ox <= 2; ox++) {
+          int y[3] = {map_nb(x[0] + ox, n, g.periodic[0]), 0, 0};
+          if (D > 1) y[1] = map_nb(x[1] + oy, n, g.periodic[1]);
+          if (D > 2) y[2] = map_nb(x[2] + oz, n, g.periodic[2]);
+          if (y[0] < 0 || y[1] < 0 || y[2] < 0) continue;
+          if (p.st[ib + (int64_t)menc<D>(y)] == ST_ABSENT) atomicOr(err, 16);
+        }
+  }
+}
+
+void launch_validate(const Geo& g, const Dev& p, int lev, int* err, hipStream_t s) {
+  DISPATCH_D(k_validate, g.B * g.n[lev], g, p, lev, err);
+}
+
+// ---------------------------------------------------------------------------
+// reductions: maximum wave speed per instance (monotone bit pattern of a
+// non-negative double, integer atomicMax), leaf mass partial sums per block
+
+template <int D>
+__global__ void k_wavespeed(Geo g, Dev p, int lev, unsigned long long* out) {
+  const int64_t nl = g.n[lev], N = g.B * nl;
+  GSL(t, N) {
+    const int64_t G = g.off[lev] + t;
+    if (p.st[G] != ST_LEAF) continue;
+    const int64_t inst = t >> (D * lev);
+    double q[5], v = 0.0;
+    for (int k = 0; k < g.m; k++) q[k] = p.q[SL_Q0][(int64_t)k * g.Ntot + G];
+    if (g.pde == PDE_BURGERS) {
+      v = fabs(q[0]);
+    } else if (g.pde == PDE_EULER) {
+      double w[5];
+      euler_prim<D>(g.gamma - 1.0, q, w);
+      const double a = sqrt((g.gamma * w[D + 1]) / w[0]);
+      for (int j = 0; j < D; j++) v = (j == 0) ? (fabs(w[1]) + a) : (v + (fabs(w[1 + j]) + a));
+    } else if (g.pde == PDE_ADVECTION) {
+      for (int j = 0; j < D; j++) v = v + fabs(g.adv[j]);
+    }
+    atomicMax(&out[inst], (unsigned long long)__double_as_longlong(v));
+  }
+}
+
+void launch_wavespeed(const Geo& g, const Dev& p, int lev, unsigned long long* out, hipStream_t s) {
+  DISPATCH_D(k_wavespeed, g.B * g.n[lev], g, p, lev, out);
+}
+
+__global__ __launch_bounds__(TPB) void k_mass_partial(Geo g, Dev p, int64_t base, int64_t n, double vol,
+                                                      double* part) {
+  __shared__ double sh[5][TPB];
+  const int64_t t = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  const bool leaf = t < n && p.st[base + t] == ST_LEAF;
+  for (int k = 0; k < g.m; k++) sh[k][threadIdx.x] = leaf ? vol * p.q[SL_Q0][(int64_t)k * g.Ntot + base + t] : 0.0;
+  __syncthreads();
+  for (int w = TPB / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int k = 0; k < g.m; k++) sh[k][threadIdx.x] = sh[k][threadIdx.x] + sh[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int k = 0; k < g.m; k++) part[(int64_t)blockIdx.x * g.m + k] = sh[k][0];
+}
+
+void launch_mass_partial(const Geo& g, const Dev& p, int lev, int inst, double* part, int nblk, hipStream_t s) {
+  const int64_t base = g.off[lev] + (int64_t)inst * g.n[lev];
+  k_mass_partial<<<nblk, TPB, 0, s>>>(g, p, base, g.n[lev], g.vol[lev], part);
+}

@@ -1,0 +1,87 @@
+// mrlt_internal.h -- device-side data model of the MRLT/NERK3 HIP library.
+//
+// Storage: for every level l in [l0, L] and every instance of a batch, a
+// dense array of 2^{d l} cells indexed by the Morton key of the cell (the key
+// is the slot: a collision-free, direct-mapped table).  Global cell index
+//   G = off[l] + inst * n[l] + morton.
+// Children of cell (l, t) with t = inst * n[l] + key are (l+1, (t << d) + c),
+// c = a | b<<1 | e<<2: a child group is contiguous.
+// Values are FP64, field-major per time slot: slot[s][k * Ntot + G].
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define MRD_MAXLEV 24
+
+enum { ST_ABSENT = 0, ST_LEAF = 1, ST_INTERNAL = 2 };
+
+// Time slots.  Internal nodes reuse slots: Q1 holds the stage-2 projection
+// (Alg. projRK2) of internal nodes, QH / QE of the mid-step level hold the
+// theta=1/2 projection and the end value of Sec. 4.3 during Case B.
+enum { SL_Q0 = 0, SL_Q1, SL_H1, SL_N14, SL_N34, SL_QH, SL_QE, SL_X2, SL_Q1REF, SL_COUNT };
+
+enum { PDE_ADVECTION = 0, PDE_BURGERS = 1, PDE_NAGUMO = 2, PDE_EULER = 3, PDE_LINEAR = 4 };
+
+// projection kinds (one kernel, selected by mode)
+enum { PJ_Q0 = 0, PJ_CASEB, PJ_REF2, PJ_RK2, PJ_REF3, PJ_RK3 };
+
+// counters per instance
+enum { CNT_UPDATES = 0, CNT_NEAR, CNT_NONFINITE, CNT_BAD, CNT_PER_INST };
+
+struct Geo {
+  int d, L, l0, m, nsub, B;
+  int pde, recon, thresh, reflux;
+  int periodic[3];
+  int64_t n[MRD_MAXLEV + 1];     // cells per instance at level l (2^{d l})
+  int64_t off[MRD_MAXLEV + 1];   // first global index of level l
+  int64_t Ntot;                  // total cells over levels and instances
+  int64_t rc_off[MRD_MAXLEV + 1];  // coarse-side register block of level l
+  int64_t rf_off[MRD_MAXLEV + 1];  // fine-side register block of level l
+  double invdx[MRD_MAXLEV + 1][3];
+  double vol[MRD_MAXLEV + 1];
+  double nu, k_react, a_react, gamma, adv[3];
+  double scale[5];
+};
+
+struct Dev {
+  uint8_t* st;     // status per cell
+  uint8_t* rf;     // remesh scratch: bit0 significant, bit1 member of W, bit2 new node
+  uint8_t* gh;     // 1: absent cell read by a leaf stencil (virtual / ghost value)
+  double* q[SL_COUNT];
+  double* regc;    // [level block][2d][m][B n_l]
+  double* regf;    // [level block][2d][nsub][m][B n_l]
+  const double* dt;   // [B] dt of the finest level
+  const double* eps;  // [B]
+  unsigned long long* cnt;  // [B][CNT_PER_INST]
+};
+
+// ---- launchers (kernels.hip) -------------------------------------------
+void launch_fill_status(const Geo& g, const Dev& p, int lev, uint8_t v, hipStream_t s);
+void launch_load_finest(const Geo& g, const Dev& p, const double* src, hipStream_t s);
+void launch_project(const Geo& g, const Dev& p, int lev, int mode, hipStream_t s);
+void launch_ghost(const Geo& g, const Dev& p, int lev, int stage, int caseb, hipStream_t s);
+void launch_stage(const Geo& g, const Dev& p, int lev, int stage, hipStream_t s);
+void launch_finalize(const Geo& g, const Dev& p, int lev, hipStream_t s);
+void launch_detail(const Geo& g, const Dev& p, int lev, hipStream_t s);
+void launch_seed(const Geo& g, const Dev& p, int lev, int la, hipStream_t s);
+void launch_close(const Geo& g, const Dev& p, int lev, hipStream_t s);
+void launch_prune(const Geo& g, const Dev& p, int lev, int la, hipStream_t s);
+void launch_apply(const Geo& g, const Dev& p, int lev, int la, hipStream_t s);
+void launch_ghost_flags(const Geo& g, const Dev& p, int lev, hipStream_t s);
+void launch_recon_level(const Geo& g, const Dev& p, int lev, double* dense, hipStream_t s);
+void launch_to_rowmajor(const Geo& g, const double* dense, double* out, hipStream_t s);
+void launch_count(const Geo& g, const Dev& p, int lev, int inst, uint8_t want, int* blockcnt,
+                  int nblk, hipStream_t s);
+void launch_scan_blocks(int* blockcnt, int nblk, long long* total, hipStream_t s);
+void launch_gather_leaves(const Geo& g, const Dev& p, int lev, int inst, const int* blockoff,
+                          int nblk, long long base, unsigned long long* keys, double* vals,
+                          long long vstride, hipStream_t s);
+void launch_scatter_leaves(const Geo& g, const Dev& p, int inst, const unsigned long long* keys,
+                           const double* vals, long long n, int* err, hipStream_t s);
+void launch_mark_parents(const Geo& g, const Dev& p, int lev, int* err, hipStream_t s);
+void launch_validate(const Geo& g, const Dev& p, int lev, int* err, hipStream_t s);
+void launch_wavespeed(const Geo& g, const Dev& p, int lev, unsigned long long* out, hipStream_t s);
+void launch_mass_partial(const Geo& g, const Dev& p, int lev, int inst, double* part, int nblk,
+                         hipStream_t s);
+void launch_clear_regs(const Geo& g, const Dev& p, hipStream_t s);
+int blocks_for(int64_t n);

@@ -1,0 +1,515 @@
+// runtime.hip -- host runtime behind the C ABI of include/mrlt.h.
+//
+// Owns the device memory of a context, sequences the kernels of one
+// local-time-stepping macro step (Alg. alg-LTS of arXiv:1905.08717, one call
+// per fine iteration n = 0 .. 2^{L-l0}-1) and marshals the boundary calls.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mrlt.h"
+#include "mrlt_internal.h"
+
+struct mr_ctx {
+  Geo g;
+  Dev p;
+  mr_scheme s;
+  hipStream_t stream = nullptr;
+  std::vector<double> eps, t, dt_host;
+  std::vector<unsigned long long> cnt_host;
+  int64_t iters = 0;
+  bool broken = false;
+  std::string err;
+  std::vector<void*> allocs;
+  double* dt_d = nullptr;
+  double* eps_d = nullptr;
+  int* blockcnt_d = nullptr;
+  long long* total_d = nullptr;
+  int* err_d = nullptr;
+  unsigned long long* ws_d = nullptr;
+  double* part_d = nullptr;
+  int max_blocks = 0;
+};
+
+namespace {
+
+mr_status set_err(mr_ctx* c, mr_status st, const std::string& msg) {
+  if (c) c->err = msg;
+  return st;
+}
+
+mr_status hip_check(mr_ctx* c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return MR_OK;
+  return set_err(c, e == hipErrorOutOfMemory ? MR_ENOMEM : MR_EDEVICE,
+                 std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(c, call)                                  \
+  do {                                                   \
+    mr_status st__ = hip_check((c), (call), #call);      \
+    if (st__ != MR_OK) return st__;                      \
+  } while (0)
+
+mr_status dalloc(mr_ctx* c, void** ptr, size_t bytes) {
+  *ptr = nullptr;
+  if (bytes == 0) bytes = 8;
+  hipError_t e = hipMalloc(ptr, bytes);
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    return hip_check(c, e, "hipMalloc");
+  }
+  c->allocs.push_back(*ptr);
+  return hip_check(c, hipMemsetAsync(*ptr, 0, bytes, c->stream), "hipMemsetAsync");
+}
+
+int lmin_of(const Geo& g, int64_t n) {
+  for (int lev = g.l0; lev <= g.L; lev++)
+    if (n % ((int64_t)1 << (g.L - lev)) == 0) return lev;
+  return g.L;
+}
+
+mr_status check_launch(mr_ctx* c, const char* what) {
+  return hip_check(c, hipGetLastError(), what);
+}
+
+void project_range(mr_ctx* c, int hi, int lo, int mode) {
+  for (int lev = hi; lev >= lo; lev--) launch_project(c->g, c->p, lev, mode, c->stream);
+}
+
+// remesh with levels below la frozen; statuses, new values and ghost flags
+void remesh(mr_ctx* c, int la) {
+  const Geo& g = c->g;
+  if (la > g.L - 1) return;
+  for (int lev = la; lev <= g.L; lev++) launch_detail(g, c->p, lev, c->stream);
+  for (int lev = la; lev <= g.L - 1; lev++) launch_seed(g, c->p, lev, la, c->stream);
+  for (int lev = g.L - 2; lev >= la; lev--) launch_close(g, c->p, lev, c->stream);
+  for (int lev = la; lev <= g.L - 1; lev++) launch_prune(g, c->p, lev, la, c->stream);
+  for (int lev = la; lev <= g.L; lev++) launch_apply(g, c->p, lev, la, c->stream);
+  for (int lev = (la > g.l0 ? la : g.l0 + 1); lev <= g.L; lev++) launch_ghost_flags(g, c->p, lev, c->stream);
+}
+
+void ghost_fill(mr_ctx* c, int lmin, int stage) {
+  const Geo& g = c->g;
+  for (int lev = (lmin > g.l0 ? lmin : g.l0 + 1); lev <= g.L; lev++)
+    launch_ghost(g, c->p, lev, stage, lev == lmin ? 1 : 0, c->stream);
+}
+
+// one iteration of Alg. alg-LTS
+void lt_iteration(mr_ctx* c, int64_t n, int64_t N) {
+  const Geo& g = c->g;
+  const int L = g.L;
+  const int lmin = lmin_of(g, n);
+  project_range(c, L - 1, lmin, PJ_Q0);
+  if (c->s.remesh && lmin <= L - 1) {
+    remesh(c, lmin);
+    project_range(c, L - 1, lmin, PJ_Q0);
+  }
+  if (lmin > g.l0) launch_project(g, c->p, lmin - 1, PJ_CASEB, c->stream);
+  ghost_fill(c, lmin, 1);
+  for (int lev = lmin; lev <= L; lev++) launch_stage(g, c->p, lev, 1, c->stream);
+  project_range(c, L - 1, lmin, PJ_REF2);
+  ghost_fill(c, lmin, 2);
+  for (int lev = L; lev >= lmin; lev--) {
+    if (lev < L) launch_project(g, c->p, lev, PJ_RK2, c->stream);
+    launch_stage(g, c->p, lev, 2, c->stream);
+  }
+  project_range(c, L - 1, lmin, PJ_REF3);
+  ghost_fill(c, lmin, 3);
+  for (int lev = L; lev >= lmin; lev--) {
+    if (lev < L) launch_project(g, c->p, lev, PJ_RK3, c->stream);
+    launch_stage(g, c->p, lev, 3, c->stream);
+  }
+  const int lnext = (n + 1 == N) ? g.l0 : lmin_of(g, n + 1);
+  for (int lev = lnext; lev <= L; lev++) launch_finalize(g, c->p, lev, c->stream);
+}
+
+mr_status read_counters(mr_ctx* c) {
+  const size_t nb = sizeof(unsigned long long) * c->g.B * CNT_PER_INST;
+  HIPCHK(c, hipMemcpyAsync(c->cnt_host.data(), c->p.cnt, nb, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return MR_OK;
+}
+
+mr_status check_flags(mr_ctx* c) {
+  mr_status st = read_counters(c);
+  if (st != MR_OK) return st;
+  for (int i = 0; i < c->g.B; i++) {
+    const unsigned long long bad = c->cnt_host[i * CNT_PER_INST + CNT_BAD];
+    if (bad) {
+      c->broken = true;
+      char buf[160];
+      snprintf(buf, sizeof buf, "tree invariant violated in instance %d (code 0x%llx)", i, bad);
+      return set_err(c, MR_ESTATE, buf);
+    }
+  }
+  for (int i = 0; i < c->g.B; i++)
+    if (c->cnt_host[i * CNT_PER_INST + CNT_NONFINITE]) {
+      c->broken = true;
+      char buf[96];
+      snprintf(buf, sizeof buf, "non-finite cell average in instance %d", i);
+      return set_err(c, MR_ENONFINITE, buf);
+    }
+  return MR_OK;
+}
+
+mr_status adapt_impl(mr_ctx* c) {
+  const Geo& g = c->g;
+  project_range(c, g.L - 1, g.l0, PJ_Q0);
+  remesh(c, g.l0);
+  project_range(c, g.L - 1, g.l0, PJ_Q0);
+  mr_status st = check_launch(c, "adapt");
+  if (st != MR_OK) return st;
+  return check_flags(c);
+}
+
+mr_status level_count(mr_ctx* c, int lev, int inst, uint8_t want, long long* total) {
+  const int nblk = (int)((c->g.n[lev] + 255) / 256);
+  launch_count(c->g, c->p, lev, inst, want, c->blockcnt_d, nblk, c->stream);
+  launch_scan_blocks(c->blockcnt_d, nblk, c->total_d, c->stream);
+  HIPCHK(c, hipMemcpyAsync(total, c->total_d, sizeof(long long), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return check_launch(c, "count");
+}
+
+}  // namespace
+
+extern "C" {
+
+int mr_ncomp(const mr_ctx* c) { return c ? c->g.m : 0; }
+
+const char* mr_last_error(const mr_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void mr_destroy(mr_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  for (void* a : c->allocs) (void)hipFree(a);
+  delete c;
+}
+
+mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_scheme* s, mr_ctx** out) {
+  if (!out) return MR_EINVAL;
+  *out = nullptr;
+  if (!s || !eps || dim < 1 || dim > 3 || n_inst < 1) return MR_EINVAL;
+  if (s->l0 < 2 || L < s->l0 || L > MR_MAXLEV || L - s->l0 > 20 || dim * L > 40) return MR_EINVAL;
+  if (s->rk != 3 || s->lt != 1 || s->pde < MR_PDE_ADVECTION || s->pde > MR_PDE_LINEAR) return MR_EINVAL;
+  if (s->recon < 0 || s->recon > 2) return MR_EINVAL;
+  for (int a = 0; a < dim; a++) {
+    if ((s->bc[a][0] == MR_BC_PERIODIC) != (s->bc[a][1] == MR_BC_PERIODIC)) return MR_EINVAL;
+    if (!(s->hi[a] > s->lo[a])) return MR_EINVAL;
+  }
+  for (int i = 0; i < n_inst; i++)
+    if (!(eps[i] >= 0.0) || !std::isfinite(eps[i])) return MR_EINVAL;
+
+  mr_ctx* c = new mr_ctx();
+  c->s = *s;
+  Geo& g = c->g;
+  memset(&g, 0, sizeof g);
+  g.d = dim;
+  g.L = L;
+  g.l0 = s->l0;
+  g.m = s->pde == MR_PDE_EULER ? dim + 2 : 1;
+  g.nsub = 1 << (dim - 1);
+  g.B = n_inst;
+  g.pde = s->pde;
+  g.recon = s->recon;
+  g.thresh = s->thresh;
+  g.reflux = s->reflux;
+  for (int a = 0; a < 3; a++) g.periodic[a] = a < dim && s->bc[a][0] == MR_BC_PERIODIC;
+  int64_t off = 0, rc = 0, rf = 0;
+  for (int lev = g.l0; lev <= L; lev++) {
+    g.n[lev] = (int64_t)1 << (dim * lev);
+    g.off[lev] = off;
+    off += g.B * g.n[lev];
+    g.rc_off[lev] = rc;
+    g.rf_off[lev] = rf;
+    if (lev < L) {
+      rc += (int64_t)2 * dim * g.m * g.B * g.n[lev];
+      rf += (int64_t)2 * dim * g.nsub * g.m * g.B * g.n[lev];
+    }
+    double v = 1.0;
+    for (int a = 0; a < 3; a++) {
+      if (a < dim) {
+        const double dx = (s->hi[a] - s->lo[a]) / (double)((int64_t)1 << lev);
+        g.invdx[lev][a] = 1.0 / dx;
+        v = v * dx;
+      } else {
+        g.invdx[lev][a] = 1.0;
+      }
+    }
+    g.vol[lev] = v;
+  }
+  g.Ntot = off;
+  g.nu = s->nu;
+  g.k_react = s->k_react;
+  g.a_react = s->a_react;
+  g.gamma = s->gamma;
+  for (int a = 0; a < 3; a++) g.adv[a] = s->adv_vel[a];
+  for (int k = 0; k < 5; k++) g.scale[k] = s->detail_scale[k] > 0.0 ? s->detail_scale[k] : 1.0;
+
+  c->eps.assign(eps, eps + n_inst);
+  c->t.assign(n_inst, 0.0);
+  c->dt_host.assign(n_inst, 0.0);
+  c->cnt_host.assign((size_t)n_inst * CNT_PER_INST, 0);
+  c->max_blocks = (int)((g.n[L] + 255) / 256);
+
+  mr_status st = MR_OK;
+  void* ptr;
+#define ALLOC(field, type, count)                                          \
+  do {                                                                     \
+    st = dalloc(c, &ptr, sizeof(type) * (size_t)(count));                  \
+    if (st != MR_OK) goto fail;                                            \
+    field = (type*)ptr;                                                    \
+  } while (0)
+  ALLOC(c->p.st, uint8_t, g.Ntot);
+  ALLOC(c->p.rf, uint8_t, g.Ntot);
+  ALLOC(c->p.gh, uint8_t, g.Ntot);
+  for (int sl = 0; sl < SL_COUNT; sl++) ALLOC(c->p.q[sl], double, (int64_t)g.m * g.Ntot);
+  ALLOC(c->p.regc, double, g.rc_off[L]);
+  ALLOC(c->p.regf, double, g.rf_off[L]);
+  ALLOC(c->dt_d, double, n_inst);
+  ALLOC(c->eps_d, double, n_inst);
+  ALLOC(c->p.cnt, unsigned long long, (int64_t)n_inst * CNT_PER_INST);
+  ALLOC(c->blockcnt_d, int, c->max_blocks + 1);
+  ALLOC(c->total_d, long long, 1);
+  ALLOC(c->err_d, int, 1);
+  ALLOC(c->ws_d, unsigned long long, n_inst);
+  ALLOC(c->part_d, double, (int64_t)(c->max_blocks + 1) * g.m);
+#undef ALLOC
+  c->p.dt = c->dt_d;
+  c->p.eps = c->eps_d;
+  st = hip_check(c, hipMemcpy(c->eps_d, eps, sizeof(double) * n_inst, hipMemcpyHostToDevice), "eps upload");
+  if (st != MR_OK) goto fail;
+  st = hip_check(c, hipDeviceSynchronize(), "init");
+  if (st != MR_OK) goto fail;
+  *out = c;
+  return MR_OK;
+fail:
+  mr_destroy(c);
+  return st;
+}
+
+mr_status mr_init(int dim, int L, double eps, const mr_scheme* s, mr_ctx** out) {
+  return mr_init_batch(dim, L, 1, &eps, s, out);
+}
+
+mr_status mr_set_stream(mr_ctx* c, void* hip_stream) {
+  if (!c) return MR_EINVAL;
+  c->stream = (hipStream_t)hip_stream;
+  return MR_OK;
+}
+
+mr_status mr_synchronize(mr_ctx* c) {
+  if (!c) return MR_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return MR_OK;
+}
+
+mr_status mr_load_finest(mr_ctx* c, const double* q0, void* hip_stream) {
+  if (!c || !q0) return MR_EINVAL;
+  c->stream = (hipStream_t)hip_stream;
+  const Geo& g = c->g;
+  for (int lev = g.l0; lev < g.L; lev++) launch_fill_status(g, c->p, lev, ST_INTERNAL, c->stream);
+  launch_load_finest(g, c->p, q0, c->stream);
+  launch_clear_regs(g, c->p, c->stream);
+  HIPCHK(c, hipMemsetAsync(c->p.cnt, 0, sizeof(unsigned long long) * g.B * CNT_PER_INST, c->stream));
+  mr_status st = check_launch(c, "load_finest");
+  if (st != MR_OK) return st;
+  std::fill(c->t.begin(), c->t.end(), 0.0);
+  c->iters = 0;
+  c->broken = false;
+  c->err.clear();
+  return adapt_impl(c);
+}
+
+mr_status mr_adapt(mr_ctx* c) {
+  if (!c) return MR_EINVAL;
+  if (c->broken) return set_err(c, MR_ESTATE, "context in error state");
+  return adapt_impl(c);
+}
+
+mr_status mr_lt_step_batch(mr_ctx* c, const double* dt) {
+  if (!c || !dt) return MR_EINVAL;
+  if (c->broken) return set_err(c, MR_ESTATE, "context in error state: reload or set leaves");
+  for (int i = 0; i < c->g.B; i++)
+    if (!(dt[i] > 0.0) || !std::isfinite(dt[i])) return set_err(c, MR_EINVAL, "dt_L must be positive");
+  c->dt_host.assign(dt, dt + c->g.B);
+  HIPCHK(c, hipMemcpyAsync(c->dt_d, c->dt_host.data(), sizeof(double) * c->g.B, hipMemcpyHostToDevice, c->stream));
+  const int64_t N = (int64_t)1 << (c->g.L - c->g.l0);
+  for (int64_t n = 0; n < N; n++) lt_iteration(c, n, N);
+  mr_status st = check_launch(c, "lt_step");
+  if (st != MR_OK) return st;
+  for (int i = 0; i < c->g.B; i++) c->t[i] = c->t[i] + (double)N * dt[i];
+  c->iters += N;
+  return check_flags(c);
+}
+
+mr_status mr_lt_step(mr_ctx* c, double dt_L) {
+  if (!c) return MR_EINVAL;
+  std::vector<double> dt((size_t)c->g.B, dt_L);
+  return mr_lt_step_batch(c, dt.data());
+}
+
+mr_status mr_reconstruct(mr_ctx* c, double* q_out) {
+  if (!c || !q_out) return MR_EINVAL;
+  const Geo& g = c->g;
+  project_range(c, g.L - 1, g.l0, PJ_Q0);
+  double* dense = c->p.q[SL_H1];
+  for (int lev = g.l0; lev <= g.L; lev++) launch_recon_level(g, c->p, lev, dense, c->stream);
+  launch_to_rowmajor(g, dense, q_out, c->stream);
+  mr_status st = check_launch(c, "reconstruct");
+  if (st != MR_OK) return st;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return MR_OK;
+}
+
+mr_status mr_max_wavespeed(mr_ctx* c, double* out) {
+  if (!c || !out) return MR_EINVAL;
+  const Geo& g = c->g;
+  HIPCHK(c, hipMemsetAsync(c->ws_d, 0, sizeof(unsigned long long) * g.B, c->stream));
+  for (int lev = g.l0; lev <= g.L; lev++) launch_wavespeed(g, c->p, lev, c->ws_d, c->stream);
+  std::vector<unsigned long long> bits((size_t)g.B);
+  HIPCHK(c, hipMemcpyAsync(bits.data(), c->ws_d, sizeof(unsigned long long) * g.B, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int i = 0; i < g.B; i++) memcpy(&out[i], &bits[i], sizeof(double));
+  return check_launch(c, "max_wavespeed");
+}
+
+mr_status mr_get_leaves_inst(mr_ctx* c, int inst, uint64_t* keys, double* q, int64_t cap, int64_t* n) {
+  if (!c || !n || inst < 0 || inst >= c->g.B) return MR_EINVAL;
+  const Geo& g = c->g;
+  std::vector<long long> per(MR_MAXLEV + 1, 0);
+  long long tot = 0;
+  for (int lev = g.l0; lev <= g.L; lev++) {
+    mr_status st = level_count(c, lev, inst, ST_LEAF, &per[lev]);
+    if (st != MR_OK) return st;
+    tot += per[lev];
+  }
+  *n = tot;
+  if (!keys || !q) return MR_OK;
+  if (cap < tot) return set_err(c, MR_ECAPACITY, "leaf buffer too small");
+  void* kd = nullptr;
+  void* vd = nullptr;
+  HIPCHK(c, hipMalloc(&kd, sizeof(unsigned long long) * (size_t)(tot + 1)));
+  if (hipMalloc(&vd, sizeof(double) * (size_t)(tot + 1) * g.m) != hipSuccess) {
+    (void)hipFree(kd);
+    return set_err(c, MR_ENOMEM, "leaf staging buffer");
+  }
+  long long base = 0;
+  for (int lev = g.l0; lev <= g.L; lev++) {
+    const int nblk = (int)((g.n[lev] + 255) / 256);
+    launch_count(g, c->p, lev, inst, ST_LEAF, c->blockcnt_d, nblk, c->stream);
+    launch_scan_blocks(c->blockcnt_d, nblk, c->total_d, c->stream);
+    launch_gather_leaves(g, c->p, lev, inst, c->blockcnt_d, nblk, base, (unsigned long long*)kd, (double*)vd,
+                         tot, c->stream);
+    base += per[lev];
+  }
+  hipError_t e1 = hipMemcpyAsync(keys, kd, sizeof(uint64_t) * (size_t)tot, hipMemcpyDeviceToHost, c->stream);
+  hipError_t e2 = hipMemcpyAsync(q, vd, sizeof(double) * (size_t)tot * g.m, hipMemcpyDeviceToHost, c->stream);
+  hipError_t e3 = hipStreamSynchronize(c->stream);
+  (void)hipFree(kd);
+  (void)hipFree(vd);
+  HIPCHK(c, e1);
+  HIPCHK(c, e2);
+  HIPCHK(c, e3);
+  return check_launch(c, "get_leaves");
+}
+
+mr_status mr_get_leaves(mr_ctx* c, uint64_t* keys, double* q, int64_t cap, int64_t* n) {
+  return mr_get_leaves_inst(c, 0, keys, q, cap, n);
+}
+
+__global__ void k_fill_range(uint8_t* st, int64_t base, int64_t n, uint8_t v) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    st[base + t] = v;
+}
+
+__global__ void k_reset_counters(unsigned long long* cnt, int inst) {
+  if (threadIdx.x < CNT_PER_INST) cnt[inst * CNT_PER_INST + threadIdx.x] = 0;
+}
+
+mr_status mr_set_leaves_inst(mr_ctx* c, int inst, const uint64_t* keys, const double* q, int64_t n, double t) {
+  if (!c || inst < 0 || inst >= c->g.B || n < 0 || (n > 0 && (!keys || !q))) return MR_EINVAL;
+  const Geo& g = c->g;
+  for (int lev = g.l0; lev <= g.L; lev++) {
+    const int64_t base = g.off[lev] + (int64_t)inst * g.n[lev];
+    k_fill_range<<<blocks_for(g.n[lev]), 256, 0, c->stream>>>(c->p.st, base, g.n[lev], ST_ABSENT);
+  }
+  void* kd = nullptr;
+  void* vd = nullptr;
+  HIPCHK(c, hipMalloc(&kd, sizeof(uint64_t) * (size_t)(n + 1)));
+  if (hipMalloc(&vd, sizeof(double) * (size_t)(n + 1) * g.m) != hipSuccess) {
+    (void)hipFree(kd);
+    return set_err(c, MR_ENOMEM, "leaf staging buffer");
+  }
+  int herr = 0;
+  hipError_t e = hipMemsetAsync(c->err_d, 0, sizeof(int), c->stream);
+  if (e == hipSuccess && n > 0)
+    e = hipMemcpyAsync(kd, keys, sizeof(uint64_t) * (size_t)n, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess && n > 0)
+    e = hipMemcpyAsync(vd, q, sizeof(double) * (size_t)n * g.m, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) {
+    launch_scatter_leaves(g, c->p, inst, (const unsigned long long*)kd, (const double*)vd, n, c->err_d, c->stream);
+    for (int lev = g.L; lev > g.l0; lev--) launch_mark_parents(g, c->p, lev, c->err_d, c->stream);
+    for (int lev = g.l0; lev <= g.L; lev++) launch_validate(g, c->p, lev, c->err_d, c->stream);
+    e = hipMemcpyAsync(&herr, c->err_d, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(kd);
+  (void)hipFree(vd);
+  HIPCHK(c, e);
+  if (herr) {
+    char buf[96];
+    snprintf(buf, sizeof buf, "leaves do not form a complete graded tree (code %d)", herr);
+    c->broken = true;
+    return set_err(c, MR_EINVAL, buf);
+  }
+  project_range(c, g.L - 1, g.l0, PJ_Q0);
+  launch_clear_regs(g, c->p, c->stream);
+  for (int lev = g.l0 + 1; lev <= g.L; lev++) launch_ghost_flags(g, c->p, lev, c->stream);
+  k_reset_counters<<<1, 64, 0, c->stream>>>(c->p.cnt, inst);
+  mr_status st = check_launch(c, "set_leaves");
+  if (st != MR_OK) return st;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->t[inst] = t;
+  c->broken = false;
+  c->err.clear();
+  return MR_OK;
+}
+
+mr_status mr_set_leaves(mr_ctx* c, const uint64_t* keys, const double* q, int64_t n, double t) {
+  return mr_set_leaves_inst(c, 0, keys, q, n, t);
+}
+
+mr_status mr_stats_inst(mr_ctx* c, int inst, mr_stats_t* out) {
+  if (!c || !out || inst < 0 || inst >= c->g.B) return MR_EINVAL;
+  const Geo& g = c->g;
+  memset(out, 0, sizeof *out);
+  out->t = c->t[inst];
+  out->iterations = c->iters;
+  std::vector<double> part;
+  for (int lev = g.l0; lev <= g.L; lev++) {
+    long long nl = 0;
+    mr_status st = level_count(c, lev, inst, ST_LEAF, &nl);
+    if (st != MR_OK) return st;
+    out->leaves[lev] = nl;
+    const int nblk = (int)((g.n[lev] + 255) / 256);
+    launch_mass_partial(g, c->p, lev, inst, c->part_d, nblk, c->stream);
+    part.resize((size_t)nblk * g.m);
+    HIPCHK(c, hipMemcpyAsync(part.data(), c->part_d, sizeof(double) * part.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int b = 0; b < nblk; b++)
+      for (int k = 0; k < g.m; k++) out->mass[k] = out->mass[k] + part[(size_t)b * g.m + k];
+  }
+  mr_status st = read_counters(c);
+  if (st != MR_OK) return st;
+  out->leaf_updates = (int64_t)c->cnt_host[inst * CNT_PER_INST + CNT_UPDATES];
+  out->near_threshold = (int64_t)c->cnt_host[inst * CNT_PER_INST + CNT_NEAR];
+  return check_launch(c, "stats");
+}
+
+mr_status mr_stats(mr_ctx* c, mr_stats_t* out) { return mr_stats_inst(c, 0, out); }
+
+}  // extern "C"

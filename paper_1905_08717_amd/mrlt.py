@@ -1,0 +1,250 @@
+"""Thin Python binding of libmrlt.so (the C ABI in include/mrlt.h).
+
+Argument marshalling only: every step of the macro step runs in the HIP
+library.  Device buffers are torch tensors on a HIP device (PyTorch is used
+for device memory and streams).  Loading fails loudly when the library has
+not been built: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmrlt.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENONFINITE, ECAPACITY = 0, -1, -2, -3, -4, -5, -6
+PDE = {"advection": 0, "burgers": 1, "nagumo": 2, "euler": 3, "linear": 4}
+BC = {"periodic": 0, "neumann": 1}
+MAXLEV = 24
+
+# every symbol declared in include/mrlt.h
+EXPORTS = [
+    "mr_init", "mr_init_batch", "mr_set_stream", "mr_ncomp", "mr_load_finest", "mr_adapt",
+    "mr_lt_step", "mr_lt_step_batch", "mr_reconstruct", "mr_max_wavespeed", "mr_get_leaves",
+    "mr_get_leaves_inst", "mr_set_leaves", "mr_set_leaves_inst", "mr_stats", "mr_stats_inst",
+    "mr_synchronize", "mr_last_error", "mr_destroy",
+]
+
+
+class MrScheme(ctypes.Structure):
+    _fields_ = [
+        ("pde", ctypes.c_int32), ("rk", ctypes.c_int32), ("lt", ctypes.c_int32),
+        ("l0", ctypes.c_int32), ("recon", ctypes.c_int32), ("thresh", ctypes.c_int32),
+        ("reflux", ctypes.c_int32), ("remesh", ctypes.c_int32),
+        ("bc", (ctypes.c_int32 * 2) * 3),
+        ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
+        ("nu", ctypes.c_double), ("k_react", ctypes.c_double), ("a_react", ctypes.c_double),
+        ("gamma", ctypes.c_double), ("adv_vel", ctypes.c_double * 3),
+        ("detail_scale", ctypes.c_double * 5),
+    ]
+
+
+class MrStats(ctypes.Structure):
+    _fields_ = [
+        ("t", ctypes.c_double),
+        ("leaves", ctypes.c_int64 * (MAXLEV + 1)),
+        ("leaf_updates", ctypes.c_int64),
+        ("near_threshold", ctypes.c_int64),
+        ("iterations", ctypes.c_int64),
+        ("mass", ctypes.c_double * 5),
+    ]
+
+
+class MrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library():
+    """Load libmrlt.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_1905_08717_amd/build.py "
+                          "(the HIP path has no fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+    dp = ctypes.POINTER(ctypes.c_double)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    sp = ctypes.POINTER(MrScheme)
+    L.mr_init.argtypes = [i32, i32, dbl, sp, ctypes.POINTER(vp)]
+    L.mr_init_batch.argtypes = [i32, i32, i32, dp, sp, ctypes.POINTER(vp)]
+    L.mr_set_stream.argtypes = [vp, vp]
+    L.mr_ncomp.argtypes = [vp]
+    L.mr_load_finest.argtypes = [vp, vp, vp]
+    L.mr_adapt.argtypes = [vp]
+    L.mr_lt_step.argtypes = [vp, dbl]
+    L.mr_lt_step_batch.argtypes = [vp, dp]
+    L.mr_reconstruct.argtypes = [vp, vp]
+    L.mr_max_wavespeed.argtypes = [vp, dp]
+    L.mr_get_leaves.argtypes = [vp, u64p, dp, i64, ctypes.POINTER(i64)]
+    L.mr_get_leaves_inst.argtypes = [vp, i32, u64p, dp, i64, ctypes.POINTER(i64)]
+    L.mr_set_leaves.argtypes = [vp, u64p, dp, i64, dbl]
+    L.mr_set_leaves_inst.argtypes = [vp, i32, u64p, dp, i64, dbl]
+    L.mr_stats.argtypes = [vp, ctypes.POINTER(MrStats)]
+    L.mr_stats_inst.argtypes = [vp, i32, ctypes.POINTER(MrStats)]
+    L.mr_synchronize.argtypes = [vp]
+    L.mr_last_error.argtypes = [vp]
+    L.mr_last_error.restype = ctypes.c_char_p
+    L.mr_destroy.argtypes = [vp]
+    L.mr_destroy.restype = None
+    for name in EXPORTS:
+        if name not in ("mr_last_error", "mr_destroy", "mr_ncomp"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def make_scheme(cfg: dict) -> MrScheme:
+    s = MrScheme()
+    d = cfg["dim"]
+    s.pde = PDE[cfg["pde"]]
+    s.rk = 3
+    s.lt = 1
+    s.l0 = cfg.get("l0", 2)
+    s.recon = cfg.get("recon", 1)
+    s.thresh = cfg.get("thresh", 1)
+    s.reflux = cfg.get("reflux", 1)
+    s.remesh = cfg.get("remesh", 1)
+    bc = cfg.get("bc", "periodic")
+    for a in range(3):
+        b = bc[a] if isinstance(bc, (list, tuple)) else bc
+        s.bc[a][0] = BC[b]
+        s.bc[a][1] = BC[b]
+        s.lo[a] = cfg.get("lo", [0.0] * 3)[a] if a < d else 0.0
+        s.hi[a] = cfg.get("hi", [1.0] * 3)[a] if a < d else 1.0
+    s.nu = cfg.get("nu", 0.0)
+    s.k_react = cfg.get("k_react", 0.0)
+    s.a_react = cfg.get("a_react", 0.0)
+    s.gamma = cfg.get("gamma", 1.4)
+    v = cfg.get("adv_vel", [1.0, 0.0, 0.0])
+    for a in range(3):
+        s.adv_vel[a] = v[a]
+    sc = cfg.get("detail_scale", [1.0] * 5)
+    for k in range(5):
+        s.detail_scale[k] = sc[k]
+    return s
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+class Solver:
+    """A batch of MRLT/NERK3 solves on one GPU (n_inst = 1 for a single solve)."""
+
+    def __init__(self, cfg: dict, n_inst: int = 1, eps=None, stream=None):
+        import torch
+
+        self.torch = torch
+        L = load_library()
+        self.cfg = dict(cfg)
+        self.dim, self.L = cfg["dim"], cfg["L"]
+        self.n_inst = n_inst
+        if eps is None:
+            eps = [cfg["eps"]] * n_inst
+        eps_arr = (ctypes.c_double * n_inst)(*[float(e) for e in eps])
+        self._s = make_scheme(cfg)
+        h = ctypes.c_void_p()
+        self._h = None
+        rc = L.mr_init_batch(self.dim, self.L, n_inst, eps_arr, ctypes.byref(self._s), ctypes.byref(h))
+        if rc != OK:
+            raise MrError(rc, "mr_init_batch failed")
+        self._h = h
+        self.m = L.mr_ncomp(h)
+        self.nfine = 1 << (self.dim * self.L)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._check(L.mr_set_stream(h, _stream_ptr(self.stream)), "mr_set_stream")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().mr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc != OK:
+            msg = load_library().mr_last_error(self._h) if self._h else b""
+            raise MrError(rc, f"{what} failed: {msg.decode() if msg else ''}")
+
+    def load_finest(self, q0):
+        """q0: torch FP64 device tensor [n_inst, m, 2^{dL}] (or numpy, copied)."""
+        t = self.torch
+        if isinstance(q0, np.ndarray):
+            q0 = t.from_numpy(np.ascontiguousarray(q0, dtype=np.float64)).to("cuda")
+        q0 = q0.contiguous()
+        assert q0.dtype == t.float64 and q0.is_cuda and q0.numel() == self.n_inst * self.m * self.nfine
+        self._q0_keep = q0
+        self._check(load_library().mr_load_finest(self._h, ctypes.c_void_p(q0.data_ptr()),
+                                                  _stream_ptr(self.stream)), "mr_load_finest")
+
+    def adapt(self):
+        self._check(load_library().mr_adapt(self._h), "mr_adapt")
+
+    def lt_step(self, dt):
+        if np.ndim(dt) == 0:
+            self._check(load_library().mr_lt_step(self._h, float(dt)), "mr_lt_step")
+        else:
+            arr = (ctypes.c_double * self.n_inst)(*[float(x) for x in dt])
+            self._check(load_library().mr_lt_step_batch(self._h, arr), "mr_lt_step_batch")
+
+    def lt_step_rc(self, dt) -> int:
+        return load_library().mr_lt_step(self._h, float(dt))
+
+    def reconstruct(self):
+        out = self.torch.empty((self.n_inst, self.m, self.nfine), dtype=self.torch.float64, device="cuda")
+        self._check(load_library().mr_reconstruct(self._h, ctypes.c_void_p(out.data_ptr())), "mr_reconstruct")
+        return out
+
+    def max_wavespeed(self):
+        arr = (ctypes.c_double * self.n_inst)()
+        self._check(load_library().mr_max_wavespeed(self._h, arr), "mr_max_wavespeed")
+        return np.array(arr[:])
+
+    def get_leaves(self, inst: int = 0):
+        L = load_library()
+        n = ctypes.c_int64()
+        self._check(L.mr_get_leaves_inst(self._h, inst, None, None, 0, ctypes.byref(n)), "mr_get_leaves")
+        keys = np.zeros(n.value, dtype=np.uint64)
+        q = np.zeros((self.m, n.value))
+        self._check(L.mr_get_leaves_inst(self._h, inst, keys.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                         q.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n.value,
+                                         ctypes.byref(n)), "mr_get_leaves")
+        return keys, q
+
+    def set_leaves(self, keys, q, t: float = 0.0, inst: int = 0):
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        q = np.ascontiguousarray(q, dtype=np.float64).reshape(self.m, len(keys))
+        self._check(load_library().mr_set_leaves_inst(
+            self._h, inst, keys.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+            q.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(keys), float(t)), "mr_set_leaves")
+
+    def stats(self, inst: int = 0) -> dict:
+        st = MrStats()
+        self._check(load_library().mr_stats_inst(self._h, inst, ctypes.byref(st)), "mr_stats")
+        return {
+            "t": st.t,
+            "leaves": [st.leaves[i] for i in range(MAXLEV + 1)],
+            "leaf_updates": st.leaf_updates,
+            "near_threshold": st.near_threshold,
+            "iterations": st.iterations,
+            "mass": [st.mass[k] for k in range(self.m)],
+        }
+
+    def synchronize(self):
+        self._check(load_library().mr_synchronize(self._h), "mr_synchronize")
