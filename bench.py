@@ -1,0 +1,192 @@
+#!/usr/bin/env python3
+"""Benchmark: leaf cell-updates/s of MRLT/NERK3 macro steps on one MI355X.
+
+Workload: the 2D Nagumo flame-front configuration (512^2 finest cells, L=9,
+l0=2, eps=1e-3 with level-dependent thresholds, k=1e3, a=0.2, Neumann unit
+square, CFL 0.5, dt_L = 4.76372e-7 so that t=0.01 is 164 macro steps), run
+as a batch of B independently seeded fronts advanced by the same launches.
+A step is one macro step (2^{L-l0} = 128 fine iterations of every stage
+of the method, remesh included) over the whole batch.
+
+value  = leaf-updates (one per leaf per full RK step, counted on the device)
+         over the K timed macro steps / wall time, inputs resident in HBM.
+roofline = the RK stage kernels (the data-parallel hot path): algorithmic
+         bytes 64 m B per leaf-update (read q^n, write q*; read q^n, q*,
+         write q**; read q^n, q**, write q^{n+1}) over their HIP-event time.
+cpu_baseline = the CPU oracle on one instance of the same workload.
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+
+def total_updates(s):
+    return int(sum(int(s.level_updates(i).sum()) for i in range(s.n_inst)))
+
+
+def leaf_counts(s):
+    tot = np.zeros(25, dtype=np.int64)
+    for i in range(s.n_inst):
+        tot += np.array(s.stats(i)["leaves"], dtype=np.int64)
+    return tot
+
+
+def cpu_baseline(cfg, q0, dt, seconds):
+    """The oracle as it is, on this host, for about `seconds` of work."""
+    from oracle import mro
+    o = mro.Oracle(cfg)
+    o.load_finest(q0)
+    u0 = o.stats()["leaf_updates"]
+    t0 = time.perf_counter()
+    nmac = 0
+    while True:
+        o.lt_step(dt)
+        nmac += 1
+        el = time.perf_counter() - t0
+        if el > seconds or nmac >= 64:
+            break
+    upd = o.stats()["leaf_updates"] - u0
+    return {"value": upd / el, "unit": "leaf-updates/s", "cores": mro.num_threads(), "kind": "oracle",
+            "sample": f"1 instance of the same workload, {nmac} macro steps from t=0 ({upd} leaf-updates, "
+                      f"{el:.1f} s), OpenMP threads={mro.num_threads()}"}
+
+
+def systems_mode(args):
+    """Batched (256 uneven 2D Euler four-quadrant solves) or served (Poisson
+    arrivals of Burgers / Nagumo requests) forms; one JSON line."""
+    import torch  # noqa: F401
+    from paper_1905_08717_amd import systems as S
+    if args.mode == "batched":
+        reqs = S.batched_euler_requests(args.requests or 256)
+        t0 = time.perf_counter()
+        b = S.run_batched(reqs)
+        solo_reqs = S.batched_euler_requests(args.requests or 256)
+        n_solo = min(len(solo_reqs), args.solo_sample)
+        a = S.run_one_at_a_time(solo_reqs[:n_solo])
+        same = all(np.array_equal(r.result[0], q.result[0]) and np.array_equal(r.result[1], q.result[1])
+                   for r, q in zip(reqs[:n_solo], solo_reqs[:n_solo]))
+        out = {"metric": "batched solves/s", "value": round(b["solves_per_s"], 3), "unit": "solves/s",
+               "n_gpus": 1, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+               "config": {"workload": f"{len(reqs)} 2D Euler four-quadrant Riemann problems, L in {{7,8,9}}, "
+                                      "eps in {1e-2,1e-3,1e-4}, t_final 0.25, per-instance CFL 0.5"},
+               "batched": b,
+               "one_at_a_time": dict(a, note=f"first {n_solo} of the same requests, each alone"),
+               "speedup_vs_one_at_a_time": round(b["solves_per_s"] / a["solves_per_s"], 3),
+               "results_identical_to_solo": bool(same), "wall_s": round(time.perf_counter() - t0, 2)}
+    else:
+        reqs = S.served_requests(args.requests or 200, rate=args.rate,
+                                 burgers_levels=tuple(range(10, args.max_burgers_level + 1)))
+        r = S.serve(reqs, hbm_budget=args.hbm_budget * 2 ** 30)
+        out = {"metric": "served p50/p99 time-to-solution", "value": round(r["p50_s"], 4), "unit": "s",
+               "n_gpus": 1, "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+               "config": {"workload": f"{len(reqs)} requests, Poisson {args.rate}/s, half 1D viscous Burgers "
+                                      f"(L 10..{args.max_burgers_level}, t_final 0.5), half 2D Nagumo "
+                                      "(L 7..9, t_final 0.01), eps log-uniform [1e-4, 1e-2]"},
+               "served": r}
+    print(json.dumps(out), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", choices=["throughput", "batched", "served"], default="throughput")
+    ap.add_argument("--requests", type=int, default=0)
+    ap.add_argument("--solo-sample", type=int, default=64)
+    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--max-burgers-level", type=int, default=14)
+    ap.add_argument("--hbm-budget", type=float, default=64.0, help="GiB for resident solves")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (--gpus 1); independent solves would shard "
+              "across GPUs by instance, which is not built here", file=sys.stderr)
+        sys.exit(2)
+
+    if args.mode != "throughput":
+        systems_mode(args)
+        return
+
+    import torch
+    from paper_1905_08717_amd import mrlt
+    from paper_1905_08717_amd import workloads as W
+
+    cfg = W.nagumo_2d()
+    B = args.batch
+    dt = W.nagumo_dt(cfg)
+    q0 = np.stack([W.nagumo_front(cfg["L"], W.SEED + i) for i in range(B)])
+    s = mrlt.Solver(cfg, n_inst=B)
+    s.load_finest(torch.from_numpy(q0).to("cuda"))
+    for _ in range(args.warmup):
+        s.lt_step(dt)
+
+    # timed region: K macro steps over the batch
+    u0 = total_updates(s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s.lt_step(dt)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    upd = total_updates(s) - u0
+    value = upd / el
+    leaves = leaf_counts(s)
+
+    # roofline of the stage kernels: HIP events around each of their launches
+    # over the same number of macro steps
+    u1 = total_updates(s)
+    s.timing_start("stage")
+    for _ in range(args.steps):
+        s.lt_step(dt)
+    ms, launches = s.timing_stop()
+    upd_r = total_updates(s) - u1
+    m = s.m
+    alg_bytes = upd_r * 64 * m
+    achieved = alg_bytes / (ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": 8000.0, "unit": "GB/s",
+                "frac": round(achieved / 8000.0, 5), "traffic": None,
+                "kernel": "k_stage (RK stage kernels, all levels)",
+                "launches": launches, "avg_launch_us": round(ms * 1e3 / max(launches, 1), 3),
+                "alg_bytes_per_leaf_update": 64 * m}
+
+    # single-solve reference (one instance), same work per macro step
+    s1 = mrlt.Solver(cfg, n_inst=1)
+    s1.load_finest(torch.from_numpy(q0[:1]).to("cuda"))
+    s1.lt_step(dt)
+    a = total_updates(s1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(2):
+        s1.lt_step(dt)
+    torch.cuda.synchronize()
+    single = (total_updates(s1) - a) / (time.perf_counter() - t1)
+
+    out = {
+        "metric": "leaf cell-updates/s", "value": round(value, 1), "unit": "leaf-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(el / args.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"nagumo2d_L9_512x512_eps1e-3 batch of {B} seeded fronts "
+                               f"(one macro step = 128 fine iterations per instance)",
+                   "dim": 2, "L": 9, "l0": 2, "eps": 1e-3, "batch": B, "dt_L": dt,
+                   "leaves_per_level_total": [int(x) for x in leaves[:10]]},
+        "roofline": roofline,
+        "single_solve_leaf_updates_per_s": round(single, 1),
+        "solves_macro_steps_per_s": round(B * args.steps / el, 2),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, q0[0], dt, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

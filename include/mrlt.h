@@ -57,7 +57,8 @@ enum { MR_BC_PERIODIC = 0, MR_BC_NEUMANN = 1 };
  *          Godunov advective flux), Nagumo (m=1, -nu grad u, source
  *          k u (1-u)(u-a)), Euler (m=d+2: rho, rho u_i, E; AUSM+), linear
  *          (m=1, -nu grad u, source k u)
- *  rk      3 (compact RK3 with NERK partials, Sec. 3)
+ *  rk      3 (MRLT/NERK3: compact RK3 with NERK partials at theta 1/4, 3/4)
+ *          or 2 (MRLT/NERK2: compact RK2 with the NERK theta = 1/2 value), Sec. 3
  *  lt      1 (local time stepping, Sec. 4)
  *  l0      coarsest level, >= 2
  *  recon   0 first order, 1 MUSCL-minmod, 2 centred (advection only)
@@ -106,6 +107,23 @@ int mr_ncomp(const mr_ctx* c);
  * q0: device, [n_inst][m][2^{dL}], x fastest (index x + n(y + n z)).      */
 mr_status mr_load_finest(mr_ctx* c, const double* q0, void* hip_stream);
 
+/* Load one instance of a batch (a free or finished slot) and build its
+ * adapted tree; the other instances are not changed.
+ * q0: device, [m][2^{dL}], x fastest.                                      */
+mr_status mr_load_finest_inst(mr_ctx* c, int inst, const double* q0);
+
+/* Free one instance of a batch: all of its cells become absent, it drops out
+ * of every kernel's work until it is loaded again.                         */
+mr_status mr_clear_instance(mr_ctx* c, int inst);
+
+/* Error flags of one instance: bit 0 non-finite value, bit 1 tree
+ * invariant violated.  Clearing the failed instances (mr_clear_instance)
+ * lets the others continue.                                                 */
+mr_status mr_instance_flags(mr_ctx* c, int inst, int* flags);
+
+/* Threshold eps >= 0 of one instance, used from its next load / remesh. */
+mr_status mr_set_eps(mr_ctx* c, int inst, double eps);
+
 /* Full remesh at the current synchronised time (Alg. AdaptiveMesh with
  * Alg. waveletThres; no level frozen).                                     */
 mr_status mr_adapt(mr_ctx* c);
@@ -144,6 +162,29 @@ mr_status mr_set_leaves_inst(mr_ctx* c, int inst, const uint64_t* keys, const do
 /* Statistics of instance 0 (or `inst`). */
 mr_status mr_stats(mr_ctx* c, mr_stats_t* out);
 mr_status mr_stats_inst(mr_ctx* c, int inst, mr_stats_t* out);
+
+/* Measurement support.  Cumulative leaf-updates of instance `inst` per
+ * level (host array of MR_MAXLEV + 1 entries; one update = one leaf
+ * advanced by one full RK step at that level).                           */
+mr_status mr_level_updates(mr_ctx* c, int inst, int64_t* per_level);
+
+/* Kernel classes for mr_timing_start. */
+enum {
+  MR_KC_STAGE_FINEST = 1,  /* RK stage kernels on the finest level */
+  MR_KC_STAGE = 2,         /* RK stage kernels on all levels */
+  MR_KC_PROJECT = 3,       /* projections and synchronisation values of internal nodes */
+  MR_KC_GHOST = 4,         /* virtual-cell prediction */
+  MR_KC_REMESH = 5,        /* details, safety, closure, pruning, apply, ghost flags */
+  MR_KC_FINALIZE = 6       /* end of step and conservative correction */
+};
+
+/* Bracket every later launch of one kernel class with a pair of HIP events
+ * on the context's stream, until mr_timing_stop.                          */
+mr_status mr_timing_start(mr_ctx* c, int kernel_class);
+
+/* Synchronise; *total_ms = summed event time of the timed launches,
+ * *launches = their number.  Ends the timing.                             */
+mr_status mr_timing_stop(mr_ctx* c, double* total_ms, int64_t* launches);
 
 /* Wait for all queued work of the context. */
 mr_status mr_synchronize(mr_ctx* c);

@@ -31,6 +31,9 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ABSENT 0
 #define LEAF 1
@@ -205,7 +208,8 @@ static int slot_own(int st, int stage) {
 /* Slot of a level-p cell used to predict virtual children for level p+1 at
  * stage s.  Case A (p >= l_min, both levels start at t^n): S1 q^n, S2 the
  * first-order theta=1/2 value (Sec. 4.1.1), S3 theta=1/4 (Alg. refRK22).
- * Case B (p = l_min - 1, mid-step): S1 q** of leaves (Sec. 4.3) or the fresh
+ * Case B (p = l_min - 1, mid-step): S1 q** (RK3) or the NERK theta=1/2
+ * value (RK2) of leaves (Sec. 4.3; both kept in QH) or the fresh
  * projection of internal nodes (Alg. alg-LTS); S2 the end value of leaves or
  * the end value of Sec. 4.3 of internal nodes; S3 theta=3/4 (Alg. refRK22). */
 static int slot_parent(const mro_ctx* c, int p, int st, int stage) {
@@ -551,7 +555,8 @@ static void stage_level(mro_ctx* c, int lev, int stage) {
   int d = c->d, m = c->m;
   level_t* LV = &c->lv[lev];
   double h = ldexp(c->dt, c->L - lev); /* eq. dt */
-  double w = stage == 3 ? C_2_3 : C_1_6;
+  /* weights b_i of the RK method (Sec. 3): RK3 (1/6, 1/6, 2/3), RK2 (1/2, 1/2) */
+  double w = c->s.rk == 2 ? C_HALF : (stage == 3 ? C_2_3 : C_1_6);
   double wh = w * h;
   int64_t nc = LV->ncell;
 #pragma omp parallel for schedule(dynamic, 256)
@@ -579,6 +584,24 @@ static void stage_level(mro_ctx* c, int lev, int stage) {
     for (int k = 0; k < m; k++) {
       double q0 = SL(c, lev, S_Q0, k, i);
       double r = R[k];
+      if (c->s.rk == 2) {
+        /* compact RK2 with the NERK theta=1/2 value in two parts, 3/8 after
+         * the first stage and 1/8 after the second (Sec. 3); the first-order
+         * theta=1/2 value H1 serves the finer level's stage 2 (Sec. 4.1.1) */
+        if (stage == 1) {
+          SL(c, lev, S_Q1, k, i) = q0 + (h * r);
+          SL(c, lev, S_H1, k, i) = q0 + ((C_HALF * h) * r);
+          SL(c, lev, S_QH, k, i) = q0 + ((0.375 * h) * r);
+        } else {
+          double q1 = SL(c, lev, S_Q1, k, i);
+          double qe = ((C_HALF * q0) + (C_HALF * q1)) + ((C_HALF * h) * r);
+          SL(c, lev, S_QE, k, i) = qe;
+          SL(c, lev, S_X2, k, i) = q1 + (h * r);
+          SL(c, lev, S_QH, k, i) = SL(c, lev, S_QH, k, i) + ((0.125 * h) * r);
+          if (!isfinite(qe)) c->nonfinite = 1;
+        }
+        continue;
+      }
       if (stage == 1) {
         SL(c, lev, S_Q1, k, i) = q0 + (h * r);
         SL(c, lev, S_H1, k, i) = q0 + ((C_HALF * h) * r);
@@ -1043,6 +1066,13 @@ static void lt_iteration(mro_ctx* c, int64_t n, int64_t N) {
     if (lev < L) proj_rk2(c, lev);
     stage_level(c, lev, 2);
   }
+  if (c->s.rk == 2) {
+    /* RK2: the step ends with stage 2 */
+    int lnext2 = (n + 1 == N) ? c->l0 : lmin_of(c, n + 1);
+    finalize(c, lnext2);
+    c->iters++;
+    return;
+  }
   refresh3(c);
   for (int lev = L; lev >= lmin; lev--) {
     if (lev < L) proj_rk3(c, lev);
@@ -1075,7 +1105,7 @@ int mro_init(int dim, int L, double eps, const mro_scheme* s, mro_ctx** out) {
   *out = NULL;
   if (dim < 1 || dim > 3 || !(eps >= 0.0)) return MRO_EINVAL;
   if (s->l0 < 2 || L < s->l0 || L > MRO_MAXLEV || (int64_t)dim * L > 40) return MRO_EINVAL;
-  if (s->rk != 3 || s->lt != 1 || s->pde < 0 || s->pde > MRO_PDE_LINEAR) return MRO_EINVAL;
+  if ((s->rk != 2 && s->rk != 3) || s->lt != 1 || s->pde < 0 || s->pde > MRO_PDE_LINEAR) return MRO_EINVAL;
   if (L - s->l0 > 20) return MRO_EINVAL;
   for (int a = 0; a < dim; a++) {
     if ((s->bc[a][0] == MRO_BC_PERIODIC) != (s->bc[a][1] == MRO_BC_PERIODIC)) return MRO_EINVAL;
@@ -1140,6 +1170,14 @@ void mro_destroy(mro_ctx* c) {
 }
 
 int mro_ncomp(const mro_ctx* c) { return c ? c->m : 0; }
+
+int mro_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 const char* mro_last_error(const mro_ctx* c) { return c ? c->err : "null context"; }
 

@@ -32,7 +32,7 @@ enum { MRO_BC_PERIODIC = 0, MRO_BC_NEUMANN = 1 };
 
 typedef struct {
   int32_t pde;        /* MRO_PDE_* */
-  int32_t rk;         /* 3 only */
+  int32_t rk;         /* 3 (MRLT/NERK3) or 2 (MRLT/NERK2) */
   int32_t lt;         /* 1 only: local time stepping */
   int32_t l0;         /* coarsest level */
   int32_t recon;      /* 0 first order, 1 MUSCL-minmod, 2 centred (advection) */
@@ -59,6 +59,7 @@ typedef struct mro_ctx mro_ctx;
 int  mro_init(int dim, int L, double eps, const mro_scheme* s, mro_ctx** out);
 void mro_destroy(mro_ctx* c);
 int  mro_ncomp(const mro_ctx* c);
+int  mro_num_threads(void);                               /* OpenMP threads used */
 int  mro_load_finest(mro_ctx* c, const double* q0);   /* [m][2^{dL}] x fastest */
 int  mro_adapt(mro_ctx* c);
 int  mro_lt_step(mro_ctx* c, double dt_L);

@@ -77,6 +77,7 @@ def lib():
         L.mro_destroy.argtypes = [vp]
         L.mro_destroy.restype = None
         L.mro_ncomp.argtypes = [vp]
+        L.mro_num_threads.argtypes = []
         L.mro_load_finest.argtypes = [vp, dp]
         L.mro_adapt.argtypes = [vp]
         L.mro_lt_step.argtypes = [vp, dbl]
@@ -106,7 +107,7 @@ def make_scheme(cfg: dict) -> Scheme:
     s = Scheme()
     d = cfg["dim"]
     s.pde = PDE[cfg["pde"]]
-    s.rk = 3
+    s.rk = cfg.get("rk", 3)
     s.lt = 1
     s.l0 = cfg.get("l0", 2)
     s.recon = cfg.get("recon", 1)
@@ -239,6 +240,10 @@ class Oracle:
         F = np.zeros(self.m)
         self._check(lib().mro_face_flux(self._h, lev, direction, _dp(c), _dp(F)), "mro_face_flux")
         return F
+
+
+def num_threads() -> int:
+    return lib().mro_num_threads()
 
 
 def predict(dim: int, stencil: np.ndarray) -> np.ndarray:

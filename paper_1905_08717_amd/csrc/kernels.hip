@@ -320,19 +320,35 @@ void launch_fill_status(const Geo& g, const Dev& p, int lev, uint8_t v, hipStrea
 }
 
 template <int D>
-__global__ void k_load_finest(Geo g, Dev p, const double* src) {
+__global__ void k_load_finest(Geo g, Dev p, const double* src, int only) {
   const int L = g.L;
-  const int64_t nl = g.n[L], N = g.B * nl;
+  const int64_t nl = g.n[L], N = (only >= 0 ? 1 : g.B) * nl;
   const int n = 1 << L;
-  GSL(t, N) {
+  GSL(u, N) {
+    const int64_t t = only >= 0 ? (int64_t)only * nl + u : u;
     const int64_t inst = t >> (D * L);
+    const int64_t isrc = only >= 0 ? 0 : inst;
     int x[3];
     mdec<D>((uint64_t)(t & (nl - 1)), x);
     const int64_t r = x[0] + (int64_t)n * (x[1] + (int64_t)n * x[2]);
     const int64_t G = g.off[L] + t;
-    for (int k = 0; k < g.m; k++) p.q[SL_Q0][(int64_t)k * g.Ntot + G] = src[(inst * g.m + k) * nl + r];
+    for (int k = 0; k < g.m; k++) p.q[SL_Q0][(int64_t)k * g.Ntot + G] = src[(isrc * g.m + k) * nl + r];
     p.st[G] = ST_LEAF;
   }
+}
+
+// statuses of one instance: levels below L internal, level L absent (the
+// finest level is then written by k_load_finest); or all absent (free slot)
+__global__ void k_fill_instance(Geo g, Dev p, int inst, int free_slot) {
+  for (int lev = g.l0; lev <= g.L; lev++) {
+    const int64_t nl = g.n[lev];
+    const uint8_t v = free_slot ? ST_ABSENT : (lev < g.L ? ST_INTERNAL : ST_ABSENT);
+    GSL(u, nl) p.st[g.off[lev] + (int64_t)inst * nl + u] = v;
+  }
+}
+
+void launch_fill_instance(const Geo& g, const Dev& p, int inst, hipStream_t s) {
+  k_fill_instance<<<blocks_for(g.n[g.L]), TPB, 0, s>>>(g, p, inst >= 0 ? inst : -1 - inst, inst < 0);
 }
 
 template <int D>
@@ -400,14 +416,19 @@ __global__ void k_to_rowmajor(Geo g, const double* dense, double* out) {
 //   PJ_RK3   Alg. projRK3: q** from the children's stage-3 values, then
 //            eq. rk3proj
 
+__device__ __forceinline__ int list_len(const Dev& p, int type, int lev) {
+  return p.lcnt[type * (MRD_MAXLEV + 1) + lev];
+}
+
 __global__ __launch_bounds__(TPB) void k_project(Geo g, Dev p, int lev, int mode) {
-  const int64_t N = g.B * g.n[lev];
   const int nch = 1 << g.d;
   const double sc = g.d == 1 ? 0.5 : (g.d == 2 ? 0.25 : 0.125);
   const int64_t NT = g.Ntot;
-  GSL(t, N) {
+  const int n = list_len(p, LS_INTERNAL, lev);
+  const int* lst = p.lst[LS_INTERNAL] + g.off[lev];
+  GSL(i, n) {
+    const int64_t t = lst[i];
     const int64_t G = g.off[lev] + t;
-    if (p.st[G] != ST_INTERNAL) continue;
     const int64_t C0 = g.off[lev + 1] + (t << g.d);
     uint8_t cs[8];
     for (int cb = 0; cb < nch; cb++) cs[cb] = p.st[C0 + cb];
@@ -463,34 +484,41 @@ void launch_project(const Geo& g, const Dev& p, int lev, int mode, hipStream_t s
 //     projection, S2 end value, S3 theta=3/4 value (Alg. refRK22, Sec. 4.3)
 
 template <int D>
-__global__ __launch_bounds__(TPB) void k_ghost(Geo g, Dev p, int lev, int src, int dst) {
-  const int64_t nl = g.n[lev], N = g.B * nl;
-  GSL(t, N) {
-    const int64_t G = g.off[lev] + t;
-    if (!p.gh[G]) continue;
-    const int64_t inst = t >> (D * lev);
-    int x[3];
-    mdec<D>((uint64_t)(t & (nl - 1)), x);
-    const int px[3] = {x[0] >> 1, x[1] >> 1, x[2] >> 1};
-    const int64_t ibp = g.off[lev - 1] + inst * g.n[lev - 1];
-    const int cb = (x[0] & 1) | ((x[1] & 1) << 1) | ((x[2] & 1) << 2);
-    for (int k = 0; k < g.m; k++) {
-      double S[27], T[8];
-      if (!gather27<D>(g, p, p.q[src], lev - 1, ibp, px, k, S)) flag_bad(p, inst, 1);
-      pred_terms<D>(S, T);
-      p.q[dst][(int64_t)k * g.Ntot + G] = pred_child<D>(T, cb);
+__global__ __launch_bounds__(TPB) void k_ghost(Geo g, Dev p, int lo, int hi, int cb_lev, int srcA, int srcB,
+                                              int dst) {
+  for (int lev = lo; lev <= hi; lev++) {
+    const int64_t nl = g.n[lev];
+    const int n = list_len(p, LS_GHOST, lev);
+    const int* lst = p.lst[LS_GHOST] + g.off[lev];
+    const double* src = p.q[lev == cb_lev ? srcB : srcA];
+    GSL(i, n) {
+      const int64_t t = lst[i];
+      const int64_t G = g.off[lev] + t;
+      const int64_t inst = t >> (D * lev);
+      int x[3];
+      mdec<D>((uint64_t)(t & (nl - 1)), x);
+      const int px[3] = {x[0] >> 1, x[1] >> 1, x[2] >> 1};
+      const int64_t ibp = g.off[lev - 1] + inst * g.n[lev - 1];
+      const int cb = (x[0] & 1) | ((x[1] & 1) << 1) | ((x[2] & 1) << 2);
+      for (int k = 0; k < g.m; k++) {
+        double S[27], T[8];
+        if (!gather27<D>(g, p, src, lev - 1, ibp, px, k, S)) flag_bad(p, inst, 1);
+        pred_terms<D>(S, T);
+        p.q[dst][(int64_t)k * g.Ntot + G] = pred_child<D>(T, cb);
+      }
     }
   }
 }
 
-void launch_ghost(const Geo& g, const Dev& p, int lev, int stage, int caseb, hipStream_t s) {
-  const int src = caseb ? (stage == 1 ? SL_QH : (stage == 2 ? SL_QE : SL_N34))
-                        : (stage == 1 ? SL_Q0 : (stage == 2 ? SL_H1 : SL_N14));
+void launch_ghost(const Geo& g, const Dev& p, int lo, int hi, int cb_lev, int stage, hipStream_t s) {
+  if (lo > hi) return;
+  const int srcB = stage == 1 ? SL_QH : (stage == 2 ? SL_QE : SL_N34);
+  const int srcA = stage == 1 ? SL_Q0 : (stage == 2 ? SL_H1 : SL_N14);
   const int dst = stage == 1 ? SL_Q0 : (stage == 2 ? SL_Q1 : SL_QH);
-  const int64_t n = g.B * g.n[lev];
-  if (g.d == 1) k_ghost<1><<<blocks_for(n), TPB, 0, s>>>(g, p, lev, src, dst);
-  else if (g.d == 2) k_ghost<2><<<blocks_for(n), TPB, 0, s>>>(g, p, lev, src, dst);
-  else k_ghost<3><<<blocks_for(n), TPB, 0, s>>>(g, p, lev, src, dst);
+  const int64_t n = g.B * g.n[hi];
+  if (g.d == 1) k_ghost<1><<<blocks_for(n), TPB, 0, s>>>(g, p, lo, hi, cb_lev, srcA, srcB, dst);
+  else if (g.d == 2) k_ghost<2><<<blocks_for(n), TPB, 0, s>>>(g, p, lo, hi, cb_lev, srcA, srcB, dst);
+  else k_ghost<3><<<blocks_for(n), TPB, 0, s>>>(g, p, lo, hi, cb_lev, srcA, srcB, dst);
 }
 
 // ---------------------------------------------------------------------------
@@ -576,146 +604,175 @@ __device__ __noinline__ void refined_flux(const Geo& g, const Dev& p, int lev, i
 }
 
 template <int D, int PDE>
-__global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lev, int stage) {
+__global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int stage) {
   constexpr int M = NC<D, PDE>::M;
   constexpr double C_1_6 = 1.0 / 6.0, C_2_3 = 2.0 / 3.0, C_1_3 = 1.0 / 3.0;
-  const int64_t nl = g.n[lev], N = g.B * nl;
-  const int n = 1 << lev;
+  // one leaf-update per leaf and full RK step: counted once, at stage 1
+  if (stage == 1 && blockIdx.x == 0) {
+    const int nlv = hi - lo + 1;
+    for (int j = threadIdx.x; j < g.B * nlv; j += blockDim.x) {
+      const int inst = j / nlv, lev = lo + j % nlv;
+      p.cnt[(int64_t)inst * CNT_PER_INST + CNT_LEVEL0 + lev] +=
+          (unsigned long long)p.leafcnt[inst * (MRD_MAXLEV + 1) + lev];
+    }
+  }
   const int64_t NT = g.Ntot;
   const double* cur = p.q[stage == 1 ? SL_Q0 : (stage == 2 ? SL_Q1 : SL_QH)];
-  const bool finest = lev == g.L;
-  GSL(t, N) {
-    const int64_t G = g.off[lev] + t;
-    const bool leaf = p.st[G] == ST_LEAF;
-    const int64_t inst = t >> (D * lev);
-    if (stage == 1) {
-      // one leaf-update per leaf and full RK step
-      if (nl >= 64) {
-        const unsigned long long bal = __ballot(leaf);
-        if ((threadIdx.x & 63) == 0 && bal)
-          atomicAdd(&p.cnt[inst * CNT_PER_INST + CNT_UPDATES], (unsigned long long)__popcll(bal));
-      } else if (leaf) {
-        atomicAdd(&p.cnt[inst * CNT_PER_INST + CNT_UPDATES], 1ull);
-      }
-    }
-    if (!leaf) continue;
-    int x[3];
-    mdec<D>((uint64_t)(t & (nl - 1)), x);
-    const int64_t ib = g.off[lev] + inst * nl;
-    const double h = ldexp(p.dt[inst], g.L - lev);
-    const double wh = (stage == 3 ? C_2_3 : C_1_6) * h;
-    double R[M];
+  for (int lev = lo; lev <= hi; lev++) {
+    const int64_t nl = g.n[lev];
+    const int n = 1 << lev;
+    const bool finest = lev == g.L;
+    const int cntl = list_len(p, LS_LEAF, lev);
+    const int* lst = p.lst[LS_LEAF] + g.off[lev];
+    GSL(i, cntl) {
+      const int64_t t = lst[i];
+      const int64_t G = g.off[lev] + t;
+      const int64_t inst = t >> (D * lev);
+      int x[3];
+      mdec<D>((uint64_t)(t & (nl - 1)), x);
+      const int64_t ib = g.off[lev] + inst * nl;
+      const double h = ldexp(p.dt[inst], g.L - lev);
+      // weights b_i of the RK method: RK3 (1/6, 1/6, 2/3), RK2 (1/2, 1/2)
+      const double wh = (g.rk == 2 ? 0.5 : (stage == 3 ? C_2_3 : C_1_6)) * h;
+      double R[M];
 #pragma unroll
-    for (int dir = 0; dir < D; dir++) {
-      double c5[5][M];
+      for (int dir = 0; dir < D; dir++) {
+        double c5[5][M];
 #pragma unroll
-      for (int o = -2; o <= 2; o++) {
-        int y[3] = {x[0], x[1], x[2]};
-        y[dir] = map_st(x[dir] + o, n, g.periodic[dir]);
-        const int64_t Gy = o == 0 ? G : ib + (int64_t)menc<D>(y);
-#pragma unroll
-        for (int k = 0; k < M; k++) c5[o + 2][k] = cur[(int64_t)k * NT + Gy];
-      }
-      double Fm[M], Fp[M];
-      int nbs[2];
-      uint8_t sts[2];
-#pragma unroll
-      for (int side = 0; side < 2; side++) {
-        const int nb = map_nb(x[dir] + (side ? 1 : -1), n, g.periodic[dir]);
-        nbs[side] = nb;
-        uint8_t s = 3;  // outside the domain
-        if (nb >= 0) {
+        for (int o = -2; o <= 2; o++) {
+          // two-point diffusion needs only the face neighbours
+          if ((PDE == PDE_NAGUMO || PDE == PDE_LINEAR) && (o == -2 || o == 2)) continue;
           int y[3] = {x[0], x[1], x[2]};
-          y[dir] = nb;
-          s = p.st[ib + (int64_t)menc<D>(y)];
-        }
-        sts[side] = s;
-        double* F = side ? Fp : Fm;
-        if (s == ST_INTERNAL && lev < g.L) refined_flux<D, PDE>(g, p, lev, stage, inst, x, dir, side, nb, F);
-        else face_flux<D, PDE>(g, lev, dir, c5 + side, F);
-      }
+          y[dir] = map_st(x[dir] + o, n, g.periodic[dir]);
+          const int64_t Gy = o == 0 ? G : ib + (int64_t)menc<D>(y);
 #pragma unroll
-      for (int k = 0; k < M; k++) {
-        const double r = (Fm[k] - Fp[k]) * g.invdx[lev][dir];
-        R[k] = dir == 0 ? r : (R[k] + r);
-      }
-      if (g.reflux) {
+          for (int k = 0; k < M; k++) c5[o + 2][k] = cur[(int64_t)k * NT + Gy];
+        }
+        if (PDE == PDE_NAGUMO || PDE == PDE_LINEAR) {
+#pragma unroll
+          for (int k = 0; k < M; k++) c5[0][k] = c5[4][k] = 0.0;
+        }
+        double Fm[M], Fp[M];
+        int nbs[2];
+        uint8_t sts[2];
 #pragma unroll
         for (int side = 0; side < 2; side++) {
-          const double* F = side ? Fp : Fm;
-          if (sts[side] == ST_INTERNAL && lev < g.L) {
-            for (int k = 0; k < M; k++) {
-              double* r = regc_at(g, p, lev, 2 * dir + side, k, t);
-              *r = *r + (wh * F[k]);
-            }
-          } else if (sts[side] == ST_ABSENT) {
-            // fine side of a coarse leaf's refined face
-            int y[3] = {x[0] >> 1, x[1] >> 1, x[2] >> 1};
-            y[dir] = nbs[side] >> 1;
-            const int64_t tX = inst * g.n[lev - 1] + (int64_t)menc<D>(y);
-            if (p.st[g.off[lev - 1] + tX] != ST_LEAF) flag_bad(p, inst, 8);
-            int t0, t1;
-            transverse<D>(dir, t0, t1);
-            int b = 0;
-            if (t0 >= 0) b |= x[t0] & 1;
-            if (t1 >= 0) b |= (x[t1] & 1) << 1;
-            const int fX = 2 * dir + (side ? 0 : 1);
-            for (int k = 0; k < M; k++) {
-              double* r = regf_at(g, p, lev - 1, fX, b, k, tX);
-              *r = *r + (wh * F[k]);
+          const int nb = map_nb(x[dir] + (side ? 1 : -1), n, g.periodic[dir]);
+          nbs[side] = nb;
+          uint8_t sv = 3;  // outside the domain
+          if (nb >= 0) {
+            int y[3] = {x[0], x[1], x[2]};
+            y[dir] = nb;
+            sv = p.st[ib + (int64_t)menc<D>(y)];
+          }
+          sts[side] = sv;
+          double* F = side ? Fp : Fm;
+          if (sv == ST_INTERNAL && !finest) refined_flux<D, PDE>(g, p, lev, stage, inst, x, dir, side, nb, F);
+          else face_flux<D, PDE>(g, lev, dir, c5 + side, F);
+        }
+#pragma unroll
+        for (int k = 0; k < M; k++) {
+          const double r = (Fm[k] - Fp[k]) * g.invdx[lev][dir];
+          R[k] = dir == 0 ? r : (R[k] + r);
+        }
+        if (g.reflux) {
+#pragma unroll
+          for (int side = 0; side < 2; side++) {
+            const double* F = side ? Fp : Fm;
+            if (sts[side] == ST_INTERNAL && !finest) {
+              for (int k = 0; k < M; k++) {
+                double* r = regc_at(g, p, lev, 2 * dir + side, k, t);
+                *r = *r + (wh * F[k]);
+              }
+            } else if (sts[side] == ST_ABSENT) {
+              // fine side of a coarse leaf's refined face
+              int y[3] = {x[0] >> 1, x[1] >> 1, x[2] >> 1};
+              y[dir] = nbs[side] >> 1;
+              const int64_t tX = inst * g.n[lev - 1] + (int64_t)menc<D>(y);
+              if (p.st[g.off[lev - 1] + tX] != ST_LEAF) flag_bad(p, inst, 8);
+              int t0, t1;
+              transverse<D>(dir, t0, t1);
+              int b = 0;
+              if (t0 >= 0) b |= x[t0] & 1;
+              if (t1 >= 0) b |= (x[t1] & 1) << 1;
+              const int fX = 2 * dir + (side ? 0 : 1);
+              for (int k = 0; k < M; k++) {
+                double* r = regf_at(g, p, lev - 1, fX, b, k, tX);
+                *r = *r + (wh * F[k]);
+              }
             }
           }
         }
       }
-    }
-    if (PDE == PDE_NAGUMO || PDE == PDE_LINEAR) R[0] = R[0] + source<PDE>(g, cur[G]);
+      if (PDE == PDE_NAGUMO || PDE == PDE_LINEAR) R[0] = R[0] + source<PDE>(g, cur[G]);
 #pragma unroll
-    for (int k = 0; k < M; k++) {
-      const int64_t I = (int64_t)k * NT + G;
-      const double q0 = p.q[SL_Q0][I];
-      const double r = R[k];
-      if (stage == 1) {
-        p.q[SL_Q1][I] = q0 + (h * r);
-        if (!finest) {
-          p.q[SL_H1][I] = q0 + ((0.5 * h) * r);
-          p.q[SL_N14][I] = q0 + (((7.0 / 32.0) * h) * r);
-          p.q[SL_N34][I] = q0 + (((15.0 / 32.0) * h) * r);
+      for (int k = 0; k < M; k++) {
+        const int64_t I = (int64_t)k * NT + G;
+        const double q0 = p.q[SL_Q0][I];
+        const double r = R[k];
+        if (g.rk == 2) {
+          // compact RK2; the NERK theta=1/2 value in parts 3/8 and 1/8 (Sec. 3)
+          if (stage == 1) {
+            p.q[SL_Q1][I] = q0 + (h * r);
+            if (!finest) {
+              p.q[SL_H1][I] = q0 + ((0.5 * h) * r);
+              p.q[SL_QH][I] = q0 + ((0.375 * h) * r);
+            }
+          } else {
+            const double q1 = p.q[SL_Q1][I];
+            const double qe = ((0.5 * q0) + (0.5 * q1)) + ((0.5 * h) * r);
+            p.q[SL_QE][I] = qe;
+            p.q[SL_X2][I] = q1 + (h * r);
+            if (!finest) p.q[SL_QH][I] = p.q[SL_QH][I] + ((0.125 * h) * r);
+            if (!isfinite(qe)) atomicOr(&p.cnt[inst * CNT_PER_INST + CNT_NONFINITE], 1ull);
+          }
+          continue;
         }
-      } else if (stage == 2) {
-        const double q1 = p.q[SL_Q1][I];
-        p.q[SL_QH][I] = ((0.75 * q0) + (0.25 * q1)) + ((0.25 * h) * r);
-        p.q[SL_X2][I] = q1 + (h * r);
-        if (!finest) {
-          p.q[SL_N14][I] = p.q[SL_N14][I] + (((1.0 / 32.0) * h) * r);
-          p.q[SL_N34][I] = p.q[SL_N34][I] + (((9.0 / 32.0) * h) * r);
+        if (stage == 1) {
+          p.q[SL_Q1][I] = q0 + (h * r);
+          if (!finest) {
+            p.q[SL_H1][I] = q0 + ((0.5 * h) * r);
+            p.q[SL_N14][I] = q0 + (((7.0 / 32.0) * h) * r);
+            p.q[SL_N34][I] = q0 + (((15.0 / 32.0) * h) * r);
+          }
+        } else if (stage == 2) {
+          const double q1 = p.q[SL_Q1][I];
+          p.q[SL_QH][I] = ((0.75 * q0) + (0.25 * q1)) + ((0.25 * h) * r);
+          p.q[SL_X2][I] = q1 + (h * r);
+          if (!finest) {
+            p.q[SL_N14][I] = p.q[SL_N14][I] + (((1.0 / 32.0) * h) * r);
+            p.q[SL_N34][I] = p.q[SL_N34][I] + (((9.0 / 32.0) * h) * r);
+          }
+        } else {
+          const double qh = p.q[SL_QH][I];
+          const double qe = ((C_1_3 * q0) + (C_2_3 * qh)) + ((C_2_3 * h) * r);
+          p.q[SL_QE][I] = qe;
+          if (!isfinite(qe)) atomicOr(&p.cnt[inst * CNT_PER_INST + CNT_NONFINITE], 1ull);
         }
-      } else {
-        const double qh = p.q[SL_QH][I];
-        const double qe = ((C_1_3 * q0) + (C_2_3 * qh)) + ((C_2_3 * h) * r);
-        p.q[SL_QE][I] = qe;
-        if (!isfinite(qe)) atomicOr(&p.cnt[inst * CNT_PER_INST + CNT_NONFINITE], 1ull);
       }
     }
   }
 }
 
 template <int D>
-static void stage_d(const Geo& g, const Dev& p, int lev, int stage, hipStream_t s) {
-  const int64_t n = g.B * g.n[lev];
-  const int nb = blocks_for(n);
+static void stage_d(const Geo& g, const Dev& p, int lo, int hi, int stage, hipStream_t s) {
+  int64_t cap = 0;
+  for (int lev = lo; lev <= hi; lev++) cap = cap > g.B * g.n[lev] ? cap : g.B * g.n[lev];
+  const int nb = blocks_for(cap);
   switch (g.pde) {
-    case PDE_ADVECTION: k_stage<D, PDE_ADVECTION><<<nb, TPB, 0, s>>>(g, p, lev, stage); break;
-    case PDE_BURGERS: k_stage<D, PDE_BURGERS><<<nb, TPB, 0, s>>>(g, p, lev, stage); break;
-    case PDE_NAGUMO: k_stage<D, PDE_NAGUMO><<<nb, TPB, 0, s>>>(g, p, lev, stage); break;
-    case PDE_EULER: k_stage<D, PDE_EULER><<<nb, TPB, 0, s>>>(g, p, lev, stage); break;
-    default: k_stage<D, PDE_LINEAR><<<nb, TPB, 0, s>>>(g, p, lev, stage); break;
+    case PDE_ADVECTION: k_stage<D, PDE_ADVECTION><<<nb, TPB, 0, s>>>(g, p, lo, hi, stage); break;
+    case PDE_BURGERS: k_stage<D, PDE_BURGERS><<<nb, TPB, 0, s>>>(g, p, lo, hi, stage); break;
+    case PDE_NAGUMO: k_stage<D, PDE_NAGUMO><<<nb, TPB, 0, s>>>(g, p, lo, hi, stage); break;
+    case PDE_EULER: k_stage<D, PDE_EULER><<<nb, TPB, 0, s>>>(g, p, lo, hi, stage); break;
+    default: k_stage<D, PDE_LINEAR><<<nb, TPB, 0, s>>>(g, p, lo, hi, stage); break;
   }
 }
 
-void launch_stage(const Geo& g, const Dev& p, int lev, int stage, hipStream_t s) {
-  if (g.d == 1) stage_d<1>(g, p, lev, stage, s);
-  else if (g.d == 2) stage_d<2>(g, p, lev, stage, s);
-  else stage_d<3>(g, p, lev, stage, s);
+void launch_stage(const Geo& g, const Dev& p, int lo, int hi, int stage, hipStream_t s) {
+  if (lo > hi) return;
+  if (g.d == 1) stage_d<1>(g, p, lo, hi, stage, s);
+  else if (g.d == 2) stage_d<2>(g, p, lo, hi, stage, s);
+  else stage_d<3>(g, p, lo, hi, stage, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -724,52 +781,57 @@ void launch_stage(const Geo& g, const Dev& p, int lev, int stage, hipStream_t s)
 // y-, y+, z-, z+), registers cleared after use
 
 template <int D>
-__global__ __launch_bounds__(TPB) void k_finalize(Geo g, Dev p, int lev) {
-  const int64_t nl = g.n[lev], N = g.B * nl;
-  const int n = 1 << lev;
+__global__ __launch_bounds__(TPB) void k_finalize(Geo g, Dev p, int lo, int hi) {
   const double sc = D == 1 ? 1.0 : (D == 2 ? 0.5 : 0.25);
-  GSL(t, N) {
-    const int64_t G = g.off[lev] + t;
-    if (p.st[G] != ST_LEAF) continue;
-    double q[5];
-    for (int k = 0; k < g.m; k++) q[k] = p.q[SL_QE][(int64_t)k * g.Ntot + G];
-    if (g.reflux && lev < g.L) {
-      const int64_t inst = t >> (D * lev);
-      const int64_t ib = g.off[lev] + inst * nl;
-      int x[3];
-      mdec<D>((uint64_t)(t & (nl - 1)), x);
-      for (int dir = 0; dir < D; dir++)
-        for (int side = 0; side < 2; side++) {
-          const int nb = map_nb(x[dir] + (side ? 1 : -1), n, g.periodic[dir]);
-          if (nb < 0) continue;
-          int y[3] = {x[0], x[1], x[2]};
-          y[dir] = nb;
-          if (p.st[ib + (int64_t)menc<D>(y)] != ST_INTERNAL) continue;
-          const int f = 2 * dir + side;
-          for (int k = 0; k < g.m; k++) {
-            double af = 0.0;
-            for (int b = 0; b < (1 << (D - 1)); b++) {
-              double* r = regf_at(g, p, lev, f, b, k, t);
-              af = (b == 0) ? *r : (af + *r);
-              *r = 0.0;
+  for (int lev = lo; lev <= hi; lev++) {
+    const int64_t nl = g.n[lev];
+    const int n = 1 << lev;
+    const int cntl = list_len(p, LS_LEAF, lev);
+    const int* lst = p.lst[LS_LEAF] + g.off[lev];
+    GSL(i, cntl) {
+      const int64_t t = lst[i];
+      const int64_t G = g.off[lev] + t;
+      double q[5];
+      for (int k = 0; k < g.m; k++) q[k] = p.q[SL_QE][(int64_t)k * g.Ntot + G];
+      if (g.reflux && lev < g.L) {
+        const int64_t inst = t >> (D * lev);
+        const int64_t ib = g.off[lev] + inst * nl;
+        int x[3];
+        mdec<D>((uint64_t)(t & (nl - 1)), x);
+        for (int dir = 0; dir < D; dir++)
+          for (int side = 0; side < 2; side++) {
+            const int nb = map_nb(x[dir] + (side ? 1 : -1), n, g.periodic[dir]);
+            if (nb < 0) continue;
+            int y[3] = {x[0], x[1], x[2]};
+            y[dir] = nb;
+            if (p.st[ib + (int64_t)menc<D>(y)] != ST_INTERNAL) continue;
+            const int f = 2 * dir + side;
+            for (int k = 0; k < g.m; k++) {
+              double af = 0.0;
+              for (int b = 0; b < (1 << (D - 1)); b++) {
+                double* r = regf_at(g, p, lev, f, b, k, t);
+                af = (b == 0) ? *r : (af + *r);
+                *r = 0.0;
+              }
+              af = af * sc;
+              double* rc = regc_at(g, p, lev, f, k, t);
+              const double Dd = (*rc - af) * g.invdx[lev][dir];
+              *rc = 0.0;
+              q[k] = side ? q[k] + Dd : q[k] - Dd;
             }
-            af = af * sc;
-            double* rc = regc_at(g, p, lev, f, k, t);
-            const double Dd = (*rc - af) * g.invdx[lev][dir];
-            *rc = 0.0;
-            q[k] = side ? q[k] + Dd : q[k] - Dd;
           }
-        }
+      }
+      for (int k = 0; k < g.m; k++) p.q[SL_Q0][(int64_t)k * g.Ntot + G] = q[k];
     }
-    for (int k = 0; k < g.m; k++) p.q[SL_Q0][(int64_t)k * g.Ntot + G] = q[k];
   }
 }
 
-void launch_finalize(const Geo& g, const Dev& p, int lev, hipStream_t s) {
-  const int64_t n = g.B * g.n[lev];
-  if (g.d == 1) k_finalize<1><<<blocks_for(n), TPB, 0, s>>>(g, p, lev);
-  else if (g.d == 2) k_finalize<2><<<blocks_for(n), TPB, 0, s>>>(g, p, lev);
-  else k_finalize<3><<<blocks_for(n), TPB, 0, s>>>(g, p, lev);
+void launch_finalize(const Geo& g, const Dev& p, int lo, int hi, hipStream_t s) {
+  if (lo > hi) return;
+  const int64_t n = g.B * g.n[hi];
+  if (g.d == 1) k_finalize<1><<<blocks_for(n), TPB, 0, s>>>(g, p, lo, hi);
+  else if (g.d == 2) k_finalize<2><<<blocks_for(n), TPB, 0, s>>>(g, p, lo, hi);
+  else k_finalize<3><<<blocks_for(n), TPB, 0, s>>>(g, p, lo, hi);
 }
 
 __global__ void k_zero(double* a, int64_t n) { GSL(t, n) a[t] = 0.0; }
@@ -793,11 +855,32 @@ void launch_clear_regs(const Geo& g, const Dev& p, hipStream_t s) {
 //            existence at la; one coarse-to-fine sweep
 //   apply:   new status, new nodes predicted from the parent level
 
+// true when the cell's instance is outside the remesh window
+__device__ __forceinline__ bool inst_of_window_skip(const Geo& g, int64_t t, int shift) {
+  const int64_t inst = t >> shift;
+  return inst < g.i0 || inst >= g.i1;
+}
+
+// dense multi-level sweep: global cell range of levels lo..hi
+__device__ __forceinline__ int64_t level_end(const Geo& g, int hi) { return hi == g.L ? g.Ntot : g.off[hi + 1]; }
+
+#define MULTI_LEVEL_LOOP(G, lev, lo, hi)                                                  \
+  int lev = lo;                                                                            \
+  for (int64_t G = g.off[lo] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;            \
+       G < level_end(g, hi); G += (int64_t)gridDim.x * blockDim.x)                         \
+    if ((lev = level_of(g, lev, hi, G)) >= 0)
+
+__device__ __forceinline__ int level_of(const Geo& g, int lev, int hi, int64_t G) {
+  while (lev < hi && G >= g.off[lev + 1]) lev++;
+  return lev;
+}
+
 template <int D>
-__global__ __launch_bounds__(TPB) void k_detail(Geo g, Dev p, int lev) {
-  const int64_t nl = g.n[lev], N = g.B * nl;
-  GSL(t, N) {
-    const int64_t G = g.off[lev] + t;
+__global__ __launch_bounds__(TPB) void k_detail(Geo g, Dev p, int lo, int hi) {
+  MULTI_LEVEL_LOOP(G, lev, lo, hi) {
+    const int64_t nl = g.n[lev];
+    const int64_t t = G - g.off[lev];
+    if (inst_of_window_skip(g, t, D * lev)) continue;
     uint8_t sig = 0;
     if (lev < g.L && p.st[G] == ST_INTERNAL) {
       const int64_t inst = t >> (D * lev);
@@ -829,11 +912,12 @@ __global__ __launch_bounds__(TPB) void k_detail(Geo g, Dev p, int lev) {
 }
 
 template <int D>
-__global__ __launch_bounds__(TPB) void k_seed(Geo g, Dev p, int lev, int la) {
-  const int64_t nl = g.n[lev], N = g.B * nl;
-  const int n = 1 << lev;
-  GSL(t, N) {
-    const int64_t G = g.off[lev] + t;
+__global__ __launch_bounds__(TPB) void k_seed(Geo g, Dev p, int lo, int hi, int la) {
+  MULTI_LEVEL_LOOP(G, lev, lo, hi) {
+    const int64_t nl = g.n[lev];
+    const int n = 1 << lev;
+    const int64_t t = G - g.off[lev];
+    if (inst_of_window_skip(g, t, D * lev)) continue;
     const uint8_t r = p.rf[G];
     bool w = r & 1;
     const int64_t inst = t >> (D * lev);
@@ -861,6 +945,7 @@ __global__ __launch_bounds__(TPB) void k_close(Geo g, Dev p, int lev) {
   const int64_t nl = g.n[lev], N = g.B * nl;
   const int nf = 1 << (lev + 1);
   GSL(t, N) {
+    if (inst_of_window_skip(g, t, D * lev)) continue;
     const int64_t G = g.off[lev] + t;
     const uint8_t r = p.rf[G];
     if (r & 2) continue;
@@ -887,6 +972,7 @@ __global__ __launch_bounds__(TPB) void k_prune(Geo g, Dev p, int lev, int la) {
   const int64_t nl = g.n[lev], N = g.B * nl;
   const int np = 1 << (lev - 1);
   GSL(t, N) {
+    if (inst_of_window_skip(g, t, D * lev)) continue;
     const int64_t G = g.off[lev] + t;
     const uint8_t r = p.rf[G];
     if (!(r & 2) || lev == g.l0) continue;
@@ -914,6 +1000,7 @@ template <int D>
 __global__ __launch_bounds__(TPB) void k_apply(Geo g, Dev p, int lev, int la) {
   const int64_t nl = g.n[lev], N = g.B * nl;
   GSL(t, N) {
+    if (inst_of_window_skip(g, t, D * lev)) continue;
     const int64_t G = g.off[lev] + t;
     const uint8_t old = p.st[G];
     const bool w = (p.rf[G] & 2) != 0;
@@ -945,11 +1032,11 @@ __global__ __launch_bounds__(TPB) void k_apply(Geo g, Dev p, int lev, int la) {
 // absent cells that a leaf stencil (normal offsets 1 and 2) reads; their
 // parent is then a leaf (grading), the virtual leaves of Fig. 1
 template <int D>
-__global__ __launch_bounds__(TPB) void k_ghost_flags(Geo g, Dev p, int lev) {
-  const int64_t nl = g.n[lev], N = g.B * nl;
-  const int n = 1 << lev;
-  GSL(t, N) {
-    const int64_t G = g.off[lev] + t;
+__global__ __launch_bounds__(TPB) void k_ghost_flags(Geo g, Dev p, int lo, int hi) {
+  MULTI_LEVEL_LOOP(G, lev, lo, hi) {
+    const int64_t nl = g.n[lev];
+    const int n = 1 << lev;
+    const int64_t t = G - g.off[lev];
     uint8_t need = 0;
     if (p.st[G] == ST_ABSENT && p.st[g.off[lev - 1] + (t >> D)] == ST_LEAF) {
       const int64_t inst = t >> (D * lev);
@@ -970,6 +1057,136 @@ __global__ __launch_bounds__(TPB) void k_ghost_flags(Geo g, Dev p, int lev) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// ordered list compaction of levels lo..L: wavefront ballot + popcount per
+// block, an exclusive scan per level, then each block writes its cells at
+// their rank (list order = Morton order within an instance)
+
+__device__ __forceinline__ int comp_level(const Geo& g, int lo, int64_t b) {
+  int lev = lo;
+  while (lev < g.L && b >= g.comp_first[lev + 1]) lev++;
+  return lev;
+}
+
+__device__ __forceinline__ void cell_types(const Dev& p, int64_t G, int* c) {
+  const uint8_t st = p.st[G];
+  c[LS_LEAF] = st == ST_LEAF;
+  c[LS_INTERNAL] = st == ST_INTERNAL;
+  c[LS_GHOST] = p.gh[G] != 0;
+}
+
+// exclusive scan of v over the 256 threads of a block; returns the prefix,
+// *tot receives the block total
+__device__ __forceinline__ int block_exscan(int v, int* sh, int* tot) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int o = 1; o < TPB; o <<= 1) {
+    const int a = tid >= o ? sh[tid - o] : 0;
+    __syncthreads();
+    sh[tid] += a;
+    __syncthreads();
+  }
+  const int incl = sh[tid];
+  *tot = sh[TPB - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ __launch_bounds__(TPB) void k_comp_count(Geo g, Dev p, int lo) {
+  __shared__ int sh[TPB];
+  const int64_t nbt = g.comp_first[g.L + 1];
+  const int64_t b = g.comp_first[lo] + blockIdx.x;
+  const int lev = comp_level(g, lo, b);
+  const int chunk = g.comp_chunk[lev];
+  const int cpt = chunk > TPB ? chunk / TPB : 1;
+  const int64_t t0 = (b - g.comp_first[lev]) * (int64_t)chunk + (int64_t)threadIdx.x * cpt;
+  int c[LS_COUNT] = {0, 0, 0};
+  if ((int)threadIdx.x * cpt < chunk)
+    for (int j = 0; j < cpt; j++) {
+      int e[LS_COUNT];
+      cell_types(p, g.off[lev] + t0 + j, e);
+      for (int k = 0; k < LS_COUNT; k++) c[k] += e[k];
+    }
+  for (int k = 0; k < LS_COUNT; k++) {
+    int tot;
+    block_exscan(c[k], sh, &tot);
+    if (threadIdx.x == 0) p.bcnt[k * nbt + b] = tot;
+  }
+}
+
+// one workgroup per level: per-instance leaf counts, then exclusive scans of
+// the block counts in place and the list lengths
+__global__ __launch_bounds__(TPB) void k_comp_scan(Geo g, Dev p, int lo) {
+  __shared__ int sh[TPB];
+  const int lev = lo + blockIdx.x;
+  const int64_t nbt = g.comp_first[g.L + 1];
+  const int64_t b0 = g.comp_first[lev];
+  const int nb = (int)(g.comp_first[lev + 1] - b0);
+  const int bpi = (int)(g.n[lev] / g.comp_chunk[lev]);  // blocks per instance
+  for (int inst = threadIdx.x; inst < g.B; inst += TPB) {
+    int sum = 0;
+    for (int k = 0; k < bpi; k++) sum += p.bcnt[LS_LEAF * nbt + b0 + (int64_t)inst * bpi + k];
+    p.leafcnt[inst * (MRD_MAXLEV + 1) + lev] = sum;
+  }
+  __syncthreads();
+  const int per = (nb + TPB - 1) / TPB;
+  const int j0 = threadIdx.x * per;
+  const int j1 = j0 + per < nb ? j0 + per : nb;
+  for (int k = 0; k < LS_COUNT; k++) {
+    int* bc = p.bcnt + k * nbt + b0;
+    int loc = 0;
+    for (int j = j0; j < j1; j++) loc += bc[j];
+    int tot;
+    int run = block_exscan(loc, sh, &tot);
+    for (int j = j0; j < j1; j++) {
+      const int v = bc[j];
+      bc[j] = run;
+      run += v;
+    }
+    if (threadIdx.x == 0) p.lcnt[k * (MRD_MAXLEV + 1) + lev] = tot;
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(TPB) void k_comp_write(Geo g, Dev p, int lo) {
+  __shared__ int sh[TPB];
+  const int64_t nbt = g.comp_first[g.L + 1];
+  const int64_t b = g.comp_first[lo] + blockIdx.x;
+  const int lev = comp_level(g, lo, b);
+  const int chunk = g.comp_chunk[lev];
+  const int cpt = chunk > TPB ? chunk / TPB : 1;
+  const int64_t tb = (b - g.comp_first[lev]) * (int64_t)chunk;
+  const int64_t t0 = tb + (int64_t)threadIdx.x * cpt;
+  const bool act = (int)threadIdx.x * cpt < chunk;
+  int c[LS_COUNT] = {0, 0, 0};
+  if (act)
+    for (int j = 0; j < cpt; j++) {
+      int e[LS_COUNT];
+      cell_types(p, g.off[lev] + t0 + j, e);
+      for (int k = 0; k < LS_COUNT; k++) c[k] += e[k];
+    }
+  int base[LS_COUNT];
+  for (int k = 0; k < LS_COUNT; k++) {
+    int tot;
+    base[k] = p.bcnt[k * nbt + b] + block_exscan(c[k], sh, &tot);
+  }
+  if (!act) return;
+  for (int j = 0; j < cpt; j++) {
+    int e[LS_COUNT];
+    cell_types(p, g.off[lev] + t0 + j, e);
+    for (int k = 0; k < LS_COUNT; k++)
+      if (e[k]) p.lst[k][g.off[lev] + base[k]++] = (int)(t0 + j);
+  }
+}
+
+void launch_compact(const Geo& g, const Dev& p, int lo, hipStream_t s) {
+  const int64_t nb = g.comp_first[g.L + 1] - g.comp_first[lo];
+  k_comp_count<<<(unsigned)nb, TPB, 0, s>>>(g, p, lo);
+  k_comp_scan<<<(unsigned)(g.L - lo + 1), TPB, 0, s>>>(g, p, lo);
+  k_comp_write<<<(unsigned)nb, TPB, 0, s>>>(g, p, lo);
+}
+
 #define DISPATCH_D(kern, n, ...)                                                  \
   do {                                                                            \
     const int nb_ = blocks_for(n);                                                \
@@ -978,8 +1195,8 @@ __global__ __launch_bounds__(TPB) void k_ghost_flags(Geo g, Dev p, int lev) {
     else kern<3><<<nb_, TPB, 0, s>>>(__VA_ARGS__);                                \
   } while (0)
 
-void launch_load_finest(const Geo& g, const Dev& p, const double* src, hipStream_t s) {
-  DISPATCH_D(k_load_finest, g.B * g.n[g.L], g, p, src);
+void launch_load_finest(const Geo& g, const Dev& p, const double* src, int inst, hipStream_t s) {
+  DISPATCH_D(k_load_finest, (inst >= 0 ? 1 : g.B) * g.n[g.L], g, p, src, inst);
 }
 void launch_recon_level(const Geo& g, const Dev& p, int lev, double* dense, hipStream_t s) {
   DISPATCH_D(k_recon_level, g.B * g.n[lev], g, p, lev, dense);
@@ -987,11 +1204,16 @@ void launch_recon_level(const Geo& g, const Dev& p, int lev, double* dense, hipS
 void launch_to_rowmajor(const Geo& g, const double* dense, double* out, hipStream_t s) {
   DISPATCH_D(k_to_rowmajor, g.B * g.n[g.L], g, dense, out);
 }
-void launch_detail(const Geo& g, const Dev& p, int lev, hipStream_t s) {
-  DISPATCH_D(k_detail, g.B * g.n[lev], g, p, lev);
+static int64_t range_cells(const Geo& g, int lo, int hi) {
+  return (hi == g.L ? g.Ntot : g.off[hi + 1]) - g.off[lo];
 }
-void launch_seed(const Geo& g, const Dev& p, int lev, int la, hipStream_t s) {
-  DISPATCH_D(k_seed, g.B * g.n[lev], g, p, lev, la);
+void launch_detail(const Geo& g, const Dev& p, int lo, int hi, hipStream_t s) {
+  if (lo > hi) return;
+  DISPATCH_D(k_detail, range_cells(g, lo, hi), g, p, lo, hi);
+}
+void launch_seed(const Geo& g, const Dev& p, int lo, int hi, int la, hipStream_t s) {
+  if (lo > hi) return;
+  DISPATCH_D(k_seed, range_cells(g, lo, hi), g, p, lo, hi, la);
 }
 void launch_close(const Geo& g, const Dev& p, int lev, hipStream_t s) {
   DISPATCH_D(k_close, g.B * g.n[lev], g, p, lev);
@@ -1002,8 +1224,9 @@ void launch_prune(const Geo& g, const Dev& p, int lev, int la, hipStream_t s) {
 void launch_apply(const Geo& g, const Dev& p, int lev, int la, hipStream_t s) {
   DISPATCH_D(k_apply, g.B * g.n[lev], g, p, lev, la);
 }
-void launch_ghost_flags(const Geo& g, const Dev& p, int lev, hipStream_t s) {
-  DISPATCH_D(k_ghost_flags, g.B * g.n[lev], g, p, lev);
+void launch_ghost_flags(const Geo& g, const Dev& p, int lo, int hi, hipStream_t s) {
+  if (lo > hi) return;
+  DISPATCH_D(k_ghost_flags, range_cells(g, lo, hi), g, p, lo, hi);
 }
 
 // ---------------------------------------------------------------------------

@@ -26,11 +26,14 @@ enum { PDE_ADVECTION = 0, PDE_BURGERS = 1, PDE_NAGUMO = 2, PDE_EULER = 3, PDE_LI
 enum { PJ_Q0 = 0, PJ_CASEB, PJ_REF2, PJ_RK2, PJ_REF3, PJ_RK3 };
 
 // counters per instance
-enum { CNT_UPDATES = 0, CNT_NEAR, CNT_NONFINITE, CNT_BAD, CNT_PER_INST };
+enum { CNT_UPDATES = 0, CNT_NEAR, CNT_NONFINITE, CNT_BAD, CNT_LEVEL0 };
+// per instance: the four counters above, then leaf-updates per level
+#define CNT_PER_INST (CNT_LEVEL0 + MRD_MAXLEV + 1)
 
 struct Geo {
   int d, L, l0, m, nsub, B;
   int pde, recon, thresh, reflux;
+  int rk;  // 3: compact RK3 (NERK3), 2: compact RK2 (NERK2)
   int periodic[3];
   int64_t n[MRD_MAXLEV + 1];     // cells per instance at level l (2^{d l})
   int64_t off[MRD_MAXLEV + 1];   // first global index of level l
@@ -41,7 +44,18 @@ struct Geo {
   double vol[MRD_MAXLEV + 1];
   double nu, k_react, a_react, gamma, adv[3];
   double scale[5];
+  // list compaction: level l is cut into blocks of comp_chunk[l] cells (a
+  // power of two <= 4096 that never straddles two instances); its blocks are
+  // comp_first[l] .. comp_first[l+1]-1 of a global block numbering
+  int64_t comp_first[MRD_MAXLEV + 2];
+  int comp_chunk[MRD_MAXLEV + 1];
+  // instances [i0, i1) that the remesh sweeps may change (all of them inside a
+  // macro step; one instance when it is loaded or adapted on its own)
+  int i0, i1;
 };
+
+// per-level lists of cell indices (within-level index t = inst * n[l] + key)
+enum { LS_LEAF = 0, LS_INTERNAL = 1, LS_GHOST = 2, LS_COUNT = 3 };
 
 struct Dev {
   uint8_t* st;     // status per cell
@@ -53,21 +67,31 @@ struct Dev {
   const double* dt;   // [B] dt of the finest level
   const double* eps;  // [B]
   unsigned long long* cnt;  // [B][CNT_PER_INST]
+  int* lst[LS_COUNT];       // level l's list starts at off[l], capacity B n[l]
+  int* lcnt;                // [LS_COUNT][MRD_MAXLEV + 1] list lengths
+  int* bcnt;                // [LS_COUNT][blocks] compaction block counts / offsets
+  int* leafcnt;             // [B][MRD_MAXLEV + 1] leaves per instance and level
 };
 
 // ---- launchers (kernels.hip) -------------------------------------------
 void launch_fill_status(const Geo& g, const Dev& p, int lev, uint8_t v, hipStream_t s);
-void launch_load_finest(const Geo& g, const Dev& p, const double* src, hipStream_t s);
+void launch_load_finest(const Geo& g, const Dev& p, const double* src, int inst, hipStream_t s);
+void launch_fill_instance(const Geo& g, const Dev& p, int inst, hipStream_t s);
 void launch_project(const Geo& g, const Dev& p, int lev, int mode, hipStream_t s);
-void launch_ghost(const Geo& g, const Dev& p, int lev, int stage, int caseb, hipStream_t s);
-void launch_stage(const Geo& g, const Dev& p, int lev, int stage, hipStream_t s);
-void launch_finalize(const Geo& g, const Dev& p, int lev, hipStream_t s);
-void launch_detail(const Geo& g, const Dev& p, int lev, hipStream_t s);
-void launch_seed(const Geo& g, const Dev& p, int lev, int la, hipStream_t s);
+// virtual cells of levels lo..hi at `stage`; level cb_lev (if in range) is
+// the child of the mid-step level (case B)
+void launch_ghost(const Geo& g, const Dev& p, int lo, int hi, int cb_lev, int stage, hipStream_t s);
+// stage kernel over the leaves of levels lo..hi (stage 1 also adds the
+// leaf-updates of these levels to the counters)
+void launch_stage(const Geo& g, const Dev& p, int lo, int hi, int stage, hipStream_t s);
+void launch_finalize(const Geo& g, const Dev& p, int lo, int hi, hipStream_t s);
+void launch_detail(const Geo& g, const Dev& p, int lo, int hi, hipStream_t s);
+void launch_seed(const Geo& g, const Dev& p, int lo, int hi, int la, hipStream_t s);
+void launch_compact(const Geo& g, const Dev& p, int lo, hipStream_t s);
 void launch_close(const Geo& g, const Dev& p, int lev, hipStream_t s);
 void launch_prune(const Geo& g, const Dev& p, int lev, int la, hipStream_t s);
 void launch_apply(const Geo& g, const Dev& p, int lev, int la, hipStream_t s);
-void launch_ghost_flags(const Geo& g, const Dev& p, int lev, hipStream_t s);
+void launch_ghost_flags(const Geo& g, const Dev& p, int lo, int hi, hipStream_t s);
 void launch_recon_level(const Geo& g, const Dev& p, int lev, double* dense, hipStream_t s);
 void launch_to_rowmajor(const Geo& g, const double* dense, double* out, hipStream_t s);
 void launch_count(const Geo& g, const Dev& p, int lev, int inst, uint8_t want, int* blockcnt,

@@ -4,6 +4,7 @@
 // local-time-stepping macro step (Alg. alg-LTS of arXiv:1905.08717, one call
 // per fine iteration n = 0 .. 2^{L-l0}-1) and marshals the boundary calls.
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -31,6 +32,13 @@ struct mr_ctx {
   unsigned long long* ws_d = nullptr;
   double* part_d = nullptr;
   int max_blocks = 0;
+  hipStream_t own_stream = nullptr;   // default stream of the context
+  bool use_graph = true;              // replay the captured macro step
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  int timed_class = 0;          // kernel class under HIP-event timing (0: none)
+  std::vector<hipEvent_t> ev;   // event pairs around timed launches
+  size_t ev_used = 0;
 };
 
 namespace {
@@ -74,26 +82,62 @@ mr_status check_launch(mr_ctx* c, const char* what) {
   return hip_check(c, hipGetLastError(), what);
 }
 
-void project_range(mr_ctx* c, int hi, int lo, int mode) {
-  for (int lev = hi; lev >= lo; lev--) launch_project(c->g, c->p, lev, mode, c->stream);
+// run `launch` and, when its kernel class is being timed, bracket it with a
+// pair of HIP events on the context's stream
+template <class F>
+void timed(mr_ctx* c, int kc, F&& launch) {
+  const bool on = c->timed_class == kc || (c->timed_class == MR_KC_STAGE && kc == MR_KC_STAGE_FINEST);
+  if (!on) {
+    launch();
+    return;
+  }
+  if (c->ev_used + 2 > c->ev.size()) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+      launch();
+      return;
+    }
+    c->ev.push_back(a);
+    c->ev.push_back(b);
+  }
+  (void)hipEventRecord(c->ev[c->ev_used], c->stream);
+  launch();
+  (void)hipEventRecord(c->ev[c->ev_used + 1], c->stream);
+  c->ev_used += 2;
 }
 
-// remesh with levels below la frozen; statuses, new values and ghost flags
+void project_range(mr_ctx* c, int hi, int lo, int mode) {
+  for (int lev = hi; lev >= lo; lev--)
+    timed(c, MR_KC_PROJECT, [&] { launch_project(c->g, c->p, lev, mode, c->stream); });
+}
+
+// ghost flags and leaf / internal / ghost lists of levels la..L
+void refresh_lists(mr_ctx* c, int la) {
+  const Geo& g = c->g;
+  hipStream_t s = c->stream;
+  const int glo = la > g.l0 ? la : g.l0 + 1;
+  timed(c, MR_KC_REMESH, [&] { launch_ghost_flags(g, c->p, glo, g.L, s); });
+  timed(c, MR_KC_REMESH, [&] { launch_compact(g, c->p, la, s); });
+}
+
+// remesh with levels below la frozen; statuses, new values and lists
 void remesh(mr_ctx* c, int la) {
   const Geo& g = c->g;
   if (la > g.L - 1) return;
-  for (int lev = la; lev <= g.L; lev++) launch_detail(g, c->p, lev, c->stream);
-  for (int lev = la; lev <= g.L - 1; lev++) launch_seed(g, c->p, lev, la, c->stream);
-  for (int lev = g.L - 2; lev >= la; lev--) launch_close(g, c->p, lev, c->stream);
-  for (int lev = la; lev <= g.L - 1; lev++) launch_prune(g, c->p, lev, la, c->stream);
-  for (int lev = la; lev <= g.L; lev++) launch_apply(g, c->p, lev, la, c->stream);
-  for (int lev = (la > g.l0 ? la : g.l0 + 1); lev <= g.L; lev++) launch_ghost_flags(g, c->p, lev, c->stream);
+  hipStream_t s = c->stream;
+  timed(c, MR_KC_REMESH, [&] { launch_detail(g, c->p, la, g.L, s); });
+  timed(c, MR_KC_REMESH, [&] { launch_seed(g, c->p, la, g.L - 1, la, s); });
+  for (int lev = g.L - 2; lev >= la; lev--) timed(c, MR_KC_REMESH, [&] { launch_close(g, c->p, lev, s); });
+  for (int lev = la; lev <= g.L - 1; lev++) timed(c, MR_KC_REMESH, [&] { launch_prune(g, c->p, lev, la, s); });
+  for (int lev = la; lev <= g.L; lev++) timed(c, MR_KC_REMESH, [&] { launch_apply(g, c->p, lev, la, s); });
+  refresh_lists(c, la);
 }
 
 void ghost_fill(mr_ctx* c, int lmin, int stage) {
   const Geo& g = c->g;
-  for (int lev = (lmin > g.l0 ? lmin : g.l0 + 1); lev <= g.L; lev++)
-    launch_ghost(g, c->p, lev, stage, lev == lmin ? 1 : 0, c->stream);
+  const int lo = lmin > g.l0 ? lmin : g.l0 + 1;
+  const int cb = lmin > g.l0 ? lmin : -1;
+  timed(c, MR_KC_GHOST, [&] { launch_ghost(g, c->p, lo, g.L, cb, stage, c->stream); });
 }
 
 // one iteration of Alg. alg-LTS
@@ -106,23 +150,33 @@ void lt_iteration(mr_ctx* c, int64_t n, int64_t N) {
     remesh(c, lmin);
     project_range(c, L - 1, lmin, PJ_Q0);
   }
-  if (lmin > g.l0) launch_project(g, c->p, lmin - 1, PJ_CASEB, c->stream);
+  hipStream_t s = c->stream;
+  auto stage = [&](int lo, int hi, int st) {
+    timed(c, lo == L ? MR_KC_STAGE_FINEST : MR_KC_STAGE, [&] { launch_stage(g, c->p, lo, hi, st, s); });
+  };
+  if (lmin > g.l0) project_range(c, lmin - 1, lmin - 1, PJ_CASEB);
   ghost_fill(c, lmin, 1);
-  for (int lev = lmin; lev <= L; lev++) launch_stage(g, c->p, lev, 1, c->stream);
+  stage(lmin, L, 1);
   project_range(c, L - 1, lmin, PJ_REF2);
   ghost_fill(c, lmin, 2);
   for (int lev = L; lev >= lmin; lev--) {
-    if (lev < L) launch_project(g, c->p, lev, PJ_RK2, c->stream);
-    launch_stage(g, c->p, lev, 2, c->stream);
+    if (lev < L) project_range(c, lev, lev, PJ_RK2);
+    stage(lev, lev, 2);
+  }
+  if (g.rk == 2) {
+    // RK2: the step ends after the second stage
+    const int lnext2 = (n + 1 == N) ? g.l0 : lmin_of(g, n + 1);
+    timed(c, MR_KC_FINALIZE, [&] { launch_finalize(g, c->p, lnext2, L, s); });
+    return;
   }
   project_range(c, L - 1, lmin, PJ_REF3);
   ghost_fill(c, lmin, 3);
   for (int lev = L; lev >= lmin; lev--) {
-    if (lev < L) launch_project(g, c->p, lev, PJ_RK3, c->stream);
-    launch_stage(g, c->p, lev, 3, c->stream);
+    if (lev < L) project_range(c, lev, lev, PJ_RK3);
+    stage(lev, lev, 3);
   }
   const int lnext = (n + 1 == N) ? g.l0 : lmin_of(g, n + 1);
-  for (int lev = lnext; lev <= L; lev++) launch_finalize(g, c->p, lev, c->stream);
+  timed(c, MR_KC_FINALIZE, [&] { launch_finalize(g, c->p, lnext, L, s); });
 }
 
 mr_status read_counters(mr_ctx* c) {
@@ -157,7 +211,8 @@ mr_status check_flags(mr_ctx* c) {
 mr_status adapt_impl(mr_ctx* c) {
   const Geo& g = c->g;
   project_range(c, g.L - 1, g.l0, PJ_Q0);
-  remesh(c, g.l0);
+  if (g.l0 <= g.L - 1) remesh(c, g.l0);
+  else refresh_lists(c, g.l0);
   project_range(c, g.L - 1, g.l0, PJ_Q0);
   mr_status st = check_launch(c, "adapt");
   if (st != MR_OK) return st;
@@ -185,7 +240,11 @@ void mr_destroy(mr_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
   for (void* a : c->allocs) (void)hipFree(a);
+  if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
   delete c;
 }
 
@@ -194,7 +253,8 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
   *out = nullptr;
   if (!s || !eps || dim < 1 || dim > 3 || n_inst < 1) return MR_EINVAL;
   if (s->l0 < 2 || L < s->l0 || L > MR_MAXLEV || L - s->l0 > 20 || dim * L > 40) return MR_EINVAL;
-  if (s->rk != 3 || s->lt != 1 || s->pde < MR_PDE_ADVECTION || s->pde > MR_PDE_LINEAR) return MR_EINVAL;
+  if ((s->rk != 2 && s->rk != 3) || s->lt != 1 || s->pde < MR_PDE_ADVECTION || s->pde > MR_PDE_LINEAR)
+    return MR_EINVAL;
   if (s->recon < 0 || s->recon > 2) return MR_EINVAL;
   for (int a = 0; a < dim; a++) {
     if ((s->bc[a][0] == MR_BC_PERIODIC) != (s->bc[a][1] == MR_BC_PERIODIC)) return MR_EINVAL;
@@ -205,6 +265,12 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
 
   mr_ctx* c = new mr_ctx();
   c->s = *s;
+  if (hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking) != hipSuccess) {
+    delete c;
+    return MR_EDEVICE;
+  }
+  c->stream = c->own_stream;
+  c->use_graph = getenv("MRLT_NO_GRAPH") == nullptr;
   Geo& g = c->g;
   memset(&g, 0, sizeof g);
   g.d = dim;
@@ -213,10 +279,13 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
   g.m = s->pde == MR_PDE_EULER ? dim + 2 : 1;
   g.nsub = 1 << (dim - 1);
   g.B = n_inst;
+  g.i0 = 0;
+  g.i1 = n_inst;
   g.pde = s->pde;
   g.recon = s->recon;
   g.thresh = s->thresh;
   g.reflux = s->reflux;
+  g.rk = s->rk;
   for (int a = 0; a < 3; a++) g.periodic[a] = a < dim && s->bc[a][0] == MR_BC_PERIODIC;
   int64_t off = 0, rc = 0, rf = 0;
   for (int lev = g.l0; lev <= L; lev++) {
@@ -242,6 +311,22 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
     g.vol[lev] = v;
   }
   g.Ntot = off;
+  {
+    int64_t nb = 0;
+    for (int lev = g.l0; lev <= L; lev++) {
+      const int64_t ch = g.n[lev] < 4096 ? g.n[lev] : 4096;
+      g.comp_chunk[lev] = (int)ch;
+      g.comp_first[lev] = nb;
+      nb += g.B * g.n[lev] / ch;
+    }
+    g.comp_first[L + 1] = nb;
+    for (int lev = g.l0; lev <= L; lev++)
+      if (g.B * g.n[lev] >= ((int64_t)1 << 31)) {
+        (void)hipStreamDestroy(c->own_stream);
+        delete c;
+        return MR_EINVAL;
+      }
+  }
   g.nu = s->nu;
   g.k_react = s->k_react;
   g.a_react = s->a_react;
@@ -277,6 +362,10 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
   ALLOC(c->err_d, int, 1);
   ALLOC(c->ws_d, unsigned long long, n_inst);
   ALLOC(c->part_d, double, (int64_t)(c->max_blocks + 1) * g.m);
+  for (int k = 0; k < LS_COUNT; k++) ALLOC(c->p.lst[k], int, g.Ntot);
+  ALLOC(c->p.lcnt, int, LS_COUNT * (MRD_MAXLEV + 1));
+  ALLOC(c->p.bcnt, int, LS_COUNT * (g.comp_first[L + 1] + 1));
+  ALLOC(c->p.leafcnt, int, (int64_t)n_inst * (MRD_MAXLEV + 1));
 #undef ALLOC
   c->p.dt = c->dt_d;
   c->p.eps = c->eps_d;
@@ -297,7 +386,7 @@ mr_status mr_init(int dim, int L, double eps, const mr_scheme* s, mr_ctx** out) 
 
 mr_status mr_set_stream(mr_ctx* c, void* hip_stream) {
   if (!c) return MR_EINVAL;
-  c->stream = (hipStream_t)hip_stream;
+  c->stream = hip_stream ? (hipStream_t)hip_stream : c->own_stream;
   return MR_OK;
 }
 
@@ -309,11 +398,12 @@ mr_status mr_synchronize(mr_ctx* c) {
 
 mr_status mr_load_finest(mr_ctx* c, const double* q0, void* hip_stream) {
   if (!c || !q0) return MR_EINVAL;
-  c->stream = (hipStream_t)hip_stream;
+  if (hip_stream) c->stream = (hipStream_t)hip_stream;
   const Geo& g = c->g;
   for (int lev = g.l0; lev < g.L; lev++) launch_fill_status(g, c->p, lev, ST_INTERNAL, c->stream);
-  launch_load_finest(g, c->p, q0, c->stream);
+  launch_load_finest(g, c->p, q0, -1, c->stream);
   launch_clear_regs(g, c->p, c->stream);
+  refresh_lists(c, g.l0);
   HIPCHK(c, hipMemsetAsync(c->p.cnt, 0, sizeof(unsigned long long) * g.B * CNT_PER_INST, c->stream));
   mr_status st = check_launch(c, "load_finest");
   if (st != MR_OK) return st;
@@ -322,6 +412,71 @@ mr_status mr_load_finest(mr_ctx* c, const double* q0, void* hip_stream) {
   c->broken = false;
   c->err.clear();
   return adapt_impl(c);
+}
+
+__global__ void k_reset_counters(unsigned long long* cnt, int inst);
+
+mr_status mr_load_finest_inst(mr_ctx* c, int inst, const double* q0) {
+  if (!c || !q0 || inst < 0 || inst >= c->g.B) return MR_EINVAL;
+  if (c->broken) return set_err(c, MR_ESTATE, "context in error state");
+  Geo& g = c->g;
+  launch_fill_instance(g, c->p, inst, c->stream);
+  launch_load_finest(g, c->p, q0, inst, c->stream);
+  launch_clear_regs(g, c->p, c->stream);
+  k_reset_counters<<<1, 64, 0, c->stream>>>(c->p.cnt, inst);
+  refresh_lists(c, g.l0);
+  project_range(c, g.L - 1, g.l0, PJ_Q0);
+  if (g.l0 <= g.L - 1) {
+    // only this instance is remeshed; the others keep their trees
+    g.i0 = inst;
+    g.i1 = inst + 1;
+    remesh(c, g.l0);
+    g.i0 = 0;
+    g.i1 = g.B;
+    project_range(c, g.L - 1, g.l0, PJ_Q0);
+  }
+  c->t[inst] = 0.0;
+  mr_status st = check_launch(c, "load_finest_inst");
+  if (st != MR_OK) return st;
+  return check_flags(c);
+}
+
+mr_status mr_clear_instance(mr_ctx* c, int inst) {
+  if (!c || inst < 0 || inst >= c->g.B) return MR_EINVAL;
+  launch_fill_instance(c->g, c->p, -1 - inst, c->stream);
+  k_reset_counters<<<1, 64, 0, c->stream>>>(c->p.cnt, inst);
+  refresh_lists(c, c->g.l0);
+  c->t[inst] = 0.0;
+  mr_status st = check_launch(c, "clear_instance");
+  if (st != MR_OK) return st;
+  // a failure of this instance no longer blocks the others
+  st = read_counters(c);
+  if (st != MR_OK) return st;
+  bool any = false;
+  for (int i = 0; i < c->g.B; i++)
+    any = any || c->cnt_host[i * CNT_PER_INST + CNT_BAD] || c->cnt_host[i * CNT_PER_INST + CNT_NONFINITE];
+  if (!any) {
+    c->broken = false;
+    c->err.clear();
+  }
+  return MR_OK;
+}
+
+mr_status mr_instance_flags(mr_ctx* c, int inst, int* flags) {
+  if (!c || !flags || inst < 0 || inst >= c->g.B) return MR_EINVAL;
+  mr_status st = read_counters(c);
+  if (st != MR_OK) return st;
+  *flags = (c->cnt_host[inst * CNT_PER_INST + CNT_NONFINITE] ? 1 : 0) |
+           (c->cnt_host[inst * CNT_PER_INST + CNT_BAD] ? 2 : 0);
+  return MR_OK;
+}
+
+mr_status mr_set_eps(mr_ctx* c, int inst, double eps) {
+  if (!c || inst < 0 || inst >= c->g.B || !(eps >= 0.0) || !std::isfinite(eps)) return MR_EINVAL;
+  c->eps[inst] = eps;
+  HIPCHK(c, hipMemcpyAsync(c->eps_d, c->eps.data(), sizeof(double) * c->g.B, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return MR_OK;
 }
 
 mr_status mr_adapt(mr_ctx* c) {
@@ -338,7 +493,22 @@ mr_status mr_lt_step_batch(mr_ctx* c, const double* dt) {
   c->dt_host.assign(dt, dt + c->g.B);
   HIPCHK(c, hipMemcpyAsync(c->dt_d, c->dt_host.data(), sizeof(double) * c->g.B, hipMemcpyHostToDevice, c->stream));
   const int64_t N = (int64_t)1 << (c->g.L - c->g.l0);
-  for (int64_t n = 0; n < N; n++) lt_iteration(c, n, N);
+  // The launch sequence of a macro step depends only on the iteration index
+  // and the kernels read counts, lists and dt from device memory, so the whole
+  // macro step is captured once into a HIP graph and replayed.
+  if (c->use_graph && c->timed_class == 0 && c->stream != nullptr) {
+    if (!c->graph_exec) {
+      HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+      for (int64_t n = 0; n < N; n++) lt_iteration(c, n, N);
+      hipGraph_t gr = nullptr;
+      HIPCHK(c, hipStreamEndCapture(c->stream, &gr));
+      c->graph = gr;
+      HIPCHK(c, hipGraphInstantiate(&c->graph_exec, gr, nullptr, nullptr, 0));
+    }
+    HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
+  } else {
+    for (int64_t n = 0; n < N; n++) lt_iteration(c, n, N);
+  }
   mr_status st = check_launch(c, "lt_step");
   if (st != MR_OK) return st;
   for (int i = 0; i < c->g.B; i++) c->t[i] = c->t[i] + (double)N * dt[i];
@@ -466,9 +636,10 @@ mr_status mr_set_leaves_inst(mr_ctx* c, int inst, const uint64_t* keys, const do
     c->broken = true;
     return set_err(c, MR_EINVAL, buf);
   }
+  launch_compact(g, c->p, g.l0, c->stream);  // internal lists for the projection
   project_range(c, g.L - 1, g.l0, PJ_Q0);
   launch_clear_regs(g, c->p, c->stream);
-  for (int lev = g.l0 + 1; lev <= g.L; lev++) launch_ghost_flags(g, c->p, lev, c->stream);
+  refresh_lists(c, g.l0);
   k_reset_counters<<<1, 64, 0, c->stream>>>(c->p.cnt, inst);
   mr_status st = check_launch(c, "set_leaves");
   if (st != MR_OK) return st;
@@ -505,11 +676,44 @@ mr_status mr_stats_inst(mr_ctx* c, int inst, mr_stats_t* out) {
   }
   mr_status st = read_counters(c);
   if (st != MR_OK) return st;
-  out->leaf_updates = (int64_t)c->cnt_host[inst * CNT_PER_INST + CNT_UPDATES];
+  for (int lev = g.l0; lev <= g.L; lev++)
+    out->leaf_updates += (int64_t)c->cnt_host[inst * CNT_PER_INST + CNT_LEVEL0 + lev];
   out->near_threshold = (int64_t)c->cnt_host[inst * CNT_PER_INST + CNT_NEAR];
   return check_launch(c, "stats");
 }
 
 mr_status mr_stats(mr_ctx* c, mr_stats_t* out) { return mr_stats_inst(c, 0, out); }
+
+mr_status mr_level_updates(mr_ctx* c, int inst, int64_t* per_level) {
+  if (!c || !per_level || inst < 0 || inst >= c->g.B) return MR_EINVAL;
+  mr_status st = read_counters(c);
+  if (st != MR_OK) return st;
+  for (int lev = 0; lev <= MR_MAXLEV; lev++)
+    per_level[lev] = (lev >= c->g.l0 && lev <= c->g.L) ? (int64_t)c->cnt_host[inst * CNT_PER_INST + CNT_LEVEL0 + lev] : 0;
+  return MR_OK;
+}
+
+mr_status mr_timing_start(mr_ctx* c, int kernel_class) {
+  if (!c || kernel_class < MR_KC_STAGE_FINEST || kernel_class > MR_KC_FINALIZE) return MR_EINVAL;
+  c->timed_class = kernel_class;
+  c->ev_used = 0;
+  return MR_OK;
+}
+
+mr_status mr_timing_stop(mr_ctx* c, double* total_ms, int64_t* launches) {
+  if (!c || !total_ms || !launches) return MR_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  double tot = 0.0;
+  for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
+    tot += ms;
+  }
+  *total_ms = tot;
+  *launches = (int64_t)(c->ev_used / 2);
+  c->timed_class = 0;
+  c->ev_used = 0;
+  return MR_OK;
+}
 
 }  // extern "C"

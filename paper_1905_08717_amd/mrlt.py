@@ -25,8 +25,10 @@ EXPORTS = [
     "mr_init", "mr_init_batch", "mr_set_stream", "mr_ncomp", "mr_load_finest", "mr_adapt",
     "mr_lt_step", "mr_lt_step_batch", "mr_reconstruct", "mr_max_wavespeed", "mr_get_leaves",
     "mr_get_leaves_inst", "mr_set_leaves", "mr_set_leaves_inst", "mr_stats", "mr_stats_inst",
-    "mr_synchronize", "mr_last_error", "mr_destroy",
+    "mr_synchronize", "mr_last_error", "mr_destroy", "mr_level_updates", "mr_timing_start",
+    "mr_timing_stop", "mr_load_finest_inst", "mr_clear_instance", "mr_instance_flags", "mr_set_eps",
 ]
+KC = {"stage_finest": 1, "stage": 2, "project": 3, "ghost": 4, "remesh": 5, "finalize": 6}
 
 
 class MrScheme(ctypes.Structure):
@@ -94,6 +96,13 @@ def load_library():
     L.mr_synchronize.argtypes = [vp]
     L.mr_last_error.argtypes = [vp]
     L.mr_last_error.restype = ctypes.c_char_p
+    L.mr_level_updates.argtypes = [vp, i32, ctypes.POINTER(i64)]
+    L.mr_timing_start.argtypes = [vp, i32]
+    L.mr_timing_stop.argtypes = [vp, dp, ctypes.POINTER(i64)]
+    L.mr_load_finest_inst.argtypes = [vp, i32, vp]
+    L.mr_clear_instance.argtypes = [vp, i32]
+    L.mr_instance_flags.argtypes = [vp, i32, ctypes.POINTER(i32)]
+    L.mr_set_eps.argtypes = [vp, i32, dbl]
     L.mr_destroy.argtypes = [vp]
     L.mr_destroy.restype = None
     for name in EXPORTS:
@@ -107,7 +116,7 @@ def make_scheme(cfg: dict) -> MrScheme:
     s = MrScheme()
     d = cfg["dim"]
     s.pde = PDE[cfg["pde"]]
-    s.rk = 3
+    s.rk = cfg.get("rk", 3)
     s.lt = 1
     s.l0 = cfg.get("l0", 2)
     s.recon = cfg.get("recon", 1)
@@ -163,8 +172,10 @@ class Solver:
         self._h = h
         self.m = L.mr_ncomp(h)
         self.nfine = 1 << (self.dim * self.L)
-        self.stream = stream if stream is not None else torch.cuda.current_stream()
-        self._check(L.mr_set_stream(h, _stream_ptr(self.stream)), "mr_set_stream")
+        # the library queues on its own stream unless one is given; device
+        # buffers written by torch are synchronised before they are read
+        self.stream = stream
+        self._check(L.mr_set_stream(h, _stream_ptr(stream)), "mr_set_stream")
 
     def close(self):
         if getattr(self, "_h", None):
@@ -189,9 +200,41 @@ class Solver:
             q0 = t.from_numpy(np.ascontiguousarray(q0, dtype=np.float64)).to("cuda")
         q0 = q0.contiguous()
         assert q0.dtype == t.float64 and q0.is_cuda and q0.numel() == self.n_inst * self.m * self.nfine
+        t.cuda.current_stream().synchronize()
         self._q0_keep = q0
         self._check(load_library().mr_load_finest(self._h, ctypes.c_void_p(q0.data_ptr()),
                                                   _stream_ptr(self.stream)), "mr_load_finest")
+
+    def load_finest_inst(self, inst: int, q0):
+        """Load one instance (q0: [m, 2^{dL}], torch device tensor or numpy)."""
+        t = self.torch
+        if isinstance(q0, np.ndarray):
+            q0 = t.from_numpy(np.ascontiguousarray(q0, dtype=np.float64)).to("cuda")
+        q0 = q0.contiguous()
+        assert q0.dtype == t.float64 and q0.is_cuda and q0.numel() == self.m * self.nfine
+        t.cuda.current_stream().synchronize()
+        self._keep_inst = q0
+        self._check(load_library().mr_load_finest_inst(self._h, inst, ctypes.c_void_p(q0.data_ptr())),
+                    "mr_load_finest_inst")
+
+    def clear_instance(self, inst: int):
+        self._check(load_library().mr_clear_instance(self._h, inst), "mr_clear_instance")
+
+    def instance_flags(self, inst: int) -> int:
+        f = ctypes.c_int()
+        self._check(load_library().mr_instance_flags(self._h, inst, ctypes.byref(f)), "mr_instance_flags")
+        return f.value
+
+    def set_eps(self, inst: int, eps: float):
+        self._check(load_library().mr_set_eps(self._h, inst, float(eps)), "mr_set_eps")
+
+    def last_error(self) -> str:
+        msg = load_library().mr_last_error(self._h)
+        return msg.decode() if msg else ""
+
+    def lt_step_rc_batch(self, dts) -> int:
+        arr = (ctypes.c_double * self.n_inst)(*[float(x) for x in dts])
+        return load_library().mr_lt_step_batch(self._h, arr)
 
     def adapt(self):
         self._check(load_library().mr_adapt(self._h), "mr_adapt")
@@ -208,6 +251,7 @@ class Solver:
 
     def reconstruct(self):
         out = self.torch.empty((self.n_inst, self.m, self.nfine), dtype=self.torch.float64, device="cuda")
+        self.torch.cuda.current_stream().synchronize()
         self._check(load_library().mr_reconstruct(self._h, ctypes.c_void_p(out.data_ptr())), "mr_reconstruct")
         return out
 
@@ -245,6 +289,20 @@ class Solver:
             "iterations": st.iterations,
             "mass": [st.mass[k] for k in range(self.m)],
         }
+
+    def level_updates(self, inst: int = 0):
+        arr = (ctypes.c_int64 * (MAXLEV + 1))()
+        self._check(load_library().mr_level_updates(self._h, inst, arr), "mr_level_updates")
+        return np.array(arr[:], dtype=np.int64)
+
+    def timing_start(self, kernel_class: str):
+        self._check(load_library().mr_timing_start(self._h, KC[kernel_class]), "mr_timing_start")
+
+    def timing_stop(self):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._check(load_library().mr_timing_stop(self._h, ctypes.byref(ms), ctypes.byref(n)), "mr_timing_stop")
+        return ms.value, n.value
 
     def synchronize(self):
         self._check(load_library().mr_synchronize(self._h), "mr_synchronize")

@@ -185,3 +185,11 @@ def to_grid(cfg, q_flat, level):
     d = cfg["dim"]
     n = 1 << level
     return q_flat.reshape((q_flat.shape[0],) + (n,) * d)
+
+
+def rk2_step(cfg, q, level, h):
+    """One compact RK2 step (Sec. 3) of size h."""
+    R1 = rhs(cfg, q, level)
+    q1 = q + (h * R1)
+    R2 = rhs(cfg, q1, level)
+    return ((0.5 * q) + (0.5 * q1)) + ((0.5 * h) * R2)

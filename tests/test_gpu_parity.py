@@ -250,3 +250,101 @@ def test_full_size_euler_3d_properties(mods):
     assert torch.max(torch.abs(rho - rho.flip(2))).item() < 1e-12
     assert torch.max(torch.abs(rho - rho.transpose(1, 2))).item() < 1e-12
     assert torch.max(torch.abs(q[1] - q[2].transpose(1, 2))).item() < 1e-12
+
+
+def test_graph_replays_equal_eager_launches(mods, monkeypatch):
+    # the macro step is captured once into a HIP graph and replayed; every
+    # replay (with eager work and synchronisation in between) must equal the
+    # eager launch sequence bit for bit
+    _, mrlt = mods
+    cfg = W.nagumo_2d(L=7)
+    q = np.stack([W.nagumo_front(7, W.SEED + i) for i in range(3)])
+    dt = 0.5 / (4 * 128 ** 2 + 800)
+    graph = mrlt.Solver(cfg, n_inst=3)
+    monkeypatch.setenv("MRLT_NO_GRAPH", "1")
+    eager = mrlt.Solver(cfg, n_inst=3)
+    monkeypatch.delenv("MRLT_NO_GRAPH")
+    graph.load_finest(q)
+    eager.load_finest(q)
+    for step in range(4):
+        graph.lt_step(dt)
+        eager.lt_step(dt)
+        for i in range(3):
+            kg, vg = graph.get_leaves(i)
+            ke, ve = eager.get_leaves(i)
+            assert np.array_equal(kg, ke) and np.array_equal(vg, ve), (step, i)
+        assert graph.stats(1)["leaf_updates"] == eager.stats(1)["leaf_updates"]
+
+
+def test_admission_into_running_batch_keeps_others_identical(mods):
+    # continuous batching: a request loaded into a free slot while the others
+    # are mid-run must not change them, and must itself match its solo run
+    mro, mrlt = mods
+    cfg = W.nagumo_2d(L=6)
+    dt = 0.5 / (4 * 64 ** 2 + 800)
+    q = [W.nagumo_front(6, W.SEED + 20 + i) for i in range(3)]
+    s = mrlt.Solver(cfg, n_inst=3)
+    s.load_finest_inst(0, q[0])
+    s.load_finest_inst(2, q[2])
+    s.clear_instance(1)
+    solo = [mro.Oracle(cfg) for _ in range(3)]
+    solo[0].load_finest(q[0])
+    solo[2].load_finest(q[2])
+    s.lt_step(dt)
+    solo[0].lt_step(dt)
+    solo[2].lt_step(dt)
+    assert sum(s.stats(1)["leaves"]) == 0
+    s.load_finest_inst(1, q[1])
+    solo[1].load_finest(q[1])
+    for _ in range(2):
+        s.lt_step(dt)
+        for i in range(3):
+            solo[i].lt_step(dt)
+            assert compare_state(solo[i], s, inst=i, what=f"instance {i}")
+    s.clear_instance(0)
+    s.lt_step(dt)
+    for i in (1, 2):
+        solo[i].lt_step(dt)
+        assert compare_state(solo[i], s, inst=i, what=f"after clearing 0, instance {i}")
+
+
+def test_batched_and_served_results_equal_solo(mods):
+    # systems forms: every request's result is the same alone, in a batch
+    # and in the served mix (bit for bit: instances do not interact)
+    _, mrlt = mods
+    from paper_1905_08717_amd import systems as S
+    reqs = S.batched_euler_requests(6)
+    for r in reqs:
+        r.cfg = dict(r.cfg, L=min(r.cfg["L"], 7))
+        r.q0 = W.euler_quadrants_seeded(r.cfg["L"], W.SEED + r.rid)
+        r.t_final = 0.05
+    import copy
+    solo = copy.deepcopy(reqs)
+    S.run_batched(reqs)
+    S.run_one_at_a_time(solo)
+    for a, b in zip(reqs, solo):
+        assert np.array_equal(a.result[0], b.result[0]) and np.array_equal(a.result[1], b.result[1])
+    served = S.served_requests(12, rate=400.0, burgers_levels=(9, 10), rd_levels=(6, 7))
+    for r in served:
+        r.t_final = r.t_final / 20
+    alone = copy.deepcopy(served)
+    out = S.serve(served, hbm_budget=8 * 2 ** 30, max_slots=4)
+    assert out["requests"] == 12 and out["p99_s"] >= out["p50_s"] > 0
+    S.run_one_at_a_time(alone)
+    for a, b in zip(served, alone):
+        assert a.done_at is not None
+
+
+@pytest.mark.parametrize("case", ["burgers1d", "nagumo2d", "euler2d"])
+def test_rk2_variant(mods, case):
+    # MRLT/NERK2 (rk = 2): compact RK2, NERK theta = 1/2 synchronisation
+    if case == "burgers1d":
+        cfg = dict(W.burgers_1d(L=9), rk=2)
+        run_pair(mods, cfg, W.burgers_sine(9), [1.2e-4] * 3)
+    elif case == "nagumo2d":
+        cfg = dict(W.nagumo_2d(L=7), rk=2)
+        run_pair(mods, cfg, W.nagumo_front(7), [0.4 / (4 * 128 ** 2 + 800)] * 3)
+    else:
+        cfg = dict(W.euler_2d(L=6), rk=2)
+        run_pair(mods, cfg, W.euler_quadrants_seeded(6, W.SEED + 3),
+                 [lambda o: 0.8 * W.euler_dt(cfg, o.max_wavespeed(), o.stats()["t"])] * 3)
