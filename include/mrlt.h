@@ -59,7 +59,8 @@ enum { MR_BC_PERIODIC = 0, MR_BC_NEUMANN = 1 };
  *          (m=1, -nu grad u, source k u)
  *  rk      3 (MRLT/NERK3: compact RK3 with NERK partials at theta 1/4, 3/4)
  *          or 2 (MRLT/NERK2: compact RK2 with the NERK theta = 1/2 value), Sec. 3
- *  lt      1 (local time stepping, Sec. 4)
+ *  lt      1: local time stepping (MRLT, Sec. 4); 0: one global step dt_L
+ *          for every level (the MR comparison scheme)
  *  l0      coarsest level, >= 2
  *  recon   0 first order, 1 MUSCL-minmod, 2 centred (advection only)
  *  thresh  1: eps_l = 2^{d(l-L)} eps for details of level l, 0: fixed eps

@@ -213,6 +213,11 @@ static int slot_own(int st, int stage) {
  * projection of internal nodes (Alg. alg-LTS); S2 the end value of leaves or
  * the end value of Sec. 4.3 of internal nodes; S3 theta=3/4 (Alg. refRK22). */
 static int slot_parent(const mro_ctx* c, int p, int st, int stage) {
+  if (!c->s.lt) {
+    /* global time step (the MR/RK comparison scheme): every level is at
+     * the same stage time, internal nodes hold the children's projection */
+    return slot_own(st, stage);
+  }
   if (p >= c->lmin) {
     if (stage == 1) return S_Q0;
     if (stage == 2) return S_H1;
@@ -301,6 +306,11 @@ static void finer_value(mro_ctx* c, int flev, const int* y, int stage, double* o
   if (st == ABSENT) {
     fail(c, "finer-side cell missing at level %d", flev);
     for (int k = 0; k < c->m; k++) out[k] = 0.0;
+    return;
+  }
+  if (!c->s.lt) {
+    int sl = slot_own(st, stage);
+    for (int k = 0; k < c->m; k++) out[k] = SL(c, flev, sl, k, i);
     return;
   }
   for (int k = 0; k < c->m; k++) {
@@ -554,7 +564,7 @@ static int leaf_face_flux(mro_ctx* c, int lev, const int* x, int dir, int side, 
 static void stage_level(mro_ctx* c, int lev, int stage) {
   int d = c->d, m = c->m;
   level_t* LV = &c->lv[lev];
-  double h = ldexp(c->dt, c->L - lev); /* eq. dt */
+  double h = c->s.lt ? ldexp(c->dt, c->L - lev) : c->dt; /* eq. dt; global step without LT */
   /* weights b_i of the RK method (Sec. 3): RK3 (1/6, 1/6, 2/3), RK2 (1/2, 1/2) */
   double w = c->s.rk == 2 ? C_HALF : (stage == 3 ? C_2_3 : C_1_6);
   double wh = w * h;
@@ -689,6 +699,26 @@ static void cv_x2(mro_ctx* c, int f, int64_t j, int k, double* v) {
 }
 static void cv_qh(mro_ctx* c, int f, int64_t j, int k, double* v) { *v = SL(c, f, S_QH, k, j); }
 static void cv_qe(mro_ctx* c, int f, int64_t j, int k, double* v) { *v = SL(c, f, S_QE, k, j); }
+
+static void cv_q1(mro_ctx* c, int f, int64_t j, int k, double* v) {
+  *v = c->lv[f].st[j] == LEAF ? SL(c, f, S_Q1, k, j) : SL(c, f, S_Q1SW, k, j);
+}
+
+/* Global time step: internal stage states are the projections of the
+ * children's stage states (the MR scheme of Sec. 2 at one time). */
+static void project_stage(mro_ctx* c, int stage) {
+  for (int lev = c->L - 1; lev >= c->l0; lev--) {
+    level_t* LV = &c->lv[lev];
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < LV->ncell; i++) {
+      if (LV->st[i] != INTERNAL) continue;
+      for (int k = 0; k < c->m; k++) {
+        if (stage == 2) SL(c, lev, S_Q1SW, k, i) = project_children(c, lev, i, k, cv_q1);
+        else SL(c, lev, S_QH, k, i) = project_children(c, lev, i, k, cv_qh);
+      }
+    }
+  }
+}
 
 /* Alg. alg-LTS first loop: internal q^n = mean of children. */
 static void project_q0(mro_ctx* c, int lev_hi, int lev_lo) {
@@ -1045,8 +1075,40 @@ static int lmin_of(const mro_ctx* c, int64_t n) {
   return c->L;
 }
 
+/* One iteration of the MR scheme with a global time step (the comparison
+ * method of the paper): all leaves advance by dt, remesh every step. */
+static void mr_iteration(mro_ctx* c) {
+  int L = c->L;
+  c->lmin = c->l0;
+  project_q0(c, L - 1, c->l0);
+  if (c->s.remesh) {
+    remesh(c, c->l0);
+    project_q0(c, L - 1, c->l0);
+  }
+  for (int lev = c->l0; lev <= L; lev++) {
+    int64_t nl = 0;
+    for (int64_t i = 0; i < c->lv[lev].ncell; i++) nl += c->lv[lev].st[i] == LEAF;
+    c->leaf_updates += nl;
+  }
+  for (int lev = c->l0; lev <= L; lev++) stage_level(c, lev, 1);
+  project_stage(c, 2);
+  for (int lev = c->l0; lev <= L; lev++) stage_level(c, lev, 2);
+  if (c->s.rk == 3) {
+    project_stage(c, 3);
+    for (int lev = c->l0; lev <= L; lev++) stage_level(c, lev, 3);
+  }
+  finalize(c, c->l0);
+  c->iters++;
+}
+
 static void lt_iteration(mro_ctx* c, int64_t n, int64_t N) {
   int L = c->L;
+  if (!c->s.lt) {
+    (void)n;
+    (void)N;
+    mr_iteration(c);
+    return;
+  }
   int lmin = lmin_of(c, n);
   c->lmin = lmin;
   project_q0(c, L - 1, lmin);
@@ -1105,7 +1167,8 @@ int mro_init(int dim, int L, double eps, const mro_scheme* s, mro_ctx** out) {
   *out = NULL;
   if (dim < 1 || dim > 3 || !(eps >= 0.0)) return MRO_EINVAL;
   if (s->l0 < 2 || L < s->l0 || L > MRO_MAXLEV || (int64_t)dim * L > 40) return MRO_EINVAL;
-  if ((s->rk != 2 && s->rk != 3) || s->lt != 1 || s->pde < 0 || s->pde > MRO_PDE_LINEAR) return MRO_EINVAL;
+  if ((s->rk != 2 && s->rk != 3) || (s->lt != 0 && s->lt != 1) || s->pde < 0 || s->pde > MRO_PDE_LINEAR)
+    return MRO_EINVAL;
   if (L - s->l0 > 20) return MRO_EINVAL;
   for (int a = 0; a < dim; a++) {
     if ((s->bc[a][0] == MRO_BC_PERIODIC) != (s->bc[a][1] == MRO_BC_PERIODIC)) return MRO_EINVAL;

@@ -33,7 +33,7 @@ enum { MRO_BC_PERIODIC = 0, MRO_BC_NEUMANN = 1 };
 typedef struct {
   int32_t pde;        /* MRO_PDE_* */
   int32_t rk;         /* 3 (MRLT/NERK3) or 2 (MRLT/NERK2) */
-  int32_t lt;         /* 1 only: local time stepping */
+  int32_t lt;         /* 1 local time stepping (MRLT), 0 global step (MR) */
   int32_t l0;         /* coarsest level */
   int32_t recon;      /* 0 first order, 1 MUSCL-minmod, 2 centred (advection) */
   int32_t thresh;     /* 1 level-dependent eps_l = 2^{d(l-L)} eps, 0 fixed */

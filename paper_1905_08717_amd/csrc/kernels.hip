@@ -441,13 +441,18 @@ __global__ __launch_bounds__(TPB) void k_project(Geo g, Dev p, int lev, int mode
         if (mode == PJ_Q0 || mode == PJ_CASEB) v = p.q[SL_Q0][C];
         else if (mode == PJ_REF2) v = cs[cb] == ST_LEAF ? p.q[SL_Q1][C] : p.q[SL_Q1REF][C];
         else if (mode == PJ_RK2) v = cs[cb] == ST_LEAF ? p.q[SL_X2][C] : (2.0 * p.q[SL_Q1][C]) - p.q[SL_Q0][C];
-        else if (mode == PJ_REF3) v = p.q[SL_QH][C];
+        else if (mode == PJ_REF3 || mode == PJ_ST3) v = p.q[SL_QH][C];
+        else if (mode == PJ_ST2) v = p.q[SL_Q1][C];
         else v = p.q[SL_QE][C];
         s = (cb == 0) ? v : (s + v);
       }
       s = s * sc;
       const int64_t I = kk + G;
-      if (mode == PJ_Q0) {
+      if (mode == PJ_ST2) {
+        p.q[SL_Q1][I] = s;          // global step: stage-2 state of the node
+      } else if (mode == PJ_ST3) {
+        p.q[SL_QH][I] = s;          // global step: stage-3 state of the node
+      } else if (mode == PJ_Q0) {
         p.q[SL_Q0][I] = s;
       } else if (mode == PJ_CASEB) {
         p.q[SL_QH][I] = s;
@@ -512,9 +517,11 @@ __global__ __launch_bounds__(TPB) void k_ghost(Geo g, Dev p, int lo, int hi, int
 
 void launch_ghost(const Geo& g, const Dev& p, int lo, int hi, int cb_lev, int stage, hipStream_t s) {
   if (lo > hi) return;
-  const int srcB = stage == 1 ? SL_QH : (stage == 2 ? SL_QE : SL_N34);
-  const int srcA = stage == 1 ? SL_Q0 : (stage == 2 ? SL_H1 : SL_N14);
   const int dst = stage == 1 ? SL_Q0 : (stage == 2 ? SL_Q1 : SL_QH);
+  const int srcB = stage == 1 ? SL_QH : (stage == 2 ? SL_QE : SL_N34);
+  // global step: the parent level's own stage state; LT case A: q^n,
+  // first-order theta=1/2, theta=1/4
+  const int srcA = !g.lt ? dst : (stage == 1 ? SL_Q0 : (stage == 2 ? SL_H1 : SL_N14));
   const int64_t n = g.B * g.n[hi];
   if (g.d == 1) k_ghost<1><<<blocks_for(n), TPB, 0, s>>>(g, p, lo, hi, cb_lev, srcA, srcB, dst);
   else if (g.d == 2) k_ghost<2><<<blocks_for(n), TPB, 0, s>>>(g, p, lo, hi, cb_lev, srcA, srcB, dst);
@@ -583,7 +590,8 @@ __device__ __noinline__ void refined_flux(const Geo& g, const Dev& p, int lev, i
       if (sf == ST_ABSENT) flag_bad(p, inst, 4);
       for (int k = 0; k < M; k++) {
         const int64_t I = (int64_t)k * g.Ntot + Gf;
-        if (stage == 1) fin[e][k] = p.q[SL_Q0][I];
+        if (!g.lt) fin[e][k] = p.q[stage == 1 ? SL_Q0 : (stage == 2 ? SL_Q1 : SL_QH)][I];
+        else if (stage == 1) fin[e][k] = p.q[SL_Q0][I];
         else if (stage == 2) fin[e][k] = sf == ST_LEAF ? p.q[SL_X2][I] : (2.0 * p.q[SL_Q1][I]) - p.q[SL_Q0][I];
         else fin[e][k] = p.q[SL_QE][I];
       }
@@ -631,7 +639,7 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
       int x[3];
       mdec<D>((uint64_t)(t & (nl - 1)), x);
       const int64_t ib = g.off[lev] + inst * nl;
-      const double h = ldexp(p.dt[inst], g.L - lev);
+      const double h = g.lt ? ldexp(p.dt[inst], g.L - lev) : p.dt[inst];
       // weights b_i of the RK method: RK3 (1/6, 1/6, 2/3), RK2 (1/2, 1/2)
       const double wh = (g.rk == 2 ? 0.5 : (stage == 3 ? C_2_3 : C_1_6)) * h;
       double R[M];

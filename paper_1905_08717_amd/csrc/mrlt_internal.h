@@ -23,7 +23,7 @@ enum { SL_Q0 = 0, SL_Q1, SL_H1, SL_N14, SL_N34, SL_QH, SL_QE, SL_X2, SL_Q1REF, S
 enum { PDE_ADVECTION = 0, PDE_BURGERS = 1, PDE_NAGUMO = 2, PDE_EULER = 3, PDE_LINEAR = 4 };
 
 // projection kinds (one kernel, selected by mode)
-enum { PJ_Q0 = 0, PJ_CASEB, PJ_REF2, PJ_RK2, PJ_REF3, PJ_RK3 };
+enum { PJ_Q0 = 0, PJ_CASEB, PJ_REF2, PJ_RK2, PJ_REF3, PJ_RK3, PJ_ST2, PJ_ST3 };
 
 // counters per instance
 enum { CNT_UPDATES = 0, CNT_NEAR, CNT_NONFINITE, CNT_BAD, CNT_LEVEL0 };
@@ -34,6 +34,7 @@ struct Geo {
   int d, L, l0, m, nsub, B;
   int pde, recon, thresh, reflux;
   int rk;  // 3: compact RK3 (NERK3), 2: compact RK2 (NERK2)
+  int lt;  // 1: local time stepping, 0: one global step for every level
   int periodic[3];
   int64_t n[MRD_MAXLEV + 1];     // cells per instance at level l (2^{d l})
   int64_t off[MRD_MAXLEV + 1];   // first global index of level l

@@ -140,10 +140,41 @@ void ghost_fill(mr_ctx* c, int lmin, int stage) {
   timed(c, MR_KC_GHOST, [&] { launch_ghost(g, c->p, lo, g.L, cb, stage, c->stream); });
 }
 
+// one step of the MR scheme with a global time step (the paper's
+// comparison method): every level advances by dt at the same stage times
+void mr_iteration(mr_ctx* c) {
+  const Geo& g = c->g;
+  const int L = g.L;
+  hipStream_t s = c->stream;
+  auto stage = [&](int st) {
+    timed(c, MR_KC_STAGE, [&] { launch_stage(g, c->p, g.l0, L, st, s); });
+  };
+  project_range(c, L - 1, g.l0, PJ_Q0);
+  if (c->s.remesh && g.l0 <= L - 1) {
+    remesh(c, g.l0);
+    project_range(c, L - 1, g.l0, PJ_Q0);
+  }
+  ghost_fill(c, g.l0, 1);
+  stage(1);
+  project_range(c, L - 1, g.l0, PJ_ST2);
+  ghost_fill(c, g.l0, 2);
+  stage(2);
+  if (g.rk == 3) {
+    project_range(c, L - 1, g.l0, PJ_ST3);
+    ghost_fill(c, g.l0, 3);
+    stage(3);
+  }
+  timed(c, MR_KC_FINALIZE, [&] { launch_finalize(g, c->p, g.l0, L, s); });
+}
+
 // one iteration of Alg. alg-LTS
 void lt_iteration(mr_ctx* c, int64_t n, int64_t N) {
   const Geo& g = c->g;
   const int L = g.L;
+  if (!g.lt) {
+    mr_iteration(c);
+    return;
+  }
   const int lmin = lmin_of(g, n);
   project_range(c, L - 1, lmin, PJ_Q0);
   if (c->s.remesh && lmin <= L - 1) {
@@ -253,7 +284,8 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
   *out = nullptr;
   if (!s || !eps || dim < 1 || dim > 3 || n_inst < 1) return MR_EINVAL;
   if (s->l0 < 2 || L < s->l0 || L > MR_MAXLEV || L - s->l0 > 20 || dim * L > 40) return MR_EINVAL;
-  if ((s->rk != 2 && s->rk != 3) || s->lt != 1 || s->pde < MR_PDE_ADVECTION || s->pde > MR_PDE_LINEAR)
+  if ((s->rk != 2 && s->rk != 3) || (s->lt != 0 && s->lt != 1) || s->pde < MR_PDE_ADVECTION ||
+      s->pde > MR_PDE_LINEAR)
     return MR_EINVAL;
   if (s->recon < 0 || s->recon > 2) return MR_EINVAL;
   for (int a = 0; a < dim; a++) {
@@ -286,6 +318,7 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
   g.thresh = s->thresh;
   g.reflux = s->reflux;
   g.rk = s->rk;
+  g.lt = s->lt;
   for (int a = 0; a < 3; a++) g.periodic[a] = a < dim && s->bc[a][0] == MR_BC_PERIODIC;
   int64_t off = 0, rc = 0, rf = 0;
   for (int lev = g.l0; lev <= L; lev++) {

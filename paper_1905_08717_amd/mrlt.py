@@ -117,7 +117,7 @@ def make_scheme(cfg: dict) -> MrScheme:
     d = cfg["dim"]
     s.pde = PDE[cfg["pde"]]
     s.rk = cfg.get("rk", 3)
-    s.lt = 1
+    s.lt = cfg.get("lt", 1)
     s.l0 = cfg.get("l0", 2)
     s.recon = cfg.get("recon", 1)
     s.thresh = cfg.get("thresh", 1)

@@ -348,3 +348,14 @@ def test_rk2_variant(mods, case):
         cfg = dict(W.euler_2d(L=6), rk=2)
         run_pair(mods, cfg, W.euler_quadrants_seeded(6, W.SEED + 3),
                  [lambda o: 0.8 * W.euler_dt(cfg, o.max_wavespeed(), o.stats()["t"])] * 3)
+
+
+@pytest.mark.parametrize("rk", [2, 3])
+def test_global_time_step_variant(mods, rk):
+    # MR with one global step for every level (lt = 0), the paper's
+    # comparison scheme
+    cfg = dict(W.nagumo_2d(L=7), lt=0, rk=rk)
+    run_pair(mods, cfg, W.nagumo_front(7), [0.4 / (4 * 128 ** 2 + 800)] * 2)
+    cfg = dict(W.euler_2d(L=6), lt=0, rk=rk)
+    run_pair(mods, cfg, W.euler_quadrants_seeded(6, W.SEED + 11),
+             [lambda o: 0.8 * W.euler_dt(cfg, o.max_wavespeed(), o.stats()["t"])] * 2)
