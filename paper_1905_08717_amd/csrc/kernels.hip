@@ -19,7 +19,7 @@ static constexpr int TPB = 256;
 int blocks_for(int64_t n) {
   int64_t b = (n + TPB - 1) / TPB;
   if (b < 1) b = 1;
-  if (b > 8192) b = 8192;
+  if (b > 2048) b = 2048;  // 8 waves per CU on 256 CUs; loops stride over the rest
   return (int)b;
 }
 
@@ -559,13 +559,14 @@ __device__ __forceinline__ void transverse(int dir, int& t0, int& t1) {
 // own stage state) and the neighbour's children (finer-side values: S1 q^n,
 // S2 eq. projleaf / projnode, S3 stage-3 or eq. rk3proj values).
 template <int D, int PDE>
-__device__ __noinline__ void refined_flux(const Geo& g, const Dev& p, int lev, int stage, int64_t inst,
-                                          const int* x, int dir, int side, int nbx, double* F) {
+__device__ __forceinline__ void refined_flux(const Geo& g, const Dev& p, int lev, int stage, int64_t inst,
+                                             const int* x, int dir, int side, int nbx, double* F) {
   constexpr int M = NC<D, PDE>::M;
   const double* cur = p.q[stage == 1 ? SL_Q0 : (stage == 2 ? SL_Q1 : SL_QH)];
   const int64_t ib = g.off[lev] + inst * g.n[lev];
   const int64_t ibf = g.off[lev + 1] + inst * g.n[lev + 1];
   double T[M][8];
+#pragma unroll
   for (int k = 0; k < M; k++) {
     double S[27];
     if (!gather27<D>(g, p, cur, lev, ib, x, k, S)) flag_bad(p, inst, 2);
@@ -574,29 +575,34 @@ __device__ __noinline__ void refined_flux(const Geo& g, const Dev& p, int lev, i
   int t0, t1;
   transverse<D>(dir, t0, t1);
   double Fs[M], Fb[M];
+#pragma unroll
   for (int b = 0; b < (1 << (D - 1)); b++) {
     int fy[3] = {2 * x[0], 2 * x[1], 2 * x[2]};
     int cbt = 0;
     if (t0 >= 0) { fy[t0] += b & 1; cbt |= (b & 1) << t0; }
     if (t1 >= 0) { fy[t1] += (b >> 1) & 1; cbt |= ((b >> 1) & 1) << t1; }
     double own[2][M], fin[2][M];
+#pragma unroll
     for (int e = 0; e < 2; e++) {
       const int cb = cbt | (e << dir);
+#pragma unroll
       for (int k = 0; k < M; k++) own[e][k] = pred_child<D>(T[k], cb);
       int y[3] = {fy[0], fy[1], fy[2]};
       y[dir] = 2 * nbx + e;
       const int64_t Gf = ibf + (int64_t)menc<D>(y);
       const uint8_t sf = p.st[Gf];
       if (sf == ST_ABSENT) flag_bad(p, inst, 4);
+#pragma unroll
       for (int k = 0; k < M; k++) {
         const int64_t I = (int64_t)k * g.Ntot + Gf;
-        if (!g.lt) fin[e][k] = p.q[stage == 1 ? SL_Q0 : (stage == 2 ? SL_Q1 : SL_QH)][I];
+        if (!g.lt) fin[e][k] = cur[I];
         else if (stage == 1) fin[e][k] = p.q[SL_Q0][I];
         else if (stage == 2) fin[e][k] = sf == ST_LEAF ? p.q[SL_X2][I] : (2.0 * p.q[SL_Q1][I]) - p.q[SL_Q0][I];
         else fin[e][k] = p.q[SL_QE][I];
       }
     }
     double c[4][M];
+#pragma unroll
     for (int k = 0; k < M; k++) {
       if (side) {
         c[0][k] = own[0][k]; c[1][k] = own[1][k]; c[2][k] = fin[0][k]; c[3][k] = fin[1][k];
@@ -605,18 +611,26 @@ __device__ __noinline__ void refined_flux(const Geo& g, const Dev& p, int lev, i
       }
     }
     face_flux<D, PDE>(g, lev + 1, dir, c, Fb);
+#pragma unroll
     for (int k = 0; k < M; k++) Fs[k] = (b == 0) ? Fb[k] : (Fs[k] + Fb[k]);
   }
   const double sc = D == 1 ? 1.0 : (D == 2 ? 0.5 : 0.25);
+#pragma unroll
   for (int k = 0; k < M; k++) F[k] = Fs[k] * sc;
 }
 
-template <int D, int PDE>
+// IFACE = false: every leaf without a refined face neighbour (the bulk of the
+// work, lean in registers); IFACE = true: the leaves of levels below L with
+// at least one refined face neighbour, whose faces are evaluated on the
+// finer level.  The two sets are disjoint and every leaf writes only its own
+// values and flux-register entries, so the two launches commute.
+template <int D, int PDE, bool IFACE>
 __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int stage) {
   constexpr int M = NC<D, PDE>::M;
   constexpr double C_1_6 = 1.0 / 6.0, C_2_3 = 2.0 / 3.0, C_1_3 = 1.0 / 3.0;
+  constexpr int LS = IFACE ? LS_IFACE : LS_LEAF;
   // one leaf-update per leaf and full RK step: counted once, at stage 1
-  if (stage == 1 && blockIdx.x == 0) {
+  if (!IFACE && stage == 1 && blockIdx.x == 0) {
     const int nlv = hi - lo + 1;
     for (int j = threadIdx.x; j < g.B * nlv; j += blockDim.x) {
       const int inst = j / nlv, lev = lo + j % nlv;
@@ -630,8 +644,8 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
     const int64_t nl = g.n[lev];
     const int n = 1 << lev;
     const bool finest = lev == g.L;
-    const int cntl = list_len(p, LS_LEAF, lev);
-    const int* lst = p.lst[LS_LEAF] + g.off[lev];
+    const int cntl = list_len(p, LS, lev);
+    const int* lst = p.lst[LS] + g.off[lev];
     GSL(i, cntl) {
       const int64_t t = lst[i];
       const int64_t G = g.off[lev] + t;
@@ -639,6 +653,26 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
       int x[3];
       mdec<D>((uint64_t)(t & (nl - 1)), x);
       const int64_t ib = g.off[lev] + inst * nl;
+      // status of the 2d face neighbours (3: outside the domain)
+      int nbs[D][2];
+      uint8_t sts[D][2];
+      bool refined = false;
+#pragma unroll
+      for (int dir = 0; dir < D; dir++)
+#pragma unroll
+        for (int side = 0; side < 2; side++) {
+          const int nb = map_nb(x[dir] + (side ? 1 : -1), n, g.periodic[dir]);
+          nbs[dir][side] = nb;
+          uint8_t sv = 3;
+          if (nb >= 0) {
+            int y[3] = {x[0], x[1], x[2]};
+            y[dir] = nb;
+            sv = p.st[ib + (int64_t)menc<D>(y)];
+          }
+          sts[dir][side] = sv;
+          refined = refined || sv == ST_INTERNAL;
+        }
+      if (!IFACE && refined && !finest) continue;  // the interface launch owns it
       const double h = g.lt ? ldexp(p.dt[inst], g.L - lev) : p.dt[inst];
       // weights b_i of the RK method: RK3 (1/6, 1/6, 2/3), RK2 (1/2, 1/2)
       const double wh = (g.rk == 2 ? 0.5 : (stage == 3 ? C_2_3 : C_1_6)) * h;
@@ -661,22 +695,13 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
           for (int k = 0; k < M; k++) c5[0][k] = c5[4][k] = 0.0;
         }
         double Fm[M], Fp[M];
-        int nbs[2];
-        uint8_t sts[2];
 #pragma unroll
         for (int side = 0; side < 2; side++) {
-          const int nb = map_nb(x[dir] + (side ? 1 : -1), n, g.periodic[dir]);
-          nbs[side] = nb;
-          uint8_t sv = 3;  // outside the domain
-          if (nb >= 0) {
-            int y[3] = {x[0], x[1], x[2]};
-            y[dir] = nb;
-            sv = p.st[ib + (int64_t)menc<D>(y)];
-          }
-          sts[side] = sv;
           double* F = side ? Fp : Fm;
-          if (sv == ST_INTERNAL && !finest) refined_flux<D, PDE>(g, p, lev, stage, inst, x, dir, side, nb, F);
-          else face_flux<D, PDE>(g, lev, dir, c5 + side, F);
+          if (IFACE && sts[dir][side] == ST_INTERNAL)
+            refined_flux<D, PDE>(g, p, lev, stage, inst, x, dir, side, nbs[dir][side], F);
+          else
+            face_flux<D, PDE>(g, lev, dir, c5 + side, F);
         }
 #pragma unroll
         for (int k = 0; k < M; k++) {
@@ -687,15 +712,16 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
 #pragma unroll
           for (int side = 0; side < 2; side++) {
             const double* F = side ? Fp : Fm;
-            if (sts[side] == ST_INTERNAL && !finest) {
+            if (IFACE && sts[dir][side] == ST_INTERNAL) {
+#pragma unroll
               for (int k = 0; k < M; k++) {
                 double* r = regc_at(g, p, lev, 2 * dir + side, k, t);
                 *r = *r + (wh * F[k]);
               }
-            } else if (sts[side] == ST_ABSENT) {
+            } else if (sts[dir][side] == ST_ABSENT) {
               // fine side of a coarse leaf's refined face
               int y[3] = {x[0] >> 1, x[1] >> 1, x[2] >> 1};
-              y[dir] = nbs[side] >> 1;
+              y[dir] = nbs[dir][side] >> 1;
               const int64_t tX = inst * g.n[lev - 1] + (int64_t)menc<D>(y);
               if (p.st[g.off[lev - 1] + tX] != ST_LEAF) flag_bad(p, inst, 8);
               int t0, t1;
@@ -762,17 +788,25 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
   }
 }
 
+template <int D, int PDE>
+static void stage_dp(const Geo& g, const Dev& p, int lo, int hi, int stage, hipStream_t s) {
+  k_stage<D, PDE, false><<<blocks_for(g.B * g.n[hi]), TPB, 0, s>>>(g, p, lo, hi, stage);
+  const int hif = hi < g.L ? hi : g.L - 1;
+  if (lo > hif) return;
+  // interface leaves lie along refinement boundaries: a small fraction
+  int nb = blocks_for(g.B * g.n[hif]);
+  if (nb > 512) nb = 512;
+  k_stage<D, PDE, true><<<nb, TPB, 0, s>>>(g, p, lo, hif, stage);
+}
+
 template <int D>
 static void stage_d(const Geo& g, const Dev& p, int lo, int hi, int stage, hipStream_t s) {
-  int64_t cap = 0;
-  for (int lev = lo; lev <= hi; lev++) cap = cap > g.B * g.n[lev] ? cap : g.B * g.n[lev];
-  const int nb = blocks_for(cap);
   switch (g.pde) {
-    case PDE_ADVECTION: k_stage<D, PDE_ADVECTION><<<nb, TPB, 0, s>>>(g, p, lo, hi, stage); break;
-    case PDE_BURGERS: k_stage<D, PDE_BURGERS><<<nb, TPB, 0, s>>>(g, p, lo, hi, stage); break;
-    case PDE_NAGUMO: k_stage<D, PDE_NAGUMO><<<nb, TPB, 0, s>>>(g, p, lo, hi, stage); break;
-    case PDE_EULER: k_stage<D, PDE_EULER><<<nb, TPB, 0, s>>>(g, p, lo, hi, stage); break;
-    default: k_stage<D, PDE_LINEAR><<<nb, TPB, 0, s>>>(g, p, lo, hi, stage); break;
+    case PDE_ADVECTION: stage_dp<D, PDE_ADVECTION>(g, p, lo, hi, stage, s); break;
+    case PDE_BURGERS: stage_dp<D, PDE_BURGERS>(g, p, lo, hi, stage, s); break;
+    case PDE_NAGUMO: stage_dp<D, PDE_NAGUMO>(g, p, lo, hi, stage, s); break;
+    case PDE_EULER: stage_dp<D, PDE_EULER>(g, p, lo, hi, stage, s); break;
+    default: stage_dp<D, PDE_LINEAR>(g, p, lo, hi, stage, s); break;
   }
 }
 
@@ -1076,11 +1110,36 @@ __device__ __forceinline__ int comp_level(const Geo& g, int lo, int64_t b) {
   return lev;
 }
 
-__device__ __forceinline__ void cell_types(const Dev& p, int64_t G, int* c) {
+// leaf of a level below L with a refined (internal) face neighbour
+template <int D>
+__device__ __forceinline__ bool refined_face(const Geo& g, const Dev& p, int lev, int64_t t) {
+  const int64_t nl = g.n[lev];
+  const int n = 1 << lev;
+  const int64_t ib = g.off[lev] + (t >> (D * lev)) * nl;
+  int x[3];
+  mdec<D>((uint64_t)(t & (nl - 1)), x);
+  bool r = false;
+#pragma unroll
+  for (int dir = 0; dir < D; dir++)
+#pragma unroll
+    for (int side = 0; side < 2; side++) {
+      const int nb = map_nb(x[dir] + (side ? 1 : -1), n, g.periodic[dir]);
+      if (nb < 0) continue;
+      int y[3] = {x[0], x[1], x[2]};
+      y[dir] = nb;
+      r = r || p.st[ib + (int64_t)menc<D>(y)] == ST_INTERNAL;
+    }
+  return r;
+}
+
+template <int D>
+__device__ __forceinline__ void cell_types(const Geo& g, const Dev& p, int lev, int64_t t, int* c) {
+  const int64_t G = g.off[lev] + t;
   const uint8_t st = p.st[G];
   c[LS_LEAF] = st == ST_LEAF;
   c[LS_INTERNAL] = st == ST_INTERNAL;
   c[LS_GHOST] = p.gh[G] != 0;
+  c[LS_IFACE] = st == ST_LEAF && lev < g.L && refined_face<D>(g, p, lev, t);
 }
 
 // exclusive scan of v over the 256 threads of a block; returns the prefix,
@@ -1101,6 +1160,7 @@ __device__ __forceinline__ int block_exscan(int v, int* sh, int* tot) {
   return incl - v;
 }
 
+template <int D>
 __global__ __launch_bounds__(TPB) void k_comp_count(Geo g, Dev p, int lo) {
   __shared__ int sh[TPB];
   const int64_t nbt = g.comp_first[g.L + 1];
@@ -1109,11 +1169,11 @@ __global__ __launch_bounds__(TPB) void k_comp_count(Geo g, Dev p, int lo) {
   const int chunk = g.comp_chunk[lev];
   const int cpt = chunk > TPB ? chunk / TPB : 1;
   const int64_t t0 = (b - g.comp_first[lev]) * (int64_t)chunk + (int64_t)threadIdx.x * cpt;
-  int c[LS_COUNT] = {0, 0, 0};
+  int c[LS_COUNT] = {};
   if ((int)threadIdx.x * cpt < chunk)
     for (int j = 0; j < cpt; j++) {
       int e[LS_COUNT];
-      cell_types(p, g.off[lev] + t0 + j, e);
+      cell_types<D>(g, p, lev, t0 + j, e);
       for (int k = 0; k < LS_COUNT; k++) c[k] += e[k];
     }
   for (int k = 0; k < LS_COUNT; k++) {
@@ -1157,6 +1217,7 @@ __global__ __launch_bounds__(TPB) void k_comp_scan(Geo g, Dev p, int lo) {
   }
 }
 
+template <int D>
 __global__ __launch_bounds__(TPB) void k_comp_write(Geo g, Dev p, int lo) {
   __shared__ int sh[TPB];
   const int64_t nbt = g.comp_first[g.L + 1];
@@ -1167,11 +1228,11 @@ __global__ __launch_bounds__(TPB) void k_comp_write(Geo g, Dev p, int lo) {
   const int64_t tb = (b - g.comp_first[lev]) * (int64_t)chunk;
   const int64_t t0 = tb + (int64_t)threadIdx.x * cpt;
   const bool act = (int)threadIdx.x * cpt < chunk;
-  int c[LS_COUNT] = {0, 0, 0};
+  int c[LS_COUNT] = {};
   if (act)
     for (int j = 0; j < cpt; j++) {
       int e[LS_COUNT];
-      cell_types(p, g.off[lev] + t0 + j, e);
+      cell_types<D>(g, p, lev, t0 + j, e);
       for (int k = 0; k < LS_COUNT; k++) c[k] += e[k];
     }
   int base[LS_COUNT];
@@ -1182,7 +1243,7 @@ __global__ __launch_bounds__(TPB) void k_comp_write(Geo g, Dev p, int lo) {
   if (!act) return;
   for (int j = 0; j < cpt; j++) {
     int e[LS_COUNT];
-    cell_types(p, g.off[lev] + t0 + j, e);
+    cell_types<D>(g, p, lev, t0 + j, e);
     for (int k = 0; k < LS_COUNT; k++)
       if (e[k]) p.lst[k][g.off[lev] + base[k]++] = (int)(t0 + j);
   }
@@ -1190,9 +1251,13 @@ __global__ __launch_bounds__(TPB) void k_comp_write(Geo g, Dev p, int lo) {
 
 void launch_compact(const Geo& g, const Dev& p, int lo, hipStream_t s) {
   const int64_t nb = g.comp_first[g.L + 1] - g.comp_first[lo];
-  k_comp_count<<<(unsigned)nb, TPB, 0, s>>>(g, p, lo);
+  if (g.d == 1) k_comp_count<1><<<(unsigned)nb, TPB, 0, s>>>(g, p, lo);
+  else if (g.d == 2) k_comp_count<2><<<(unsigned)nb, TPB, 0, s>>>(g, p, lo);
+  else k_comp_count<3><<<(unsigned)nb, TPB, 0, s>>>(g, p, lo);
   k_comp_scan<<<(unsigned)(g.L - lo + 1), TPB, 0, s>>>(g, p, lo);
-  k_comp_write<<<(unsigned)nb, TPB, 0, s>>>(g, p, lo);
+  if (g.d == 1) k_comp_write<1><<<(unsigned)nb, TPB, 0, s>>>(g, p, lo);
+  else if (g.d == 2) k_comp_write<2><<<(unsigned)nb, TPB, 0, s>>>(g, p, lo);
+  else k_comp_write<3><<<(unsigned)nb, TPB, 0, s>>>(g, p, lo);
 }
 
 #define DISPATCH_D(kern, n, ...)                                                  \

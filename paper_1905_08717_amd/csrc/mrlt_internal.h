@@ -55,8 +55,9 @@ struct Geo {
   int i0, i1;
 };
 
-// per-level lists of cell indices (within-level index t = inst * n[l] + key)
-enum { LS_LEAF = 0, LS_INTERNAL = 1, LS_GHOST = 2, LS_COUNT = 3 };
+// per-level lists of cell indices (within-level index t = inst * n[l] + key);
+// LS_IFACE: the leaves of LS_LEAF below L with a refined face neighbour
+enum { LS_LEAF = 0, LS_INTERNAL = 1, LS_GHOST = 2, LS_IFACE = 3, LS_COUNT = 4 };
 
 struct Dev {
   uint8_t* st;     // status per cell
