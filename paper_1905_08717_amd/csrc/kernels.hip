@@ -420,6 +420,26 @@ __device__ __forceinline__ int list_len(const Dev& p, int type, int lev) {
   return p.lcnt[type * (MRD_MAXLEV + 1) + lev];
 }
 
+// The lists of levels lo..hi as one index space, so that a lane takes one
+// item whatever its level (no per-lane walk over the levels): the lengths
+// go to shared memory, a lane finds its level by a scan of them.
+__device__ __forceinline__ int64_t flat_setup(const Dev& p, int type, int lo, int hi, int* s_cnt) {
+  const int nlv = hi - lo + 1;
+  if ((int)threadIdx.x < nlv) s_cnt[threadIdx.x] = list_len(p, type, lo + (int)threadIdx.x);
+  __syncthreads();
+  int64_t tot = 0;
+  for (int j = 0; j < nlv; j++) tot += s_cnt[j];
+  return tot;
+}
+__device__ __forceinline__ int flat_level(const int* s_cnt, int lo, int64_t& k) {
+  int j = 0;
+  while (k >= s_cnt[j]) {
+    k -= s_cnt[j];
+    j++;
+  }
+  return lo + j;
+}
+
 __global__ __launch_bounds__(TPB) void k_project(Geo g, Dev p, int lev, int mode) {
   const int nch = 1 << g.d;
   const double sc = g.d == 1 ? 0.5 : (g.d == 2 ? 0.25 : 0.125);
@@ -491,13 +511,15 @@ void launch_project(const Geo& g, const Dev& p, int lev, int mode, hipStream_t s
 template <int D>
 __global__ __launch_bounds__(TPB) void k_ghost(Geo g, Dev p, int lo, int hi, int cb_lev, int srcA, int srcB,
                                               int dst) {
-  for (int lev = lo; lev <= hi; lev++) {
-    const int64_t nl = g.n[lev];
-    const int n = list_len(p, LS_GHOST, lev);
-    const int* lst = p.lst[LS_GHOST] + g.off[lev];
-    const double* src = p.q[lev == cb_lev ? srcB : srcA];
-    GSL(i, n) {
-      const int64_t t = lst[i];
+  __shared__ int s_cnt[MRD_MAXLEV + 1];
+  const int64_t ntot = flat_setup(p, LS_GHOST, lo, hi, s_cnt);
+  GSL(i, ntot) {
+    {
+      int64_t kk = i;
+      const int lev = flat_level(s_cnt, lo, kk);
+      const int64_t nl = g.n[lev];
+      const double* src = p.q[lev == cb_lev ? srcB : srcA];
+      const int64_t t = p.lst[LS_GHOST][g.off[lev] + kk];
       const int64_t G = g.off[lev] + t;
       const int64_t inst = t >> (D * lev);
       int x[3];
@@ -640,14 +662,16 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
   }
   const int64_t NT = g.Ntot;
   const double* cur = p.q[stage == 1 ? SL_Q0 : (stage == 2 ? SL_Q1 : SL_QH)];
-  for (int lev = lo; lev <= hi; lev++) {
-    const int64_t nl = g.n[lev];
-    const int n = 1 << lev;
-    const bool finest = lev == g.L;
-    const int cntl = list_len(p, LS, lev);
-    const int* lst = p.lst[LS] + g.off[lev];
-    GSL(i, cntl) {
-      const int64_t t = lst[i];
+  __shared__ int s_cnt[MRD_MAXLEV + 1];
+  const int64_t ntot = flat_setup(p, LS, lo, hi, s_cnt);
+  GSL(i, ntot) {
+    {
+      int64_t kk = i;
+      const int lev = flat_level(s_cnt, lo, kk);
+      const int64_t nl = g.n[lev];
+      const int n = 1 << lev;
+      const bool finest = lev == g.L;
+      const int64_t t = p.lst[LS][g.off[lev] + kk];
       const int64_t G = g.off[lev] + t;
       const int64_t inst = t >> (D * lev);
       int x[3];
@@ -825,13 +849,15 @@ void launch_stage(const Geo& g, const Dev& p, int lo, int hi, int stage, hipStre
 template <int D>
 __global__ __launch_bounds__(TPB) void k_finalize(Geo g, Dev p, int lo, int hi) {
   const double sc = D == 1 ? 1.0 : (D == 2 ? 0.5 : 0.25);
-  for (int lev = lo; lev <= hi; lev++) {
-    const int64_t nl = g.n[lev];
-    const int n = 1 << lev;
-    const int cntl = list_len(p, LS_LEAF, lev);
-    const int* lst = p.lst[LS_LEAF] + g.off[lev];
-    GSL(i, cntl) {
-      const int64_t t = lst[i];
+  __shared__ int s_cnt[MRD_MAXLEV + 1];
+  const int64_t ntot = flat_setup(p, LS_LEAF, lo, hi, s_cnt);
+  GSL(i, ntot) {
+    {
+      int64_t kk = i;
+      const int lev = flat_level(s_cnt, lo, kk);
+      const int64_t nl = g.n[lev];
+      const int n = 1 << lev;
+      const int64_t t = p.lst[LS_LEAF][g.off[lev] + kk];
       const int64_t G = g.off[lev] + t;
       double q[5];
       for (int k = 0; k < g.m; k++) q[k] = p.q[SL_QE][(int64_t)k * g.Ntot + G];
@@ -886,16 +912,31 @@ void launch_clear_regs(const Geo& g, const Dev& p, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 // remesh (Alg. AdaptiveMesh, Alg. waveletThres; only scales evolved in the
-// current iteration may split or merge).  Levels below la are frozen.
-//   detail:  significant internal node: max_{c,k} |q_c - q~_c| / scale_k >
-//            eps_{l+1} (level-dependent 2^{d(l+1-L)} eps); eps = 0 keeps all
-//   seed:    significant nodes, existing nodes at distance 1 (space safety),
-//            children of significant nodes below L (scale safety)
-//   close:   least set with the tree rule and the radius-2 grading rule; all
-//            implications point one level down, so one fine-to-coarse sweep
-//   prune:   greatest subset still satisfying both rules with frozen
-//            existence at la; one coarse-to-fine sweep
+// current iteration may split or merge).  Levels below la are frozen.  The
+// set W of nodes that will be internal is built in the remesh byte table:
+//   detail + seed (one pass over the internal nodes): a node is significant
+//            when max_{c,k} |q_c - q~_c| / scale_k > eps_{l+1} (level-
+//            dependent 2^{d(l+1-L)} eps; eps = 0 keeps every node); it puts
+//            itself, its existing neighbours at distance 1 (space safety)
+//            and, below L-1, its children (scale safety) into W
+//   close:   least superset closed under the tree rule and the radius-2
+//            grading rule; every implication points one level down, so one
+//            fine-to-coarse sweep: each W node at l+1 adds the 3^d cells of
+//            level l whose children's radius-2 neighbourhood holds it
+//   prune:   greatest subset still satisfying both rules with existence
+//            frozen at la; one coarse-to-fine sweep
 //   apply:   new status, new nodes predicted from the parent level
+// Marks only ever grow inside a pass, so the passes that add them use
+// atomic ORs on the 32-bit word holding the byte and give the same set in
+// any order.  The dense passes read 16 cells per lane with one 16-byte load;
+// a block gathers the cells that need work into shared memory and then
+// spreads them over its lanes.
+
+static constexpr uint8_t RF_W = 2;
+// block summaries (4096-cell blocks of a level): any cell exists / is
+// internal / is a leaf
+static constexpr unsigned BS_EXIST = 1u, BS_INT = 2u, BS_LEAF = 4u;
+static constexpr int GRP = 16;            // cells per lane in the dense passes of large levels
 
 // true when the cell's instance is outside the remesh window
 __device__ __forceinline__ bool inst_of_window_skip(const Geo& g, int64_t t, int shift) {
@@ -903,43 +944,145 @@ __device__ __forceinline__ bool inst_of_window_skip(const Geo& g, int64_t t, int
   return inst < g.i0 || inst >= g.i1;
 }
 
-// dense multi-level sweep: global cell range of levels lo..hi
-__device__ __forceinline__ int64_t level_end(const Geo& g, int hi) { return hi == g.L ? g.Ntot : g.off[hi + 1]; }
+// bytes of cells [t0, t0+16) of a level table (zero past the level end);
+// level tables start at multiples of 256 cells, so the load is aligned
+__device__ __forceinline__ uint4 ld16(const uint8_t* base, int64_t t0, int64_t N) {
+  if (t0 + 16 <= N) return *reinterpret_cast<const uint4*>(base + t0);
+  uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+  for (int j = 0; j < 16; j++)
+    if (t0 + j < N) w[j >> 2] |= (uint32_t)base[t0 + j] << (8 * (j & 3));
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+// G = 16: ld16; G = 1: the one byte of cell t0 (zero past the level end)
+template <int G>
+__device__ __forceinline__ uint4 ldg(const uint8_t* base, int64_t t0, int64_t N) {
+  if (G == 16) return ld16(base, t0, N);
+  return make_uint4(t0 < N ? (uint32_t)base[t0] : 0u, 0u, 0u, 0u);
+}
+__device__ __forceinline__ uint8_t byte_of(const uint4& v, int j) {
+  const uint32_t w = j < 4 ? v.x : (j < 8 ? v.y : (j < 12 ? v.z : v.w));
+  return (uint8_t)(w >> (8 * (j & 3)));
+}
+__device__ __forceinline__ bool any16(const uint4& v, uint32_t mask) {
+  return ((v.x | v.y | v.z | v.w) & mask) != 0u;
+}
+// the 16 >> D parent statuses of a group (parent k of cell j: k = j >> D);
+// with G = 1 the parent of cell t0
+template <int D, int G = 16>
+__device__ __forceinline__ uint64_t ld_parents(const uint8_t* stp, int64_t t0, int64_t N) {
+  const int64_t p0 = t0 >> D;
+  if (G == 1) return t0 < N ? (uint64_t)stp[p0] : 0ull;
+  if (t0 + 16 <= N) {
+    if (D == 1) return *reinterpret_cast<const uint64_t*>(stp + p0);
+    if (D == 2) return *reinterpret_cast<const uint32_t*>(stp + p0);
+    return *reinterpret_cast<const uint16_t*>(stp + p0);
+  }
+  uint64_t r = 0ull;
+  const int64_t pl = (N - 1) >> D;
+  for (int k = 0; k < (16 >> D); k++)
+    if (p0 + k <= pl) r |= (uint64_t)stp[p0 + k] << (8 * k);
+  return r;
+}
 
-#define MULTI_LEVEL_LOOP(G, lev, lo, hi)                                                  \
-  int lev = lo;                                                                            \
-  for (int64_t G = g.off[lo] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;            \
-       G < level_end(g, hi); G += (int64_t)gridDim.x * blockDim.x)                         \
-    if ((lev = level_of(g, lev, hi, G)) >= 0)
+// Levels with >= 4096 cells per instance and >= 2^20 cells in all are
+// "wide": their dense passes take 16 cells per lane, their 4096-cell blocks
+// are the compaction blocks, and they keep block summaries.
+__host__ __device__ __forceinline__ bool wide_level(const Geo& g, int lev) {
+  return g.comp_chunk[lev] == (1 << BS_SHIFT) && g.B * g.n[lev] >= ((int64_t)1 << 20);
+}
+// block summary of a wide level; unknown (all bits) elsewhere
+__device__ __forceinline__ unsigned bsum_of(const Geo& g, const Dev& p, int lev, int64_t sb) {
+  return wide_level(g, lev) ? p.bsum[g.bs_off[lev] + sb] : 0xffu;
+}
 
-__device__ __forceinline__ int level_of(const Geo& g, int lev, int hi, int64_t G) {
-  while (lev < hi && G >= g.off[lev + 1]) lev++;
-  return lev;
+// cell t of level lev into W; its 4096-cell block is flagged in wsum (every
+// writer of the flag stores the same value)
+__device__ __forceinline__ void mark_w(const Geo& g, const Dev& p, int lev, int64_t t) {
+  const int64_t G = g.off[lev] + t;
+  atomicOr(reinterpret_cast<unsigned*>(p.rf + (G & ~(int64_t)3)), (unsigned)RF_W << (8 * (int)(G & 3)));
+  p.wsum[g.bs_off[lev] + (t >> BS_SHIFT)] = 1;
+}
+// A marking pass first reads the current bytes of all its targets (loads
+// only, so they are in flight together), then sets the missing marks (atomics
+// only): one memory round trip per item, and no atomic for a mark that is
+// already there.
+
+// exclusive scan over the 256 threads of a block; *tot receives the total
+template <class T>
+__device__ __forceinline__ T block_exscan(T v, T* sh, T* tot) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int o = 1; o < TPB; o <<= 1) {
+    const T a = tid >= o ? sh[tid - o] : (T)0;
+    __syncthreads();
+    sh[tid] += a;
+    __syncthreads();
+  }
+  const T incl = sh[tid];
+  *tot = sh[TPB - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+// block-wide gather of work cells: lane i offers the cells of its group
+// flagged in `mask`; returns their number, block-local indices in `items`
+template <int G>
+__device__ __forceinline__ int block_items(uint32_t mask, int* items, int* sh) {
+  int tot;
+  int k = block_exscan<int>(__popc(mask), sh, &tot);
+  while (mask) {
+    const int j = __builtin_ctz(mask);
+    mask &= mask - 1u;
+    items[k++] = (int)threadIdx.x * G + j;
+  }
+  __syncthreads();
+  return tot;
+}
+
+// remesh table and W flags cleared on levels lo..hi: one workgroup per
+// 4096-cell block, only blocks flagged in wsum hold marks
+__global__ __launch_bounds__(TPB) void k_clear_w(Geo g, Dev p, int lo, int hi) {
+  for (int64_t sb = g.bs_off[lo] + blockIdx.x; sb < g.bs_off[hi + 1]; sb += gridDim.x) {
+    if (p.wsum[sb] == 0) continue;
+    int lev = lo;
+    while (sb >= g.bs_off[lev + 1]) lev++;
+    const int64_t n256 = (g.B * g.n[lev] + 255) & ~(int64_t)255;  // padded level table
+    const int64_t t = ((sb - g.bs_off[lev]) << BS_SHIFT) + (int64_t)threadIdx.x * 16;
+    if (t < n256) *reinterpret_cast<uint4*>(p.rf + g.off[lev] + t) = make_uint4(0u, 0u, 0u, 0u);
+    __syncthreads();
+    if (threadIdx.x == 0) p.wsum[sb] = 0;
+  }
 }
 
 template <int D>
-__global__ __launch_bounds__(TPB) void k_detail(Geo g, Dev p, int lo, int hi) {
-  MULTI_LEVEL_LOOP(G, lev, lo, hi) {
-    const int64_t nl = g.n[lev];
-    const int64_t t = G - g.off[lev];
-    if (inst_of_window_skip(g, t, D * lev)) continue;
-    uint8_t sig = 0;
-    if (lev < g.L && p.st[G] == ST_INTERNAL) {
+__global__ __launch_bounds__(TPB) void k_detail_seed(Geo g, Dev p, int lo, int hi) {
+  __shared__ int s_cnt[MRD_MAXLEV + 1];
+  const int64_t ntot = flat_setup(p, LS_INTERNAL, lo, hi, s_cnt);
+  GSL(i, ntot) {
+    {
+      int64_t kk = i;
+      const int lev = flat_level(s_cnt, lo, kk);
+      const int64_t nl = g.n[lev];
+      const int n = 1 << lev;
+      const int64_t t = p.lst[LS_INTERNAL][g.off[lev] + kk];
+      if (inst_of_window_skip(g, t, D * lev)) continue;
       const int64_t inst = t >> (D * lev);
+      const int64_t ib = g.off[lev] + inst * nl;
+      int x[3];
+      mdec<D>((uint64_t)(t & (nl - 1)), x);
       const double e0 = p.eps[inst];
-      if (e0 == 0.0) {
-        sig = 1;
-      } else {
+      bool sig = true;
+      if (e0 != 0.0) {
         const double e = g.thresh ? ldexp(e0, D * (lev + 1 - g.L)) : e0;
-        int x[3];
-        mdec<D>((uint64_t)(t & (nl - 1)), x);
-        const int64_t ib = g.off[lev] + inst * nl;
         const int64_t C0 = g.off[lev + 1] + (t << D);
         double Dm = 0.0;
         for (int k = 0; k < g.m; k++) {
           double S[27], T[8];
           if (!gather27<D>(g, p, p.q[SL_Q0], lev, ib, x, k, S)) flag_bad(p, inst, 16);
           pred_terms<D>(S, T);
+#pragma unroll
           for (int cb = 0; cb < (1 << D); cb++) {
             const double det = fabs(p.q[SL_Q0][(int64_t)k * g.Ntot + C0 + cb] - pred_child<D>(T, cb)) / g.scale[k];
             if (det > Dm) Dm = det;
@@ -948,113 +1091,222 @@ __global__ __launch_bounds__(TPB) void k_detail(Geo g, Dev p, int lo, int hi) {
         sig = Dm > e;
         if (fabs(Dm - e) <= 1e-12 * e) atomicAdd(&p.cnt[inst * CNT_PER_INST + CNT_NEAR], 1ull);
       }
+      if (!sig) continue;
+      // targets: the 3^d neighbourhood (existing cells; the node itself is
+      // internal) and, below L-1, the 2^d children
+      constexpr int NN = D == 1 ? 3 : (D == 2 ? 9 : 27);
+      const bool kids = lev + 1 <= g.L - 1;
+      uint64_t need = 0ull;
+#pragma unroll
+      for (int o = 0; o < NN; o++) {
+        const int ox = o % 3 - 1, oy = D > 1 ? (o / 3) % 3 - 1 : 0, oz = D > 2 ? o / 9 - 1 : 0;
+        int y[3] = {map_nb(x[0] + ox, n, g.periodic[0]), 0, 0};
+        if (D > 1) y[1] = map_nb(x[1] + oy, n, g.periodic[1]);
+        if (D > 2) y[2] = map_nb(x[2] + oz, n, g.periodic[2]);
+        if (y[0] < 0 || y[1] < 0 || y[2] < 0) continue;
+        const int64_t Gy = g.off[lev] + inst * nl + (int64_t)menc<D>(y);
+        if (p.st[Gy] != ST_ABSENT && !(p.rf[Gy] & RF_W)) need |= 1ull << o;
+      }
+      if (kids) {
+#pragma unroll
+        for (int cb = 0; cb < (1 << D); cb++)
+          if (!(p.rf[g.off[lev + 1] + (t << D) + cb] & RF_W)) need |= 1ull << (NN + cb);
+      }
+#pragma unroll
+      for (int o = 0; o < NN; o++) {
+        if (!((need >> o) & 1ull)) continue;
+        const int ox = o % 3 - 1, oy = D > 1 ? (o / 3) % 3 - 1 : 0, oz = D > 2 ? o / 9 - 1 : 0;
+        int y[3] = {map_nb(x[0] + ox, n, g.periodic[0]), 0, 0};
+        if (D > 1) y[1] = map_nb(x[1] + oy, n, g.periodic[1]);
+        if (D > 2) y[2] = map_nb(x[2] + oz, n, g.periodic[2]);
+        mark_w(g, p, lev, inst * nl + (int64_t)menc<D>(y));
+      }
+#pragma unroll
+      for (int cb = 0; cb < (1 << D); cb++)
+        if ((need >> (NN + cb)) & 1ull) mark_w(g, p, lev + 1, (t << D) + cb);
     }
-    p.rf[G] = sig;
   }
 }
 
-template <int D>
-__global__ __launch_bounds__(TPB) void k_seed(Geo g, Dev p, int lo, int hi, int la) {
-  MULTI_LEVEL_LOOP(G, lev, lo, hi) {
-    const int64_t nl = g.n[lev];
-    const int n = 1 << lev;
-    const int64_t t = G - g.off[lev];
-    if (inst_of_window_skip(g, t, D * lev)) continue;
-    const uint8_t r = p.rf[G];
-    bool w = r & 1;
-    const int64_t inst = t >> (D * lev);
-    if (!w && p.st[G] != ST_ABSENT) {
-      int x[3];
-      mdec<D>((uint64_t)(t & (nl - 1)), x);
-      const int64_t ib = g.off[lev] + inst * nl;
-      for (int oz = (D > 2 ? -1 : 0); oz <= (D > 2 ? 1 : 0) && !w; oz++)
-        for (int oy = (D > 1 ? -1 : 0); oy <= (D > 1 ? 1 : 0) && !w; oy++)
-          for (int ox = -1; ox <= 1 && !w; ox++) {
-            int y[3] = {map_nb(x[0] + ox, n, g.periodic[0]), 0, 0};
-            if (D > 1) y[1] = map_nb(x[1] + oy, n, g.periodic[1]);
-            if (D > 2) y[2] = map_nb(x[2] + oz, n, g.periodic[2]);
-            if (y[0] < 0 || y[1] < 0 || y[2] < 0) continue;
-            if (p.rf[ib + (int64_t)menc<D>(y)] & 1) w = true;
-          }
-    }
-    if (!w && lev - 1 >= la && lev <= g.L - 1) w = p.rf[g.off[lev - 1] + (t >> D)] & 1;
-    if (w) p.rf[G] = r | 2;
-  }
+// mask of the W cells of a group inside the remesh window
+template <int G>
+__device__ __forceinline__ uint32_t w_mask(const Geo& g, const uint4& v, int64_t t0, int shift) {
+  uint32_t mask = 0u;
+  if (!any16(v, 0x02020202u)) return 0u;
+  if (G == 1) return inst_of_window_skip(g, t0, shift) ? 0u : 1u;
+#pragma unroll
+  for (int j = 0; j < 16; j++)
+    if (byte_of(v, j) & RF_W) mask |= 1u << j;
+  // a group never straddles two instances unless the level has < 16 cells
+  if (mask && (inst_of_window_skip(g, t0, shift) || inst_of_window_skip(g, t0 + 15, shift)))
+    for (int j = 0; j < 16; j++)
+      if (inst_of_window_skip(g, t0 + j, shift)) mask &= ~(1u << j);
+  return mask;
 }
 
-template <int D>
+// W nodes of level lev+1 put the cells of level lev into W whose children's
+// radius-2 neighbourhood (fine offsets -2..3 per axis) holds them: per axis
+// the coarse cells (y >> 1) + {-1, 0, 1}, mapped by the boundary conditions
+template <int D, int G>
 __global__ __launch_bounds__(TPB) void k_close(Geo g, Dev p, int lev) {
-  const int64_t nl = g.n[lev], N = g.B * nl;
-  const int nf = 1 << (lev + 1);
-  GSL(t, N) {
-    if (inst_of_window_skip(g, t, D * lev)) continue;
-    const int64_t G = g.off[lev] + t;
-    const uint8_t r = p.rf[G];
-    if (r & 2) continue;
-    const int64_t inst = t >> (D * lev);
-    int x[3];
-    mdec<D>((uint64_t)(t & (nl - 1)), x);
-    const int64_t ibf = g.off[lev + 1] + inst * g.n[lev + 1];
-    bool w = false;
-    for (int oz = (D > 2 ? -2 : 0); oz <= (D > 2 ? 3 : 0) && !w; oz++)
-      for (int oy = (D > 1 ? -2 : 0); oy <= (D > 1 ? 3 : 0) && !w; oy++)
-        for (int ox = -2; ox <= 3 && !w; ox++) {
-          int y[3] = {map_nb(2 * x[0] + ox, nf, g.periodic[0]), 0, 0};
-          if (D > 1) y[1] = map_nb(2 * x[1] + oy, nf, g.periodic[1]);
-          if (D > 2) y[2] = map_nb(2 * x[2] + oz, nf, g.periodic[2]);
-          if (y[0] < 0 || y[1] < 0 || y[2] < 0) continue;
-          if (p.rf[ibf + (int64_t)menc<D>(y)] & 2) w = true;
-        }
-    if (w) p.rf[G] = r | 2;
+  __shared__ int sh[TPB];
+  __shared__ int items[TPB * G];
+  const int lf = lev + 1;
+  const int64_t nf = g.n[lf], N = g.B * nf;
+  const int nc = 1 << lev;
+  const uint8_t* rff = p.rf + g.off[lf];
+  for (int64_t tb = (int64_t)blockIdx.x * (TPB * G); tb < N; tb += (int64_t)gridDim.x * (TPB * G)) {
+    if (p.wsum[g.bs_off[lf] + (tb >> BS_SHIFT)] == 0) continue;  // no W in the block
+    const int64_t t0 = tb + (int64_t)threadIdx.x * G;
+    const uint32_t mask = t0 < N ? w_mask<G>(g, ldg<G>(rff, t0, N), t0, D * lf) : 0u;
+    const int cnt = block_items<G>(mask, items, sh);
+    for (int i = threadIdx.x; i < cnt; i += TPB) {
+      const int64_t t = tb + items[i];
+      const int64_t inst = t >> (D * lf);
+      const int64_t ibc = inst * g.n[lev];
+      int y[3];
+      mdec<D>((uint64_t)(t & (nf - 1)), y);
+      constexpr int NN = D == 1 ? 3 : (D == 2 ? 9 : 27);
+      uint32_t need = 0u;
+#pragma unroll
+      for (int o = 0; o < NN; o++) {
+        const int ox = o % 3 - 1, oy = D > 1 ? (o / 3) % 3 - 1 : 0, oz = D > 2 ? o / 9 - 1 : 0;
+        int X[3] = {map_nb((y[0] >> 1) + ox, nc, g.periodic[0]), 0, 0};
+        if (D > 1) X[1] = map_nb((y[1] >> 1) + oy, nc, g.periodic[1]);
+        if (D > 2) X[2] = map_nb((y[2] >> 1) + oz, nc, g.periodic[2]);
+        if (X[0] < 0 || X[1] < 0 || X[2] < 0) continue;
+        if (!(p.rf[g.off[lev] + ibc + (int64_t)menc<D>(X)] & RF_W)) need |= 1u << o;
+      }
+#pragma unroll
+      for (int o = 0; o < NN; o++) {
+        if (!((need >> o) & 1u)) continue;
+        const int ox = o % 3 - 1, oy = D > 1 ? (o / 3) % 3 - 1 : 0, oz = D > 2 ? o / 9 - 1 : 0;
+        int X[3] = {map_nb((y[0] >> 1) + ox, nc, g.periodic[0]), 0, 0};
+        if (D > 1) X[1] = map_nb((y[1] >> 1) + oy, nc, g.periodic[1]);
+        if (D > 2) X[2] = map_nb((y[2] >> 1) + oz, nc, g.periodic[2]);
+        mark_w(g, p, lev, ibc + (int64_t)menc<D>(X));
+      }
+    }
+    __syncthreads();
   }
 }
 
-template <int D>
+// a W node of level lev > l0 stays in W only if the 3^d neighbourhood of its
+// parent is in W (levels >= la) or internal (frozen levels)
+template <int D, int G>
 __global__ __launch_bounds__(TPB) void k_prune(Geo g, Dev p, int lev, int la) {
+  __shared__ int sh[TPB];
+  __shared__ int items[TPB * G];
   const int64_t nl = g.n[lev], N = g.B * nl;
   const int np = 1 << (lev - 1);
-  GSL(t, N) {
-    if (inst_of_window_skip(g, t, D * lev)) continue;
-    const int64_t G = g.off[lev] + t;
-    const uint8_t r = p.rf[G];
-    if (!(r & 2) || lev == g.l0) continue;
-    const int64_t inst = t >> (D * lev);
-    int x[3];
-    mdec<D>((uint64_t)(t & (nl - 1)), x);
-    const int px[3] = {x[0] >> 1, x[1] >> 1, x[2] >> 1};
-    const int64_t ibp = g.off[lev - 1] + inst * g.n[lev - 1];
-    bool ok = true;
-    for (int oz = (D > 2 ? -1 : 0); oz <= (D > 2 ? 1 : 0) && ok; oz++)
-      for (int oy = (D > 1 ? -1 : 0); oy <= (D > 1 ? 1 : 0) && ok; oy++)
-        for (int ox = -1; ox <= 1 && ok; ox++) {
-          int y[3] = {map_nb(px[0] + ox, np, g.periodic[0]), 0, 0};
-          if (D > 1) y[1] = map_nb(px[1] + oy, np, g.periodic[1]);
-          if (D > 2) y[2] = map_nb(px[2] + oz, np, g.periodic[2]);
-          if (y[0] < 0 || y[1] < 0 || y[2] < 0) continue;
-          const int64_t Gp = ibp + (int64_t)menc<D>(y);
-          ok = (lev - 1 >= la) ? ((p.rf[Gp] & 2) != 0) : (p.st[Gp] == ST_INTERNAL);
-        }
-    if (!ok) p.rf[G] = r & ~2;
+  uint8_t* rfl = p.rf + g.off[lev];
+  for (int64_t tb = (int64_t)blockIdx.x * (TPB * G); tb < N; tb += (int64_t)gridDim.x * (TPB * G)) {
+    if (p.wsum[g.bs_off[lev] + (tb >> BS_SHIFT)] == 0) continue;  // no W in the block
+    const int64_t t0 = tb + (int64_t)threadIdx.x * G;
+    const uint32_t mask = t0 < N ? w_mask<G>(g, ldg<G>(rfl, t0, N), t0, D * lev) : 0u;
+    const int cnt = block_items<G>(mask, items, sh);
+    for (int i = threadIdx.x; i < cnt; i += TPB) {
+      const int64_t t = tb + items[i];
+      const int64_t inst = t >> (D * lev);
+      int x[3];
+      mdec<D>((uint64_t)(t & (nl - 1)), x);
+      const int px[3] = {x[0] >> 1, x[1] >> 1, x[2] >> 1};
+      const int64_t ibp = g.off[lev - 1] + inst * g.n[lev - 1];
+      bool ok = true;
+#pragma unroll
+      for (int oz = (D > 2 ? -1 : 0); oz <= (D > 2 ? 1 : 0); oz++)
+#pragma unroll
+        for (int oy = (D > 1 ? -1 : 0); oy <= (D > 1 ? 1 : 0); oy++)
+#pragma unroll
+          for (int ox = -1; ox <= 1; ox++) {
+            int y[3] = {map_nb(px[0] + ox, np, g.periodic[0]), 0, 0};
+            if (D > 1) y[1] = map_nb(px[1] + oy, np, g.periodic[1]);
+            if (D > 2) y[2] = map_nb(px[2] + oz, np, g.periodic[2]);
+            if (y[0] < 0 || y[1] < 0 || y[2] < 0) continue;
+            const int64_t Gp = ibp + (int64_t)menc<D>(y);
+            const bool in = (lev - 1 >= la) ? ((p.rf[Gp] & RF_W) != 0) : (p.st[Gp] == ST_INTERNAL);
+            ok = ok && in;
+          }
+      if (!ok) rfl[t] = 0;  // the byte holds only the W bit
+    }
+    __syncthreads();
   }
 }
 
-template <int D>
+// summary bits of eight packed statuses
+__device__ __forceinline__ unsigned group_summary(uint64_t s) {
+  const uint64_t lo = s & 0x0101010101010101ull, hi = (s >> 1) & 0x0101010101010101ull;
+  return (s ? BS_EXIST : 0u) | (lo ? BS_LEAF : 0u) | (hi ? BS_INT : 0u);
+}
+
+// new status of the cells of level lev (parents already updated); cells
+// that come into existence get the value predicted from the parent level
+template <int D, int G>
 __global__ __launch_bounds__(TPB) void k_apply(Geo g, Dev p, int lev, int la) {
+  __shared__ int sh[TPB];
+  __shared__ int items[TPB * G];
+  __shared__ unsigned bor;
   const int64_t nl = g.n[lev], N = g.B * nl;
-  GSL(t, N) {
-    if (inst_of_window_skip(g, t, D * lev)) continue;
-    const int64_t G = g.off[lev] + t;
-    const uint8_t old = p.st[G];
-    const bool w = (p.rf[G] & 2) != 0;
-    uint8_t nw;
-    if (lev == la) {
-      nw = old == ST_ABSENT ? ST_ABSENT : (w ? ST_INTERNAL : ST_LEAF);
-    } else {
-      const uint8_t ps = p.st[g.off[lev - 1] + (t >> D)];
-      nw = ps == ST_INTERNAL ? ((lev <= g.L - 1 && w) ? ST_INTERNAL : ST_LEAF) : ST_ABSENT;
+  uint8_t* stl = p.st + g.off[lev];
+  const uint8_t* stp = p.st + g.off[lev - 1];
+  if (threadIdx.x == 0) bor = 0u;
+  __syncthreads();
+  for (int64_t tb = (int64_t)blockIdx.x * (TPB * G); tb < N; tb += (int64_t)gridDim.x * (TPB * G)) {
+    // nothing exists in the block and no parent is internal: it stays absent
+    const int64_t sb = tb >> BS_SHIFT;
+    if (!(bsum_of(g, p, lev, sb) & BS_EXIST) && (lev == la || !(bsum_of(g, p, lev - 1, sb >> D) & BS_INT)))
+      continue;
+    const int64_t t0 = tb + (int64_t)threadIdx.x * G;
+    uint32_t mask = 0u;
+    if (t0 < N) {
+      const uint4 so = ldg<G>(stl, t0, N);
+      const uint64_t par = lev > la ? ld_parents<D, G>(stp, t0, N) : 0ull;
+      // a parent that is internal after the update has all its children
+      bool par_int = false;
+#pragma unroll
+      for (int k = 0; k < (G == 1 ? 1 : (16 >> D)); k++) par_int = par_int || ((par >> (8 * k)) & 0xff) == ST_INTERNAL;
+      // nothing exists and nothing will: the group stays absent
+      if (any16(so, 0xffffffffu) || par_int) {
+        const uint4 wv = lev <= g.L - 1 ? ldg<G>(p.rf + g.off[lev], t0, N) : make_uint4(0u, 0u, 0u, 0u);
+        uint64_t nlo = 0ull, nhi = 0ull;  // new statuses of cells 0-7, 8-15
+#pragma unroll
+        for (int j = 0; j < G; j++) {
+          const int64_t t = t0 + j;
+          const uint8_t old = byte_of(so, j);
+          uint8_t nw = old;
+          if (t < N && !inst_of_window_skip(g, t, D * lev)) {
+            const bool w = (byte_of(wv, j) & RF_W) != 0;
+            if (lev == la) {
+              nw = old == ST_ABSENT ? ST_ABSENT : (w ? ST_INTERNAL : ST_LEAF);
+            } else {
+              const uint8_t ps = (uint8_t)(par >> (8 * (G == 1 ? 0 : (j >> D))));
+              nw = ps == ST_INTERNAL ? ((lev <= g.L - 1 && w) ? ST_INTERNAL : ST_LEAF) : ST_ABSENT;
+            }
+            if (lev > la && old == ST_ABSENT && nw != ST_ABSENT) mask |= 1u << j;
+          }
+          if (j < 8) nlo |= (uint64_t)nw << (8 * j);
+          else nhi |= (uint64_t)nw << (8 * (j - 8));
+        }
+        if (G == 1) {
+          stl[t0] = (uint8_t)nlo;
+        } else if (t0 + 16 <= N) {
+          *reinterpret_cast<uint4*>(stl + t0) =
+              make_uint4((uint32_t)nlo, (uint32_t)(nlo >> 32), (uint32_t)nhi, (uint32_t)(nhi >> 32));
+        } else {
+          for (int j = 0; t0 + j < N; j++) stl[t0 + j] = (uint8_t)(j < 8 ? nlo >> (8 * j) : nhi >> (8 * (j - 8)));
+        }
+        const unsigned bits = group_summary(nlo) | group_summary(nhi);
+        if (bits) atomicOr(&bor, bits);
+      }
     }
-    p.st[G] = nw;
-    if (lev > la && old == ST_ABSENT && nw != ST_ABSENT) {
+    const int cnt = block_items<G>(mask, items, sh);
+    // G = 16 blocks are the summary blocks; G = 1 levels keep no summary
+    if (threadIdx.x == 0) {
+      if (G == 16) p.bsum[g.bs_off[lev] + sb] = (uint8_t)bor;
+      bor = 0u;
+    }
+    for (int i = threadIdx.x; i < cnt; i += TPB) {
+      const int64_t t = tb + items[i];
       const int64_t inst = t >> (D * lev);
       int x[3];
       mdec<D>((uint64_t)(t & (nl - 1)), x);
@@ -1065,44 +1317,24 @@ __global__ __launch_bounds__(TPB) void k_apply(Geo g, Dev p, int lev, int la) {
         double S[27], T[8];
         if (!gather27<D>(g, p, p.q[SL_Q0], lev - 1, ibp, px, k, S)) flag_bad(p, inst, 32);
         pred_terms<D>(S, T);
-        p.q[SL_Q0][(int64_t)k * g.Ntot + G] = pred_child<D>(T, cb);
+        p.q[SL_Q0][(int64_t)k * g.Ntot + g.off[lev] + t] = pred_child<D>(T, cb);
       }
     }
-  }
-}
-
-// absent cells that a leaf stencil (normal offsets 1 and 2) reads; their
-// parent is then a leaf (grading), the virtual leaves of Fig. 1
-template <int D>
-__global__ __launch_bounds__(TPB) void k_ghost_flags(Geo g, Dev p, int lo, int hi) {
-  MULTI_LEVEL_LOOP(G, lev, lo, hi) {
-    const int64_t nl = g.n[lev];
-    const int n = 1 << lev;
-    const int64_t t = G - g.off[lev];
-    uint8_t need = 0;
-    if (p.st[G] == ST_ABSENT && p.st[g.off[lev - 1] + (t >> D)] == ST_LEAF) {
-      const int64_t inst = t >> (D * lev);
-      const int64_t ib = g.off[lev] + inst * nl;
-      int x[3];
-      mdec<D>((uint64_t)(t & (nl - 1)), x);
-      for (int dir = 0; dir < D && !need; dir++)
-        for (int o = -2; o <= 2 && !need; o++) {
-          if (o == 0) continue;
-          const int u = map_nb(x[dir] - o, n, g.periodic[dir]);
-          if (u < 0) continue;
-          int y[3] = {x[0], x[1], x[2]};
-          y[dir] = u;
-          if (p.st[ib + (int64_t)menc<D>(y)] == ST_LEAF) need = 1;
-        }
-    }
-    p.gh[G] = need;
+    __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
-// ordered list compaction of levels lo..L: wavefront ballot + popcount per
-// block, an exclusive scan per level, then each block writes its cells at
-// their rank (list order = Morton order within an instance)
+// ordered compaction of the per-level lists of levels lo..L: leaves,
+// internal nodes, interface leaves (below L, with an internal face
+// neighbour) and virtual cells (absent cells that a leaf stencil reads at
+// offsets 1 and 2 along an axis; their parent is then a leaf by grading:
+// the virtual leaves of Fig. 1).  Per-block counts, an exclusive scan per
+// level, then each block writes its cells at their rank (list order =
+// Morton order within an instance).  On levels with >= 4096 cells a lane
+// classifies a 16-cell Morton group (extent 16, 4x4 or 4x2x2) from the
+// group and its 2d face-adjacent groups, one 16-byte load each; on smaller
+// levels a lane takes one cell.
 
 __device__ __forceinline__ int comp_level(const Geo& g, int lo, int64_t b) {
   int lev = lo;
@@ -1110,154 +1342,362 @@ __device__ __forceinline__ int comp_level(const Geo& g, int lo, int64_t b) {
   return lev;
 }
 
-// leaf of a level below L with a refined (internal) face neighbour
+// list k of the packed counts (16 bits each) and codes (4 bits per cell)
+static constexpr int NCL = 4;
+__device__ __forceinline__ constexpr int clist(int k) {
+  return k == 0 ? LS_LEAF : (k == 1 ? LS_INTERNAL : (k == 2 ? LS_IFACE : LS_GHOST));
+}
+__device__ __forceinline__ uint64_t code_count(uint32_t c) {
+  return (uint64_t)(c & 1u) | ((uint64_t)((c >> 1) & 1u) << 16) | ((uint64_t)((c >> 2) & 1u) << 32) |
+         ((uint64_t)((c >> 3) & 1u) << 48);
+}
+static constexpr uint32_t CODE_LEAF = 1u, CODE_INT = 2u, CODE_IFACE = 4u, CODE_GHOST = 8u;
+
+// one cell, direct loads
 template <int D>
-__device__ __forceinline__ bool refined_face(const Geo& g, const Dev& p, int lev, int64_t t) {
+__device__ __forceinline__ uint32_t cell_code(const Geo& g, const Dev& p, int lev, int64_t t) {
   const int64_t nl = g.n[lev];
+  const uint8_t st = p.st[g.off[lev] + t];
+  if (st == ST_INTERNAL) return CODE_INT;
+  const bool leaf = st == ST_LEAF;
+  if (leaf && lev == g.L) return CODE_LEAF;
+  if (!leaf && (lev == g.l0 || p.st[g.off[lev - 1] + (t >> D)] != ST_LEAF)) return 0u;
   const int n = 1 << lev;
   const int64_t ib = g.off[lev] + (t >> (D * lev)) * nl;
   int x[3];
   mdec<D>((uint64_t)(t & (nl - 1)), x);
-  bool r = false;
+  bool hit = false;
 #pragma unroll
   for (int dir = 0; dir < D; dir++)
 #pragma unroll
-    for (int side = 0; side < 2; side++) {
-      const int nb = map_nb(x[dir] + (side ? 1 : -1), n, g.periodic[dir]);
-      if (nb < 0) continue;
+    for (int o = -2; o <= 2; o++) {
+      if (o == 0 || (leaf && (o == -2 || o == 2))) continue;
+      const int u = map_nb(x[dir] + o, n, g.periodic[dir]);
+      if (u < 0) continue;
       int y[3] = {x[0], x[1], x[2]};
-      y[dir] = nb;
-      r = r || p.st[ib + (int64_t)menc<D>(y)] == ST_INTERNAL;
+      y[dir] = u;
+      hit = hit || p.st[ib + (int64_t)menc<D>(y)] == (leaf ? ST_INTERNAL : ST_LEAF);
     }
+  if (leaf) return hit ? (CODE_LEAF | CODE_IFACE) : CODE_LEAF;
+  return hit ? CODE_GHOST : 0u;
+}
+
+// 16-cell Morton groups: extent per axis and local coordinates of cell j
+template <int D>
+__device__ __forceinline__ constexpr int gw(int a) {
+  return D == 1 ? 16 : (D == 2 ? 4 : (a == 0 ? 4 : 2));
+}
+template <int D>
+__device__ __forceinline__ constexpr int lco(int j, int a) {
+  return D == 1 ? j
+         : D == 2 ? (a == 0 ? ((j & 1) | (((j >> 2) & 1) << 1)) : (((j >> 1) & 1) | (((j >> 3) & 1) << 1)))
+                  : (a == 0 ? ((j & 1) | (((j >> 3) & 1) << 1)) : (a == 1 ? ((j >> 1) & 1) : ((j >> 2) & 1)));
+}
+template <int D>
+__device__ __forceinline__ constexpr int lidx(int lx, int ly, int lz) {
+  return D == 1 ? lx
+         : D == 2 ? ((lx & 1) | ((ly & 1) << 1) | (((lx >> 1) & 1) << 2) | (((ly >> 1) & 1) << 3))
+                  : ((lx & 1) | ((ly & 1) << 1) | ((lz & 1) << 2) | (((lx >> 1) & 1) << 3));
+}
+
+struct GroupNbhd {
+  uint4 c, m[3], p[3];   // the group, its lower and upper neighbours per axis
+  bool vm[3], vp[3];     // neighbour group inside the domain
+};
+
+// status of the cell at offset o along axis a from cell j (3: outside)
+template <int D>
+__device__ __forceinline__ uint8_t nb_status(const GroupNbhd& h, int j, int a, int o) {
+  int l[3] = {lco<D>(j, 0), D > 1 ? lco<D>(j, 1) : 0, D > 2 ? lco<D>(j, 2) : 0};
+  const int w = gw<D>(a);
+  const int v = l[a] + o;
+  if (v >= 0 && v < w) {
+    l[a] = v;
+    return byte_of(h.c, lidx<D>(l[0], l[1], l[2]));
+  }
+  if (v < 0) {
+    if (!h.vm[a]) return 3;
+    l[a] = v + w;
+    return byte_of(h.m[a], lidx<D>(l[0], l[1], l[2]));
+  }
+  if (!h.vp[a]) return 3;
+  l[a] = v - w;
+  return byte_of(h.p[a], lidx<D>(l[0], l[1], l[2]));
+}
+
+// codes of the 16 cells of the group at t0 (4 bits each)
+template <int D>
+__device__ __forceinline__ uint64_t group_codes(const Geo& g, const Dev& p, int lev, int64_t t0) {
+  const int64_t nl = g.n[lev];
+  const uint8_t* stl = p.st + g.off[lev];
+  GroupNbhd h;
+  h.c = *reinterpret_cast<const uint4*>(stl + t0);
+  const uint64_t par = lev > g.l0 ? ld_parents<D>(p.st + g.off[lev - 1], t0, g.B * nl) : 0ull;
+  bool par_leaf = false;
+#pragma unroll
+  for (int k = 0; k < (16 >> D); k++) par_leaf = par_leaf || ((par >> (8 * k)) & 0xff) == ST_LEAF;
+  const bool any_leaf = any16(h.c, 0x01010101u);
+  uint64_t codes = 0ull;
+  if (!any_leaf && !par_leaf) {
+#pragma unroll
+    for (int j = 0; j < 16; j++)
+      if (byte_of(h.c, j) == ST_INTERNAL) codes |= (uint64_t)CODE_INT << (4 * j);
+    return codes;
+  }
+  const int n = 1 << lev;
+  const int64_t ib = g.off[lev] + (t0 >> (D * lev)) * nl;
+  int x0[3];
+  mdec<D>((uint64_t)(t0 & (nl - 1)), x0);
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    h.vm[a] = h.vp[a] = false;
+    h.m[a] = h.p[a] = make_uint4(0u, 0u, 0u, 0u);
+    if (a >= D) continue;
+#pragma unroll
+    for (int s = 0; s < 2; s++) {
+      const int u = map_nb(x0[a] + (s ? gw<D>(a) : -gw<D>(a)), n, g.periodic[a]);
+      if (u < 0) continue;
+      int y[3] = {x0[0], x0[1], x0[2]};
+      y[a] = u;
+      const uint4 v = *reinterpret_cast<const uint4*>(p.st + ib + (int64_t)menc<D>(y));
+      if (s) { h.p[a] = v; h.vp[a] = true; } else { h.m[a] = v; h.vm[a] = true; }
+    }
+  }
+  // virtual cells need a leaf of the level within two cells, interface
+  // leaves an internal face neighbour: both read the loaded neighbourhood
+  uint4 u = h.c;
+#pragma unroll
+  for (int a = 0; a < D; a++) {
+    u.x |= h.m[a].x | h.p[a].x; u.y |= h.m[a].y | h.p[a].y;
+    u.z |= h.m[a].z | h.p[a].z; u.w |= h.m[a].w | h.p[a].w;
+  }
+  const bool nb_leaf = any16(u, 0x01010101u), nb_int = lev < g.L && any16(u, 0x02020202u);
+#pragma unroll
+  for (int j = 0; j < 16; j++) {
+    const uint8_t st = byte_of(h.c, j);
+    uint32_t c = 0u;
+    if (st == ST_INTERNAL) {
+      c = CODE_INT;
+    } else if (st == ST_LEAF) {
+      bool ref = false;
+      if (nb_int) {
+#pragma unroll
+        for (int a = 0; a < D; a++) ref = ref || nb_status<D>(h, j, a, -1) == ST_INTERNAL || nb_status<D>(h, j, a, 1) == ST_INTERNAL;
+      }
+      c = ref ? (CODE_LEAF | CODE_IFACE) : CODE_LEAF;
+    } else if (nb_leaf && ((par >> (8 * (j >> D))) & 0xff) == ST_LEAF) {
+      bool rd = false;
+#pragma unroll
+      for (int a = 0; a < D; a++)
+#pragma unroll
+        for (int o = -2; o <= 2; o++)
+          if (o != 0) rd = rd || nb_status<D>(h, j, a, o) == ST_LEAF;
+      c = rd ? CODE_GHOST : 0u;
+    }
+    codes |= (uint64_t)c << (4 * j);
+  }
+  return codes;
+}
+
+// per-lane cell range of block b: [t0, t0 + cpt)
+struct CompRange {
+  int lev, cpt;
+  int64_t t0, tb;  // first cell of the lane, of the block
+  bool act;
+};
+__device__ __forceinline__ CompRange comp_range(const Geo& g, int lo, int64_t b) {
+  CompRange r;
+  r.lev = comp_level(g, lo, b);
+  const int chunk = g.comp_chunk[r.lev];
+  r.cpt = chunk > TPB ? chunk / TPB : 1;
+  r.tb = (b - g.comp_first[r.lev]) * (int64_t)chunk;
+  r.t0 = r.tb + (int64_t)threadIdx.x * r.cpt;
+  r.act = (int)threadIdx.x * r.cpt < chunk;
   return r;
 }
 
+// a block with no existing cell whose parents hold no leaf has nothing to
+// list (virtual cells are children of leaves); decided from the summaries
+// a block lists nothing when no cell of it exists and no leaf of its level
+// lies in it or in an adjacent 4096-cell tile (a virtual cell is within two
+// cells of a leaf of its level); 4096-cell blocks of a level are tiles of
+// 4096, 64x64 or 16x16x16 cells in Morton order
 template <int D>
-__device__ __forceinline__ void cell_types(const Geo& g, const Dev& p, int lev, int64_t t, int* c) {
-  const int64_t G = g.off[lev] + t;
-  const uint8_t st = p.st[G];
-  c[LS_LEAF] = st == ST_LEAF;
-  c[LS_INTERNAL] = st == ST_INTERNAL;
-  c[LS_GHOST] = p.gh[G] != 0;
-  c[LS_IFACE] = st == ST_LEAF && lev < g.L && refined_face<D>(g, p, lev, t);
-}
-
-// exclusive scan of v over the 256 threads of a block; returns the prefix,
-// *tot receives the block total
-__device__ __forceinline__ int block_exscan(int v, int* sh, int* tot) {
-  const int tid = threadIdx.x;
-  sh[tid] = v;
-  __syncthreads();
-  for (int o = 1; o < TPB; o <<= 1) {
-    const int a = tid >= o ? sh[tid - o] : 0;
-    __syncthreads();
-    sh[tid] += a;
-    __syncthreads();
+__device__ __forceinline__ bool comp_skip(const Geo& g, const Dev& p, const CompRange& r) {
+  if (!wide_level(g, r.lev)) return false;
+  const int64_t sb = r.tb >> BS_SHIFT;
+  const uint8_t* bs = p.bsum + g.bs_off[r.lev];
+  if (bs[sb] & BS_EXIST) return false;
+  const int64_t tpi = g.n[r.lev] >> BS_SHIFT;  // tiles per instance
+  const int64_t i0 = sb - (sb & (tpi - 1));
+  const int nt = D == 1 ? (int)tpi : (D == 2 ? (1 << (r.lev - 6)) : (1 << (r.lev - 4)));
+  int x[3];
+  mdec<D>((uint64_t)(sb & (tpi - 1)), x);
+  bool leaf = false;
+#pragma unroll
+  for (int o = 0; o < (D == 1 ? 3 : (D == 2 ? 9 : 27)); o++) {
+    const int ox = o % 3 - 1, oy = D > 1 ? (o / 3) % 3 - 1 : 0, oz = D > 2 ? o / 9 - 1 : 0;
+    int y[3] = {map_nb(x[0] + ox, nt, g.periodic[0]), 0, 0};
+    if (D > 1) y[1] = map_nb(x[1] + oy, nt, g.periodic[1]);
+    if (D > 2) y[2] = map_nb(x[2] + oz, nt, g.periodic[2]);
+    if (y[0] < 0 || y[1] < 0 || y[2] < 0) continue;
+    leaf = leaf || (bs[i0 + (int64_t)menc<D>(y)] & BS_LEAF);
   }
-  const int incl = sh[tid];
-  *tot = sh[TPB - 1];
-  __syncthreads();
-  return incl - v;
+  return !leaf;
 }
 
+// packed counts of the lane's cells; *codes gets 4 bits per cell
 template <int D>
-__global__ __launch_bounds__(TPB) void k_comp_count(Geo g, Dev p, int lo) {
-  __shared__ int sh[TPB];
+__device__ __forceinline__ uint64_t lane_counts(const Geo& g, const Dev& p, const CompRange& r, bool skip,
+                                                uint64_t* codes) {
+  uint64_t c = 0ull, cd = 0ull;
+  if (r.act && !skip) {
+    if (r.cpt == GRP) {
+      cd = group_codes<D>(g, p, r.lev, r.t0);
+    } else {
+      for (int j = 0; j < r.cpt; j++) cd |= (uint64_t)cell_code<D>(g, p, r.lev, r.t0 + j) << (4 * j);
+    }
+    for (int j = 0; j < r.cpt; j++) c += code_count((uint32_t)(cd >> (4 * j)) & 15u);
+  }
+  *codes = cd;
+  return c;
+}
+
+// full: statuses changed outside the remesh, the summaries are not trusted
+template <int D>
+__global__ __launch_bounds__(TPB) void k_comp_count(Geo g, Dev p, int lo, int full) {
+  __shared__ uint64_t sh[TPB];
   const int64_t nbt = g.comp_first[g.L + 1];
   const int64_t b = g.comp_first[lo] + blockIdx.x;
-  const int lev = comp_level(g, lo, b);
-  const int chunk = g.comp_chunk[lev];
-  const int cpt = chunk > TPB ? chunk / TPB : 1;
-  const int64_t t0 = (b - g.comp_first[lev]) * (int64_t)chunk + (int64_t)threadIdx.x * cpt;
-  int c[LS_COUNT] = {};
-  if ((int)threadIdx.x * cpt < chunk)
-    for (int j = 0; j < cpt; j++) {
-      int e[LS_COUNT];
-      cell_types<D>(g, p, lev, t0 + j, e);
-      for (int k = 0; k < LS_COUNT; k++) c[k] += e[k];
-    }
-  for (int k = 0; k < LS_COUNT; k++) {
-    int tot;
-    block_exscan(c[k], sh, &tot);
-    if (threadIdx.x == 0) p.bcnt[k * nbt + b] = tot;
+  const CompRange r = comp_range(g, lo, b);
+  const bool skip = !full && comp_skip<D>(g, p, r);
+  if (skip) {
+    if (threadIdx.x < NCL) p.bcnt[clist(threadIdx.x) * nbt + b] = 0;
+    return;
   }
+  uint64_t codes, tot;
+  block_exscan<uint64_t>(lane_counts<D>(g, p, r, false, &codes), sh, &tot);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < NCL; k++) p.bcnt[clist(k) * nbt + b] = (int)((tot >> (16 * k)) & 0xffffull);
 }
 
-// one workgroup per level: per-instance leaf counts, then exclusive scans of
-// the block counts in place and the list lengths
+// one workgroup per level: exclusive scans of the block counts of the four
+// lists in place, the list lengths and the leaves per instance
 __global__ __launch_bounds__(TPB) void k_comp_scan(Geo g, Dev p, int lo) {
-  __shared__ int sh[TPB];
+  __shared__ int4 sh[TPB];
   const int lev = lo + blockIdx.x;
   const int64_t nbt = g.comp_first[g.L + 1];
   const int64_t b0 = g.comp_first[lev];
   const int nb = (int)(g.comp_first[lev + 1] - b0);
   const int bpi = (int)(g.n[lev] / g.comp_chunk[lev]);  // blocks per instance
-  for (int inst = threadIdx.x; inst < g.B; inst += TPB) {
-    int sum = 0;
-    for (int k = 0; k < bpi; k++) sum += p.bcnt[LS_LEAF * nbt + b0 + (int64_t)inst * bpi + k];
-    p.leafcnt[inst * (MRD_MAXLEV + 1) + lev] = sum;
-  }
-  __syncthreads();
+  int* bc[NCL];
+#pragma unroll
+  for (int k = 0; k < NCL; k++) bc[k] = p.bcnt + clist(k) * nbt + b0;
   const int per = (nb + TPB - 1) / TPB;
   const int j0 = threadIdx.x * per;
   const int j1 = j0 + per < nb ? j0 + per : nb;
-  for (int k = 0; k < LS_COUNT; k++) {
-    int* bc = p.bcnt + k * nbt + b0;
-    int loc = 0;
-    for (int j = j0; j < j1; j++) loc += bc[j];
-    int tot;
-    int run = block_exscan(loc, sh, &tot);
-    for (int j = j0; j < j1; j++) {
-      const int v = bc[j];
-      bc[j] = run;
-      run += v;
+  // up to 16 blocks per thread: all loads in flight at once
+  constexpr int PMAX = 16;
+  int4 v[PMAX];
+  int4 loc = make_int4(0, 0, 0, 0);
+  if (per <= PMAX) {
+#pragma unroll
+    for (int q = 0; q < PMAX; q++) {
+      const int j = j0 + q;
+      v[q] = j < j1 ? make_int4(bc[0][j], bc[1][j], bc[2][j], bc[3][j]) : make_int4(0, 0, 0, 0);
     }
-    if (threadIdx.x == 0) p.lcnt[k * (MRD_MAXLEV + 1) + lev] = tot;
+#pragma unroll
+    for (int q = 0; q < PMAX; q++) {
+      loc.x += v[q].x; loc.y += v[q].y; loc.z += v[q].z; loc.w += v[q].w;
+    }
+  } else {
+    for (int j = j0; j < j1; j++) {
+      loc.x += bc[0][j]; loc.y += bc[1][j]; loc.z += bc[2][j]; loc.w += bc[3][j];
+    }
+  }
+  // Hillis-Steele scan of the per-thread sums
+  const int tid = threadIdx.x;
+  sh[tid] = loc;
+  __syncthreads();
+  for (int o = 1; o < TPB; o <<= 1) {
+    const int4 v = tid >= o ? sh[tid - o] : make_int4(0, 0, 0, 0);
     __syncthreads();
+    sh[tid].x += v.x; sh[tid].y += v.y; sh[tid].z += v.z; sh[tid].w += v.w;
+    __syncthreads();
+  }
+  const int4 incl = sh[tid], tot = sh[TPB - 1];
+  int4 run = make_int4(incl.x - loc.x, incl.y - loc.y, incl.z - loc.z, incl.w - loc.w);
+  if (per <= PMAX) {
+#pragma unroll
+    for (int q = 0; q < PMAX; q++) {
+      const int j = j0 + q;
+      if (j < j1) {
+        bc[0][j] = run.x; bc[1][j] = run.y; bc[2][j] = run.z; bc[3][j] = run.w;
+      }
+      run.x += v[q].x; run.y += v[q].y; run.z += v[q].z; run.w += v[q].w;
+    }
+  } else {
+    for (int j = j0; j < j1; j++) {
+      const int4 w = make_int4(bc[0][j], bc[1][j], bc[2][j], bc[3][j]);
+      bc[0][j] = run.x; bc[1][j] = run.y; bc[2][j] = run.z; bc[3][j] = run.w;
+      run.x += w.x; run.y += w.y; run.z += w.z; run.w += w.w;
+    }
+  }
+  if (tid == 0) {
+    p.lcnt[clist(0) * (MRD_MAXLEV + 1) + lev] = tot.x;
+    p.lcnt[clist(1) * (MRD_MAXLEV + 1) + lev] = tot.y;
+    p.lcnt[clist(2) * (MRD_MAXLEV + 1) + lev] = tot.z;
+    p.lcnt[clist(3) * (MRD_MAXLEV + 1) + lev] = tot.w;
+  }
+  __syncthreads();
+  for (int inst = tid; inst < g.B; inst += TPB) {
+    const int s = bc[0][(int64_t)inst * bpi];
+    const int e = inst + 1 < g.B ? bc[0][(int64_t)(inst + 1) * bpi] : tot.x;
+    p.leafcnt[inst * (MRD_MAXLEV + 1) + lev] = e - s;
   }
 }
 
 template <int D>
-__global__ __launch_bounds__(TPB) void k_comp_write(Geo g, Dev p, int lo) {
-  __shared__ int sh[TPB];
+__global__ __launch_bounds__(TPB) void k_comp_write(Geo g, Dev p, int lo, int full) {
+  __shared__ uint64_t sh[TPB];
   const int64_t nbt = g.comp_first[g.L + 1];
   const int64_t b = g.comp_first[lo] + blockIdx.x;
-  const int lev = comp_level(g, lo, b);
-  const int chunk = g.comp_chunk[lev];
-  const int cpt = chunk > TPB ? chunk / TPB : 1;
-  const int64_t tb = (b - g.comp_first[lev]) * (int64_t)chunk;
-  const int64_t t0 = tb + (int64_t)threadIdx.x * cpt;
-  const bool act = (int)threadIdx.x * cpt < chunk;
-  int c[LS_COUNT] = {};
-  if (act)
-    for (int j = 0; j < cpt; j++) {
-      int e[LS_COUNT];
-      cell_types<D>(g, p, lev, t0 + j, e);
-      for (int k = 0; k < LS_COUNT; k++) c[k] += e[k];
-    }
-  int base[LS_COUNT];
-  for (int k = 0; k < LS_COUNT; k++) {
-    int tot;
-    base[k] = p.bcnt[k * nbt + b] + block_exscan(c[k], sh, &tot);
+  const CompRange r = comp_range(g, lo, b);
+  if (!full && comp_skip<D>(g, p, r)) return;
+  uint64_t codes, tot;
+  const uint64_t c = lane_counts<D>(g, p, r, false, &codes);
+  const uint64_t ex = block_exscan<uint64_t>(c, sh, &tot);
+  // block summary of a 4096-cell block (levels with >= 4096 cells)
+  if (threadIdx.x == 0 && wide_level(g, r.lev)) {
+    unsigned bits = 0u;
+    if (tot & 0xffffull) bits |= BS_EXIST | BS_LEAF;
+    if ((tot >> 16) & 0xffffull) bits |= BS_EXIST | BS_INT;
+    p.bsum[g.bs_off[r.lev] + (r.tb >> BS_SHIFT)] = (uint8_t)bits;
   }
-  if (!act) return;
-  for (int j = 0; j < cpt; j++) {
-    int e[LS_COUNT];
-    cell_types<D>(g, p, lev, t0 + j, e);
-    for (int k = 0; k < LS_COUNT; k++)
-      if (e[k]) p.lst[k][g.off[lev] + base[k]++] = (int)(t0 + j);
+  if (c == 0ull) return;
+  int base[NCL];
+#pragma unroll
+  for (int k = 0; k < NCL; k++) base[k] = p.bcnt[clist(k) * nbt + b] + (int)((ex >> (16 * k)) & 0xffffull);
+  const int64_t o = g.off[r.lev];
+  for (int j = 0; j < r.cpt; j++) {
+    const uint32_t e = (uint32_t)(codes >> (4 * j)) & 15u;
+#pragma unroll
+    for (int k = 0; k < NCL; k++)
+      if ((e >> k) & 1u) p.lst[clist(k)][o + base[k]++] = (int)(r.t0 + j);
   }
 }
 
-void launch_compact(const Geo& g, const Dev& p, int lo, hipStream_t s) {
+void launch_compact(const Geo& g, const Dev& p, int lo, bool full, hipStream_t s) {
   const int64_t nb = g.comp_first[g.L + 1] - g.comp_first[lo];
-  if (g.d == 1) k_comp_count<1><<<(unsigned)nb, TPB, 0, s>>>(g, p, lo);
-  else if (g.d == 2) k_comp_count<2><<<(unsigned)nb, TPB, 0, s>>>(g, p, lo);
-  else k_comp_count<3><<<(unsigned)nb, TPB, 0, s>>>(g, p, lo);
+  const int f = full ? 1 : 0;
+  if (g.d == 1) k_comp_count<1><<<(unsigned)nb, TPB, 0, s>>>(g, p, lo, f);
+  else if (g.d == 2) k_comp_count<2><<<(unsigned)nb, TPB, 0, s>>>(g, p, lo, f);
+  else k_comp_count<3><<<(unsigned)nb, TPB, 0, s>>>(g, p, lo, f);
   k_comp_scan<<<(unsigned)(g.L - lo + 1), TPB, 0, s>>>(g, p, lo);
-  if (g.d == 1) k_comp_write<1><<<(unsigned)nb, TPB, 0, s>>>(g, p, lo);
-  else if (g.d == 2) k_comp_write<2><<<(unsigned)nb, TPB, 0, s>>>(g, p, lo);
-  else k_comp_write<3><<<(unsigned)nb, TPB, 0, s>>>(g, p, lo);
+  if (g.d == 1) k_comp_write<1><<<(unsigned)nb, TPB, 0, s>>>(g, p, lo, f);
+  else if (g.d == 2) k_comp_write<2><<<(unsigned)nb, TPB, 0, s>>>(g, p, lo, f);
+  else k_comp_write<3><<<(unsigned)nb, TPB, 0, s>>>(g, p, lo, f);
 }
 
 #define DISPATCH_D(kern, n, ...)                                                  \
@@ -1277,31 +1717,46 @@ void launch_recon_level(const Geo& g, const Dev& p, int lev, double* dense, hipS
 void launch_to_rowmajor(const Geo& g, const double* dense, double* out, hipStream_t s) {
   DISPATCH_D(k_to_rowmajor, g.B * g.n[g.L], g, dense, out);
 }
-static int64_t range_cells(const Geo& g, int lo, int hi) {
-  return (hi == g.L ? g.Ntot : g.off[hi + 1]) - g.off[lo];
-}
-void launch_detail(const Geo& g, const Dev& p, int lo, int hi, hipStream_t s) {
+// remesh table and W flags cleared on levels lo..hi
+void launch_remesh_clear(const Geo& g, const Dev& p, int lo, int hi, hipStream_t s) {
   if (lo > hi) return;
-  DISPATCH_D(k_detail, range_cells(g, lo, hi), g, p, lo, hi);
+  int64_t nb = g.bs_off[hi + 1] - g.bs_off[lo];
+  if (nb > 2048) nb = 2048;
+  k_clear_w<<<(unsigned)nb, TPB, 0, s>>>(g, p, lo, hi);
 }
-void launch_seed(const Geo& g, const Dev& p, int lo, int hi, int la, hipStream_t s) {
+void launch_detail_seed(const Geo& g, const Dev& p, int lo, int hi, hipStream_t s) {
   if (lo > hi) return;
-  DISPATCH_D(k_seed, range_cells(g, lo, hi), g, p, lo, hi, la);
+  DISPATCH_D(k_detail_seed, g.B * g.n[hi], g, p, lo, hi);
 }
+// dense passes: 16 cells per lane on levels with >= 2^20 cells (where the
+// block summaries let whole blocks be skipped), one cell per lane below (so
+// a block never hands a lane more than one work item there)
+#define DISPATCH_DG(kern, lev_, ...)                                                     \
+  do {                                                                                   \
+    const int64_t cells_ = g.B * g.n[lev_];                                              \
+    if (wide_level(g, lev_)) {                                                           \
+      const int nb_ = blocks_for((cells_ + 15) >> 4);                                    \
+      if (g.d == 1) kern<1, 16><<<nb_, TPB, 0, s>>>(__VA_ARGS__);                        \
+      else if (g.d == 2) kern<2, 16><<<nb_, TPB, 0, s>>>(__VA_ARGS__);                   \
+      else kern<3, 16><<<nb_, TPB, 0, s>>>(__VA_ARGS__);                                 \
+    } else {                                                                             \
+      int64_t b_ = (cells_ + TPB - 1) / TPB;                                             \
+      const int nb_ = (int)(b_ > 4096 ? 4096 : b_);                                      \
+      if (g.d == 1) kern<1, 1><<<nb_, TPB, 0, s>>>(__VA_ARGS__);                         \
+      else if (g.d == 2) kern<2, 1><<<nb_, TPB, 0, s>>>(__VA_ARGS__);                    \
+      else kern<3, 1><<<nb_, TPB, 0, s>>>(__VA_ARGS__);                                  \
+    }                                                                                    \
+  } while (0)
 void launch_close(const Geo& g, const Dev& p, int lev, hipStream_t s) {
-  DISPATCH_D(k_close, g.B * g.n[lev], g, p, lev);
+  DISPATCH_DG(k_close, lev + 1, g, p, lev);
 }
 void launch_prune(const Geo& g, const Dev& p, int lev, int la, hipStream_t s) {
-  DISPATCH_D(k_prune, g.B * g.n[lev], g, p, lev, la);
+  if (lev == g.l0) return;
+  DISPATCH_DG(k_prune, lev, g, p, lev, la);
 }
 void launch_apply(const Geo& g, const Dev& p, int lev, int la, hipStream_t s) {
-  DISPATCH_D(k_apply, g.B * g.n[lev], g, p, lev, la);
+  DISPATCH_DG(k_apply, lev, g, p, lev, la);
 }
-void launch_ghost_flags(const Geo& g, const Dev& p, int lo, int hi, hipStream_t s) {
-  if (lo > hi) return;
-  DISPATCH_D(k_ghost_flags, range_cells(g, lo, hi), g, p, lo, hi);
-}
-
 // ---------------------------------------------------------------------------
 // leaf lists of one instance and level in Morton order: wavefront ballot +
 // popcount, per-block counts, an exclusive scan of the block counts, then a

@@ -6,12 +6,15 @@
 //   G = off[l] + inst * n[l] + morton.
 // Children of cell (l, t) with t = inst * n[l] + key are (l+1, (t << d) + c),
 // c = a | b<<1 | e<<2: a child group is contiguous.
+// Level tables start at multiples of 256 cells (off[l] is padded), so byte
+// tables can be read 16 cells at a time.
 // Values are FP64, field-major per time slot: slot[s][k * Ntot + G].
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #define MRD_MAXLEV 24
+#define BS_SHIFT 12  // block summaries cover 4096 cells
 
 enum { ST_ABSENT = 0, ST_LEAF = 1, ST_INTERNAL = 2 };
 
@@ -50,19 +53,23 @@ struct Geo {
   // comp_first[l] .. comp_first[l+1]-1 of a global block numbering
   int64_t comp_first[MRD_MAXLEV + 2];
   int comp_chunk[MRD_MAXLEV + 1];
+  // 4096-cell blocks of level l (one summary byte each) start at bs_off[l]
+  int64_t bs_off[MRD_MAXLEV + 2];
   // instances [i0, i1) that the remesh sweeps may change (all of them inside a
   // macro step; one instance when it is loaded or adapted on its own)
   int i0, i1;
 };
 
-// per-level lists of cell indices (within-level index t = inst * n[l] + key);
+// per-level lists of cell indices (within-level index t = inst * n[l] + key):
+// leaves, internal nodes, virtual (ghost) cells read by leaf stencils, and
 // LS_IFACE: the leaves of LS_LEAF below L with a refined face neighbour
 enum { LS_LEAF = 0, LS_INTERNAL = 1, LS_GHOST = 2, LS_IFACE = 3, LS_COUNT = 4 };
 
 struct Dev {
   uint8_t* st;     // status per cell
-  uint8_t* rf;     // remesh scratch: bit0 significant, bit1 member of W, bit2 new node
-  uint8_t* gh;     // 1: absent cell read by a leaf stencil (virtual / ghost value)
+  uint8_t* rf;     // remesh scratch: bit1 member of W (nodes that will be internal)
+  uint8_t* bsum;   // per 4096-cell block: 1 a cell exists, 2 one is internal, 4 one is a leaf
+  uint8_t* wsum;   // per 4096-cell block: 1 when the block may hold W marks
   double* q[SL_COUNT];
   double* regc;    // [level block][2d][m][B n_l]
   double* regf;    // [level block][2d][nsub][m][B n_l]
@@ -87,13 +94,15 @@ void launch_ghost(const Geo& g, const Dev& p, int lo, int hi, int cb_lev, int st
 // leaf-updates of these levels to the counters)
 void launch_stage(const Geo& g, const Dev& p, int lo, int hi, int stage, hipStream_t s);
 void launch_finalize(const Geo& g, const Dev& p, int lo, int hi, hipStream_t s);
-void launch_detail(const Geo& g, const Dev& p, int lo, int hi, hipStream_t s);
-void launch_seed(const Geo& g, const Dev& p, int lo, int hi, int la, hipStream_t s);
-void launch_compact(const Geo& g, const Dev& p, int lo, hipStream_t s);
+// remesh byte table cleared on levels lo..hi
+void launch_remesh_clear(const Geo& g, const Dev& p, int lo, int hi, hipStream_t s);
+// details of the internal nodes of levels lo..hi and the seed of W
+void launch_detail_seed(const Geo& g, const Dev& p, int lo, int hi, hipStream_t s);
+// lists of levels lo..L; full: rebuild without trusting the block summaries
+void launch_compact(const Geo& g, const Dev& p, int lo, bool full, hipStream_t s);
 void launch_close(const Geo& g, const Dev& p, int lev, hipStream_t s);
 void launch_prune(const Geo& g, const Dev& p, int lev, int la, hipStream_t s);
 void launch_apply(const Geo& g, const Dev& p, int lev, int la, hipStream_t s);
-void launch_ghost_flags(const Geo& g, const Dev& p, int lo, int hi, hipStream_t s);
 void launch_recon_level(const Geo& g, const Dev& p, int lev, double* dense, hipStream_t s);
 void launch_to_rowmajor(const Geo& g, const double* dense, double* out, hipStream_t s);
 void launch_count(const Geo& g, const Dev& p, int lev, int inst, uint8_t want, int* blockcnt,

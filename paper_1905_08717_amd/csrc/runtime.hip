@@ -111,13 +111,10 @@ void project_range(mr_ctx* c, int hi, int lo, int mode) {
     timed(c, MR_KC_PROJECT, [&] { launch_project(c->g, c->p, lev, mode, c->stream); });
 }
 
-// ghost flags and leaf / internal / ghost lists of levels la..L
-void refresh_lists(mr_ctx* c, int la) {
-  const Geo& g = c->g;
-  hipStream_t s = c->stream;
-  const int glo = la > g.l0 ? la : g.l0 + 1;
-  timed(c, MR_KC_REMESH, [&] { launch_ghost_flags(g, c->p, glo, g.L, s); });
-  timed(c, MR_KC_REMESH, [&] { launch_compact(g, c->p, la, s); });
+// leaf / internal / interface / ghost lists of levels la..L; full after
+// status changes made outside the remesh
+void refresh_lists(mr_ctx* c, int la, bool full) {
+  timed(c, MR_KC_REMESH, [&] { launch_compact(c->g, c->p, la, full, c->stream); });
 }
 
 // remesh with levels below la frozen; statuses, new values and lists
@@ -125,12 +122,12 @@ void remesh(mr_ctx* c, int la) {
   const Geo& g = c->g;
   if (la > g.L - 1) return;
   hipStream_t s = c->stream;
-  timed(c, MR_KC_REMESH, [&] { launch_detail(g, c->p, la, g.L, s); });
-  timed(c, MR_KC_REMESH, [&] { launch_seed(g, c->p, la, g.L - 1, la, s); });
+  timed(c, MR_KC_REMESH, [&] { launch_remesh_clear(g, c->p, la, g.L - 1, s); });
+  timed(c, MR_KC_REMESH, [&] { launch_detail_seed(g, c->p, la, g.L - 1, s); });
   for (int lev = g.L - 2; lev >= la; lev--) timed(c, MR_KC_REMESH, [&] { launch_close(g, c->p, lev, s); });
   for (int lev = la; lev <= g.L - 1; lev++) timed(c, MR_KC_REMESH, [&] { launch_prune(g, c->p, lev, la, s); });
   for (int lev = la; lev <= g.L; lev++) timed(c, MR_KC_REMESH, [&] { launch_apply(g, c->p, lev, la, s); });
-  refresh_lists(c, la);
+  refresh_lists(c, la, false);
 }
 
 void ghost_fill(mr_ctx* c, int lmin, int stage) {
@@ -243,7 +240,7 @@ mr_status adapt_impl(mr_ctx* c) {
   const Geo& g = c->g;
   project_range(c, g.L - 1, g.l0, PJ_Q0);
   if (g.l0 <= g.L - 1) remesh(c, g.l0);
-  else refresh_lists(c, g.l0);
+  else refresh_lists(c, g.l0, true);
   project_range(c, g.L - 1, g.l0, PJ_Q0);
   mr_status st = check_launch(c, "adapt");
   if (st != MR_OK) return st;
@@ -324,7 +321,7 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
   for (int lev = g.l0; lev <= L; lev++) {
     g.n[lev] = (int64_t)1 << (dim * lev);
     g.off[lev] = off;
-    off += g.B * g.n[lev];
+    off += (g.B * g.n[lev] + 255) & ~(int64_t)255;
     g.rc_off[lev] = rc;
     g.rf_off[lev] = rf;
     if (lev < L) {
@@ -345,9 +342,18 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
   }
   g.Ntot = off;
   {
+    int64_t nbs = 0;
+    for (int lev = g.l0; lev <= L; lev++) {
+      g.bs_off[lev] = nbs;
+      nbs += (g.B * g.n[lev] + (1 << BS_SHIFT) - 1) >> BS_SHIFT;
+    }
+    g.bs_off[L + 1] = nbs;
+  }
+  {
     int64_t nb = 0;
     for (int lev = g.l0; lev <= L; lev++) {
-      const int64_t ch = g.n[lev] < 4096 ? g.n[lev] : 4096;
+      // 4096-cell blocks of 16-cell lane groups, else one cell per lane
+      const int64_t ch = g.n[lev] >= 4096 ? 4096 : (g.n[lev] < 256 ? g.n[lev] : 256);
       g.comp_chunk[lev] = (int)ch;
       g.comp_first[lev] = nb;
       nb += g.B * g.n[lev] / ch;
@@ -383,7 +389,8 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
   } while (0)
   ALLOC(c->p.st, uint8_t, g.Ntot);
   ALLOC(c->p.rf, uint8_t, g.Ntot);
-  ALLOC(c->p.gh, uint8_t, g.Ntot);
+  ALLOC(c->p.bsum, uint8_t, g.bs_off[L + 1]);
+  ALLOC(c->p.wsum, uint8_t, g.bs_off[L + 1]);
   for (int sl = 0; sl < SL_COUNT; sl++) ALLOC(c->p.q[sl], double, (int64_t)g.m * g.Ntot);
   ALLOC(c->p.regc, double, g.rc_off[L]);
   ALLOC(c->p.regf, double, g.rf_off[L]);
@@ -436,7 +443,7 @@ mr_status mr_load_finest(mr_ctx* c, const double* q0, void* hip_stream) {
   for (int lev = g.l0; lev < g.L; lev++) launch_fill_status(g, c->p, lev, ST_INTERNAL, c->stream);
   launch_load_finest(g, c->p, q0, -1, c->stream);
   launch_clear_regs(g, c->p, c->stream);
-  refresh_lists(c, g.l0);
+  refresh_lists(c, g.l0, true);
   HIPCHK(c, hipMemsetAsync(c->p.cnt, 0, sizeof(unsigned long long) * g.B * CNT_PER_INST, c->stream));
   mr_status st = check_launch(c, "load_finest");
   if (st != MR_OK) return st;
@@ -457,7 +464,7 @@ mr_status mr_load_finest_inst(mr_ctx* c, int inst, const double* q0) {
   launch_load_finest(g, c->p, q0, inst, c->stream);
   launch_clear_regs(g, c->p, c->stream);
   k_reset_counters<<<1, 64, 0, c->stream>>>(c->p.cnt, inst);
-  refresh_lists(c, g.l0);
+  refresh_lists(c, g.l0, true);
   project_range(c, g.L - 1, g.l0, PJ_Q0);
   if (g.l0 <= g.L - 1) {
     // only this instance is remeshed; the others keep their trees
@@ -478,7 +485,7 @@ mr_status mr_clear_instance(mr_ctx* c, int inst) {
   if (!c || inst < 0 || inst >= c->g.B) return MR_EINVAL;
   launch_fill_instance(c->g, c->p, -1 - inst, c->stream);
   k_reset_counters<<<1, 64, 0, c->stream>>>(c->p.cnt, inst);
-  refresh_lists(c, c->g.l0);
+  refresh_lists(c, c->g.l0, true);
   c->t[inst] = 0.0;
   mr_status st = check_launch(c, "clear_instance");
   if (st != MR_OK) return st;
@@ -669,10 +676,10 @@ mr_status mr_set_leaves_inst(mr_ctx* c, int inst, const uint64_t* keys, const do
     c->broken = true;
     return set_err(c, MR_EINVAL, buf);
   }
-  launch_compact(g, c->p, g.l0, c->stream);  // internal lists for the projection
+  launch_compact(g, c->p, g.l0, true, c->stream);  // internal lists for the projection
   project_range(c, g.L - 1, g.l0, PJ_Q0);
   launch_clear_regs(g, c->p, c->stream);
-  refresh_lists(c, g.l0);
+  refresh_lists(c, g.l0, true);
   k_reset_counters<<<1, 64, 0, c->stream>>>(c->p.cnt, inst);
   mr_status st = check_launch(c, "set_leaves");
   if (st != MR_OK) return st;

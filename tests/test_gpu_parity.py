@@ -82,6 +82,15 @@ def test_burgers_1d_full_config_to_t_final(mods):
     assert abs(s.stats()["t"] - 0.5) < 1e-12
 
 
+@pytest.mark.parametrize("L", [12, 13])
+def test_euler_1d_deep_tree(mods, L):
+    # levels with >= 4096 cells take the 16-cell group path of the list
+    # compaction; the shock tube keeps leaves on every level from 5 to L
+    cfg = W.euler_1d(L=L)
+    run_pair(mods, cfg, W.euler_shock_tube(L),
+             [lambda o: W.euler_dt(cfg, o.max_wavespeed(), o.stats()["t"])] * 3)
+
+
 @pytest.mark.parametrize("L", [6, 7])
 def test_nagumo_2d_reduced(mods, L):
     cfg = W.nagumo_2d(L=L)
