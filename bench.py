@@ -10,14 +10,16 @@ of the method, remesh included) over the whole batch.
 
 value  = leaf-updates (one per leaf per full RK step, counted on the device)
          over the K timed macro steps / wall time, inputs resident in HBM.
-roofline = the RK stage kernels (the data-parallel hot path): algorithmic
-         bytes 64 m B per leaf-update (read q^n, write q*; read q^n, q*,
-         write q**; read q^n, q**, write q^{n+1}) over their HIP-event time.
+roofline = the bulk RK stage kernel (the data-parallel hot path): algorithmic
+         bytes 16m / 24m / 24m per leaf and stage (read q^n, write q*; read
+         q^n, q*, write q**; read q^n, q**, write q^{n+1}), leaf-stage updates
+         counted on the device, over the kernel's HIP-event time.
 cpu_baseline = the CPU oracle on one instance of the same workload.
 
 Prints one JSON line.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -35,6 +37,25 @@ def leaf_counts(s):
     for i in range(s.n_inst):
         tot += np.array(s.stats(i)["leaves"], dtype=np.int64)
     return tot
+
+
+def stage_traffic(batch):
+    """HBM bytes per launch of the bulk stage kernel from the committed
+    FETCH_SIZE / WRITE_SIZE counter runs, when they were taken on this batch
+    size and on the current kernel source; otherwise None."""
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", "stage_bulk_traffic.json")
+    src = os.path.join(here, "paper_1905_08717_amd", "csrc", "kernels.hip")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        with open(src, "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernels_hip_sha256") != digest or rec.get("batch") != batch:
+        return None
+    return rec.get("hbm_bytes_per_launch")
 
 
 def cpu_baseline(cfg, q0, dt, seconds):
@@ -55,6 +76,57 @@ def cpu_baseline(cfg, q0, dt, seconds):
     return {"value": upd / el, "unit": "leaf-updates/s", "cores": mro.num_threads(), "kind": "oracle",
             "sample": f"1 instance of the same workload, {nmac} macro steps from t=0 ({upd} leaf-updates, "
                       f"{el:.1f} s), OpenMP threads={mro.num_threads()}"}
+
+
+def copy_calibration():
+    """A plain device-to-device copy of known size (1 GiB read, 1 GiB written
+    per copy), run under the FETCH_SIZE / WRITE_SIZE counters to calibrate
+    them against known traffic."""
+    import torch
+    n = 1 << 27
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "copycal", "copies": 3, "bytes_read_per_copy": n * 8,
+                      "bytes_written_per_copy": n * 8}), flush=True)
+
+
+def traffic_record(args):
+    """HBM traffic of the bulk stage kernel from four rocprofv3 counter runs
+    (FETCH_SIZE and WRITE_SIZE of this bench's throughput mode and of the
+    copy calibration), written to profiles/stage_bulk_traffic.json: the
+    counters of the last K*3 bulk launches (the stage-timing pass), scaled by
+    what the counters read for the 1 GiB copy."""
+    import csv
+    d = args.pmc_dir
+
+    def col(path, kern):
+        with open(path) as f:
+            return [float(r["Counter_Value"]) for r in csv.DictReader(f) if kern in r["Kernel_Name"]]
+
+    cf = col(os.path.join(d, "pmc_cfetch", "cfetch_counter_collection.csv"), "copyBuffer")
+    cw = col(os.path.join(d, "pmc_cwrite", "cwrite_counter_collection.csv"), "copyBuffer")
+    gib_kib = float(1 << 20)
+    sf, sw = gib_kib / max(cf), gib_kib / max(cw)
+    kern = "k_stage<2, 2, false>"
+    from paper_1905_08717_amd import workloads as W
+    n = 3 * W.macro_iters(W.nagumo_2d()) * args.steps  # one bulk launch per stage and iteration
+    f = col(os.path.join(d, "pmc_fetch", "fetch_counter_collection.csv"), kern)[-n:]
+    w = col(os.path.join(d, "pmc_write", "write_counter_collection.csv"), kern)[-n:]
+    fetch = sum(f) / len(f) * sf * 1024
+    write = sum(w) / len(w) * sw * 1024
+    here = os.path.dirname(os.path.abspath(__file__))
+    with open(os.path.join(here, "paper_1905_08717_amd", "csrc", "kernels.hip"), "rb") as fh:
+        digest = hashlib.sha256(fh.read()).hexdigest()
+    rec = {"kernel": kern, "batch": args.batch, "steps": args.steps, "warmup": args.warmup,
+           "launches_averaged": len(f), "fetch_scale": round(sf, 4), "write_scale": round(sw, 4),
+           "fetch_bytes_per_launch": round(fetch), "write_bytes_per_launch": round(write),
+           "hbm_bytes_per_launch": round(fetch + write), "kernels_hip_sha256": digest}
+    with open(os.path.join(here, "profiles", "stage_bulk_traffic.json"), "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec), flush=True)
 
 
 def systems_mode(args):
@@ -97,10 +169,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--batch", type=int, default=512)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", choices=["throughput", "batched", "served"], default="throughput")
+    ap.add_argument("--mode", choices=["throughput", "batched", "served", "copycal", "traffic"], default="throughput")
+    ap.add_argument("--pmc-dir", default="gpurun_out", help="traffic mode: folder of the four counter runs")
+    ap.add_argument("--no-single", action="store_true", help="skip the single-solve reference run")
     ap.add_argument("--requests", type=int, default=0)
     ap.add_argument("--solo-sample", type=int, default=64)
     ap.add_argument("--rate", type=float, default=200.0)
@@ -112,6 +186,12 @@ def main():
               "across GPUs by instance, which is not built here", file=sys.stderr)
         sys.exit(2)
 
+    if args.mode == "copycal":
+        copy_calibration()
+        return
+    if args.mode == "traffic":
+        traffic_record(args)
+        return
     if args.mode != "throughput":
         systems_mode(args)
         return
@@ -141,34 +221,40 @@ def main():
     value = upd / el
     leaves = leaf_counts(s)
 
-    # roofline of the stage kernels: HIP events around each of their launches
-    # over the same number of macro steps
-    u1 = total_updates(s)
-    s.timing_start("stage")
+    # roofline of the dominant kernel, the bulk RK stage kernel: HIP events
+    # around each of its launches over the same number of macro steps, and
+    # its leaf-stage updates counted on the device; algorithmic bytes per
+    # leaf-stage update 16m (stage 1), 24m (stages 2, 3)
+    it0 = s.stage_items()
+    s.timing_start("stage_bulk")
     for _ in range(args.steps):
         s.lt_step(dt)
     ms, launches = s.timing_stop()
-    upd_r = total_updates(s) - u1
+    items = s.stage_items() - it0
     m = s.m
-    alg_bytes = upd_r * 64 * m
+    alg_bytes = int(items[0]) * 16 * m + int(items[1]) * 24 * m + int(items[2]) * 24 * m
     achieved = alg_bytes / (ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": 8000.0, "unit": "GB/s",
-                "frac": round(achieved / 8000.0, 5), "traffic": None,
-                "kernel": "k_stage (RK stage kernels, all levels)",
+                "frac": round(achieved / 8000.0, 5), "traffic": stage_traffic(B),
+                "kernel": "k_stage<2, 2, false> (bulk RK stage kernel, all levels of a stage)",
                 "launches": launches, "avg_launch_us": round(ms * 1e3 / max(launches, 1), 3),
-                "alg_bytes_per_leaf_update": 64 * m}
+                "alg_bytes_per_launch": round(alg_bytes / max(launches, 1), 1),
+                "leaf_stage_updates": [int(x) for x in items],
+                "alg_bytes_per_leaf_stage": [16 * m, 24 * m, 24 * m]}
 
     # single-solve reference (one instance), same work per macro step
-    s1 = mrlt.Solver(cfg, n_inst=1)
-    s1.load_finest(torch.from_numpy(q0[:1]).to("cuda"))
-    s1.lt_step(dt)
-    a = total_updates(s1)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(2):
+    single = None
+    if not args.no_single:
+        s1 = mrlt.Solver(cfg, n_inst=1)
+        s1.load_finest(torch.from_numpy(q0[:1]).to("cuda"))
         s1.lt_step(dt)
-    torch.cuda.synchronize()
-    single = (total_updates(s1) - a) / (time.perf_counter() - t1)
+        a = total_updates(s1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(2):
+            s1.lt_step(dt)
+        torch.cuda.synchronize()
+        single = round((total_updates(s1) - a) / (time.perf_counter() - t1), 1)
 
     out = {
         "metric": "leaf cell-updates/s", "value": round(value, 1), "unit": "leaf-updates/s",
@@ -180,7 +266,7 @@ def main():
                    "dim": 2, "L": 9, "l0": 2, "eps": 1e-3, "batch": B, "dt_L": dt,
                    "leaves_per_level_total": [int(x) for x in leaves[:10]]},
         "roofline": roofline,
-        "single_solve_leaf_updates_per_s": round(single, 1),
+        "single_solve_leaf_updates_per_s": single,
         "solves_macro_steps_per_s": round(B * args.steps / el, 2),
     }
     if not args.no_cpu_baseline:

@@ -176,8 +176,19 @@ enum {
   MR_KC_PROJECT = 3,       /* projections and synchronisation values of internal nodes */
   MR_KC_GHOST = 4,         /* virtual-cell prediction */
   MR_KC_REMESH = 5,        /* details, safety, closure, pruning, apply, ghost flags */
-  MR_KC_FINALIZE = 6       /* end of step and conservative correction */
+  MR_KC_FINALIZE = 6,      /* end of step and conservative correction */
+  MR_KC_STAGE_BULK = 7     /* the bulk RK stage kernel alone: leaves whose stencil
+                              reaches no internal cell, all levels of a stage */
 };
+
+/* Measurement support.  Cumulative leaf-stage updates done by the bulk RK
+ * stage kernel (class MR_KC_STAGE_BULK), summed over instances, for stages
+ * 1, 2, 3 (host array of 3 entries).  With the algorithmic bytes of a stage
+ * (Sec. 3: stage 1 reads q^n and writes q*, stage 2 reads q^n and q* and
+ * writes q**, stage 3 reads q^n and q** and writes q^{n+1}: 16m, 24m, 24m
+ * bytes per leaf) this gives the kernel's algorithmic traffic.  Synchronises
+ * the context's stream.                                                   */
+mr_status mr_stage_items(mr_ctx* c, int64_t* per_stage);
 
 /* Bracket every later launch of one kernel class with a pair of HIP events
  * on the context's stream, until mr_timing_stop.                          */

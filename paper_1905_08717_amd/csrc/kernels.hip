@@ -263,6 +263,12 @@ struct NC {
   static constexpr int M = (PDE == PDE_EULER) ? D + 2 : 1;
 };
 
+// how far along an axis a leaf's stencil reads: 2 with the MUSCL
+// reconstruction, 1 for two-point diffusion, first order or centred fluxes
+__host__ __device__ __forceinline__ int stencil_reach(const Geo& g) {
+  return (g.pde == PDE_NAGUMO || g.pde == PDE_LINEAR || g.recon != 1) ? 1 : 2;
+}
+
 // flux across the face between cells a and a+1 along dir; c holds a-1..a+2
 template <int D, int PDE>
 __device__ __forceinline__ void face_flux(const Geo& g, int lev, int dir,
@@ -641,16 +647,26 @@ __device__ __forceinline__ void refined_flux(const Geo& g, const Dev& p, int lev
   for (int k = 0; k < M; k++) F[k] = Fs[k] * sc;
 }
 
-// IFACE = false: every leaf without a refined face neighbour (the bulk of the
-// work, lean in registers); IFACE = true: the leaves of levels below L with
-// at least one refined face neighbour, whose faces are evaluated on the
-// finer level.  The two sets are disjoint and every leaf writes only its own
-// values and flux-register entries, so the two launches commute.
+// IFACE = false: every leaf whose stencil reaches no internal cell (the bulk
+// of the work, lean in registers); it reads only leaves and virtual cells of
+// its own level, so one launch serves all levels of a stage.  IFACE = true:
+// the leaves of levels below L whose stencil reaches an internal cell (a
+// refined face neighbour, evaluated on the finer level, or an internal cell
+// at distance 2 read through its projected value); they run level by level
+// inside the stage sweeps.  The two sets are disjoint and every leaf writes
+// only its own values and flux-register entries.
 template <int D, int PDE, bool IFACE>
 __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int stage) {
   constexpr int M = NC<D, PDE>::M;
   constexpr double C_1_6 = 1.0 / 6.0, C_2_3 = 2.0 / 3.0, C_1_3 = 1.0 / 3.0;
   constexpr int LS = IFACE ? LS_IFACE : LS_LEAF;
+  // leaf-stage updates of this bulk launch (measurement)
+  if (!IFACE && blockIdx.x == 0 && threadIdx.x == 0) {
+    unsigned long long it = 0ull;
+    for (int lev = lo; lev <= hi; lev++)
+      it += (unsigned long long)(list_len(p, LS_LEAF, lev) - (lev < g.L ? list_len(p, LS_IFACE, lev) : 0));
+    atomicAdd(&p.items[stage - 1], it);
+  }
   // one leaf-update per leaf and full RK step: counted once, at stage 1
   if (!IFACE && stage == 1 && blockIdx.x == 0) {
     const int nlv = hi - lo + 1;
@@ -696,6 +712,18 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
           sts[dir][side] = sv;
           refined = refined || sv == ST_INTERNAL;
         }
+      if (!IFACE && !finest && !refined && (PDE != PDE_NAGUMO && PDE != PDE_LINEAR) && g.recon == 1) {
+#pragma unroll
+        for (int dir = 0; dir < D; dir++)
+#pragma unroll
+          for (int side = 0; side < 2; side++) {
+            const int nb = map_nb(x[dir] + (side ? 2 : -2), n, g.periodic[dir]);
+            if (nb < 0) continue;
+            int y[3] = {x[0], x[1], x[2]};
+            y[dir] = nb;
+            refined = refined || p.st[ib + (int64_t)menc<D>(y)] == ST_INTERNAL;
+          }
+      }
       if (!IFACE && refined && !finest) continue;  // the interface launch owns it
       const double h = g.lt ? ldexp(p.dt[inst], g.L - lev) : p.dt[inst];
       // weights b_i of the RK method: RK3 (1/6, 1/6, 2/3), RK2 (1/2, 1/2)
@@ -813,8 +841,11 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
 }
 
 template <int D, int PDE>
-static void stage_dp(const Geo& g, const Dev& p, int lo, int hi, int stage, hipStream_t s) {
-  k_stage<D, PDE, false><<<blocks_for(g.B * g.n[hi]), TPB, 0, s>>>(g, p, lo, hi, stage);
+static void stage_dp(const Geo& g, const Dev& p, int lo, int hi, int stage, int part, hipStream_t s) {
+  if (part == 0) {
+    k_stage<D, PDE, false><<<blocks_for(g.B * g.n[hi]), TPB, 0, s>>>(g, p, lo, hi, stage);
+    return;
+  }
   const int hif = hi < g.L ? hi : g.L - 1;
   if (lo > hif) return;
   // interface leaves lie along refinement boundaries: a small fraction
@@ -824,21 +855,21 @@ static void stage_dp(const Geo& g, const Dev& p, int lo, int hi, int stage, hipS
 }
 
 template <int D>
-static void stage_d(const Geo& g, const Dev& p, int lo, int hi, int stage, hipStream_t s) {
+static void stage_d(const Geo& g, const Dev& p, int lo, int hi, int stage, int part, hipStream_t s) {
   switch (g.pde) {
-    case PDE_ADVECTION: stage_dp<D, PDE_ADVECTION>(g, p, lo, hi, stage, s); break;
-    case PDE_BURGERS: stage_dp<D, PDE_BURGERS>(g, p, lo, hi, stage, s); break;
-    case PDE_NAGUMO: stage_dp<D, PDE_NAGUMO>(g, p, lo, hi, stage, s); break;
-    case PDE_EULER: stage_dp<D, PDE_EULER>(g, p, lo, hi, stage, s); break;
-    default: stage_dp<D, PDE_LINEAR>(g, p, lo, hi, stage, s); break;
+    case PDE_ADVECTION: stage_dp<D, PDE_ADVECTION>(g, p, lo, hi, stage, part, s); break;
+    case PDE_BURGERS: stage_dp<D, PDE_BURGERS>(g, p, lo, hi, stage, part, s); break;
+    case PDE_NAGUMO: stage_dp<D, PDE_NAGUMO>(g, p, lo, hi, stage, part, s); break;
+    case PDE_EULER: stage_dp<D, PDE_EULER>(g, p, lo, hi, stage, part, s); break;
+    default: stage_dp<D, PDE_LINEAR>(g, p, lo, hi, stage, part, s); break;
   }
 }
 
-void launch_stage(const Geo& g, const Dev& p, int lo, int hi, int stage, hipStream_t s) {
+void launch_stage(const Geo& g, const Dev& p, int lo, int hi, int stage, int part, hipStream_t s) {
   if (lo > hi) return;
-  if (g.d == 1) stage_d<1>(g, p, lo, hi, stage, s);
-  else if (g.d == 2) stage_d<2>(g, p, lo, hi, stage, s);
-  else stage_d<3>(g, p, lo, hi, stage, s);
+  if (g.d == 1) stage_d<1>(g, p, lo, hi, stage, part, s);
+  else if (g.d == 2) stage_d<2>(g, p, lo, hi, stage, part, s);
+  else stage_d<3>(g, p, lo, hi, stage, part, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1371,7 +1402,7 @@ __device__ __forceinline__ uint32_t cell_code(const Geo& g, const Dev& p, int le
   for (int dir = 0; dir < D; dir++)
 #pragma unroll
     for (int o = -2; o <= 2; o++) {
-      if (o == 0 || (leaf && (o == -2 || o == 2))) continue;
+      if (o == 0 || (leaf && stencil_reach(g) == 1 && (o == -2 || o == 2))) continue;
       const int u = map_nb(x[dir] + o, n, g.periodic[dir]);
       if (u < 0) continue;
       int y[3] = {x[0], x[1], x[2]};
@@ -1472,6 +1503,7 @@ __device__ __forceinline__ uint64_t group_codes(const Geo& g, const Dev& p, int 
     u.z |= h.m[a].z | h.p[a].z; u.w |= h.m[a].w | h.p[a].w;
   }
   const bool nb_leaf = any16(u, 0x01010101u), nb_int = lev < g.L && any16(u, 0x02020202u);
+  const int reach = stencil_reach(g);
 #pragma unroll
   for (int j = 0; j < 16; j++) {
     const uint8_t st = byte_of(h.c, j);
@@ -1482,7 +1514,11 @@ __device__ __forceinline__ uint64_t group_codes(const Geo& g, const Dev& p, int 
       bool ref = false;
       if (nb_int) {
 #pragma unroll
-        for (int a = 0; a < D; a++) ref = ref || nb_status<D>(h, j, a, -1) == ST_INTERNAL || nb_status<D>(h, j, a, 1) == ST_INTERNAL;
+        for (int a = 0; a < D; a++) {
+          ref = ref || nb_status<D>(h, j, a, -1) == ST_INTERNAL || nb_status<D>(h, j, a, 1) == ST_INTERNAL;
+          if (reach == 2)
+            ref = ref || nb_status<D>(h, j, a, -2) == ST_INTERNAL || nb_status<D>(h, j, a, 2) == ST_INTERNAL;
+        }
       }
       c = ref ? (CODE_LEAF | CODE_IFACE) : CODE_LEAF;
     } else if (nb_leaf && ((par >> (8 * (j >> D))) & 0xff) == ST_LEAF) {
@@ -1597,7 +1633,7 @@ __global__ __launch_bounds__(TPB) void k_comp_scan(Geo g, Dev p, int lo) {
   const int per = (nb + TPB - 1) / TPB;
   const int j0 = threadIdx.x * per;
   const int j1 = j0 + per < nb ? j0 + per : nb;
-  // up to 16 blocks per thread: all loads in flight at once
+  // the thread's blocks in chunks of 16, all loads of a chunk in flight at once
   constexpr int PMAX = 16;
   int4 v[PMAX];
   int4 loc = make_int4(0, 0, 0, 0);
@@ -1612,8 +1648,17 @@ __global__ __launch_bounds__(TPB) void k_comp_scan(Geo g, Dev p, int lo) {
       loc.x += v[q].x; loc.y += v[q].y; loc.z += v[q].z; loc.w += v[q].w;
     }
   } else {
-    for (int j = j0; j < j1; j++) {
-      loc.x += bc[0][j]; loc.y += bc[1][j]; loc.z += bc[2][j]; loc.w += bc[3][j];
+    for (int jc = j0; jc < j1; jc += PMAX) {
+      int4 w[PMAX];
+#pragma unroll
+      for (int q = 0; q < PMAX; q++) {
+        const int j = jc + q;
+        w[q] = j < j1 ? make_int4(bc[0][j], bc[1][j], bc[2][j], bc[3][j]) : make_int4(0, 0, 0, 0);
+      }
+#pragma unroll
+      for (int q = 0; q < PMAX; q++) {
+        loc.x += w[q].x; loc.y += w[q].y; loc.z += w[q].z; loc.w += w[q].w;
+      }
     }
   }
   // Hillis-Steele scan of the per-thread sums
@@ -1638,10 +1683,21 @@ __global__ __launch_bounds__(TPB) void k_comp_scan(Geo g, Dev p, int lo) {
       run.x += v[q].x; run.y += v[q].y; run.z += v[q].z; run.w += v[q].w;
     }
   } else {
-    for (int j = j0; j < j1; j++) {
-      const int4 w = make_int4(bc[0][j], bc[1][j], bc[2][j], bc[3][j]);
-      bc[0][j] = run.x; bc[1][j] = run.y; bc[2][j] = run.z; bc[3][j] = run.w;
-      run.x += w.x; run.y += w.y; run.z += w.z; run.w += w.w;
+    for (int jc = j0; jc < j1; jc += PMAX) {
+      int4 w[PMAX];
+#pragma unroll
+      for (int q = 0; q < PMAX; q++) {
+        const int j = jc + q;
+        w[q] = j < j1 ? make_int4(bc[0][j], bc[1][j], bc[2][j], bc[3][j]) : make_int4(0, 0, 0, 0);
+      }
+#pragma unroll
+      for (int q = 0; q < PMAX; q++) {
+        const int j = jc + q;
+        if (j < j1) {
+          bc[0][j] = run.x; bc[1][j] = run.y; bc[2][j] = run.z; bc[3][j] = run.w;
+        }
+        run.x += w[q].x; run.y += w[q].y; run.z += w[q].z; run.w += w[q].w;
+      }
     }
   }
   if (tid == 0) {

@@ -62,7 +62,8 @@ struct Geo {
 
 // per-level lists of cell indices (within-level index t = inst * n[l] + key):
 // leaves, internal nodes, virtual (ghost) cells read by leaf stencils, and
-// LS_IFACE: the leaves of LS_LEAF below L with a refined face neighbour
+// LS_IFACE: the leaves of LS_LEAF below L whose stencil (offsets 1, and 2
+// with the MUSCL reconstruction, along an axis) reaches an internal cell
 enum { LS_LEAF = 0, LS_INTERNAL = 1, LS_GHOST = 2, LS_IFACE = 3, LS_COUNT = 4 };
 
 struct Dev {
@@ -80,6 +81,7 @@ struct Dev {
   int* lcnt;                // [LS_COUNT][MRD_MAXLEV + 1] list lengths
   int* bcnt;                // [LS_COUNT][blocks] compaction block counts / offsets
   int* leafcnt;             // [B][MRD_MAXLEV + 1] leaves per instance and level
+  unsigned long long* items;  // [3] leaf-stage updates of the bulk stage launches, per stage
 };
 
 // ---- launchers (kernels.hip) -------------------------------------------
@@ -90,9 +92,10 @@ void launch_project(const Geo& g, const Dev& p, int lev, int mode, hipStream_t s
 // virtual cells of levels lo..hi at `stage`; level cb_lev (if in range) is
 // the child of the mid-step level (case B)
 void launch_ghost(const Geo& g, const Dev& p, int lo, int hi, int cb_lev, int stage, hipStream_t s);
-// stage kernel over the leaves of levels lo..hi (stage 1 also adds the
-// leaf-updates of these levels to the counters)
-void launch_stage(const Geo& g, const Dev& p, int lo, int hi, int stage, hipStream_t s);
+// stage kernel over the leaves of levels lo..hi: part 0 the leaves whose
+// stencil reaches no internal cell (stage 1 also adds the leaf-updates of
+// these levels to the counters), part 1 the interface leaves
+void launch_stage(const Geo& g, const Dev& p, int lo, int hi, int stage, int part, hipStream_t s);
 void launch_finalize(const Geo& g, const Dev& p, int lo, int hi, hipStream_t s);
 // remesh byte table cleared on levels lo..hi
 void launch_remesh_clear(const Geo& g, const Dev& p, int lo, int hi, hipStream_t s);

@@ -139,13 +139,23 @@ void ghost_fill(mr_ctx* c, int lmin, int stage) {
 
 // one step of the MR scheme with a global time step (the paper's
 // comparison method): every level advances by dt at the same stage times
+// RK stage st on the leaves of levels lo..hi: the bulk launch (timed under
+// MR_KC_STAGE_BULK too) and, unless bulk_only, the interface launch
+void stage_launch(mr_ctx* c, int lo, int hi, int st, bool bulk, bool iface) {
+  const Geo& g = c->g;
+  hipStream_t s = c->stream;
+  const int cls = lo == g.L ? MR_KC_STAGE_FINEST : MR_KC_STAGE;
+  if (bulk)
+    timed(c, cls, [&] { timed(c, MR_KC_STAGE_BULK, [&] { launch_stage(g, c->p, lo, hi, st, 0, s); }); });
+  if (iface && lo <= g.L - 1)
+    timed(c, cls, [&] { launch_stage(g, c->p, lo, hi < g.L ? hi : g.L - 1, st, 1, s); });
+}
+
 void mr_iteration(mr_ctx* c) {
   const Geo& g = c->g;
   const int L = g.L;
   hipStream_t s = c->stream;
-  auto stage = [&](int st) {
-    timed(c, MR_KC_STAGE, [&] { launch_stage(g, c->p, g.l0, L, st, s); });
-  };
+  auto stage = [&](int st) { stage_launch(c, g.l0, L, st, true, true); };
   project_range(c, L - 1, g.l0, PJ_Q0);
   if (c->s.remesh && g.l0 <= L - 1) {
     remesh(c, g.l0);
@@ -179,17 +189,18 @@ void lt_iteration(mr_ctx* c, int64_t n, int64_t N) {
     project_range(c, L - 1, lmin, PJ_Q0);
   }
   hipStream_t s = c->stream;
-  auto stage = [&](int lo, int hi, int st) {
-    timed(c, lo == L ? MR_KC_STAGE_FINEST : MR_KC_STAGE, [&] { launch_stage(g, c->p, lo, hi, st, s); });
-  };
   if (lmin > g.l0) project_range(c, lmin - 1, lmin - 1, PJ_CASEB);
   ghost_fill(c, lmin, 1);
-  stage(lmin, L, 1);
+  stage_launch(c, lmin, L, 1, true, true);
   project_range(c, L - 1, lmin, PJ_REF2);
   ghost_fill(c, lmin, 2);
-  for (int lev = L; lev >= lmin; lev--) {
-    if (lev < L) project_range(c, lev, lev, PJ_RK2);
-    stage(lev, lev, 2);
+  // stage-2 sweep L -> lmin: the bulk leaves of every level read only their
+  // own level, so they go first in one launch; the interface leaves of a
+  // level need the finer level's stage-2 values and its projection
+  stage_launch(c, lmin, L, 2, true, false);
+  for (int lev = L - 1; lev >= lmin; lev--) {
+    project_range(c, lev, lev, PJ_RK2);
+    stage_launch(c, lev, lev, 2, false, true);
   }
   if (g.rk == 2) {
     // RK2: the step ends after the second stage
@@ -199,9 +210,10 @@ void lt_iteration(mr_ctx* c, int64_t n, int64_t N) {
   }
   project_range(c, L - 1, lmin, PJ_REF3);
   ghost_fill(c, lmin, 3);
-  for (int lev = L; lev >= lmin; lev--) {
-    if (lev < L) project_range(c, lev, lev, PJ_RK3);
-    stage(lev, lev, 3);
+  stage_launch(c, lmin, L, 3, true, false);
+  for (int lev = L - 1; lev >= lmin; lev--) {
+    project_range(c, lev, lev, PJ_RK3);
+    stage_launch(c, lev, lev, 3, false, true);
   }
   const int lnext = (n + 1 == N) ? g.l0 : lmin_of(g, n + 1);
   timed(c, MR_KC_FINALIZE, [&] { launch_finalize(g, c->p, lnext, L, s); });
@@ -406,6 +418,7 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
   ALLOC(c->p.lcnt, int, LS_COUNT * (MRD_MAXLEV + 1));
   ALLOC(c->p.bcnt, int, LS_COUNT * (g.comp_first[L + 1] + 1));
   ALLOC(c->p.leafcnt, int, (int64_t)n_inst * (MRD_MAXLEV + 1));
+  ALLOC(c->p.items, unsigned long long, 3);
 #undef ALLOC
   c->p.dt = c->dt_d;
   c->p.eps = c->eps_d;
@@ -733,8 +746,17 @@ mr_status mr_level_updates(mr_ctx* c, int inst, int64_t* per_level) {
   return MR_OK;
 }
 
+mr_status mr_stage_items(mr_ctx* c, int64_t* per_stage) {
+  if (!c || !per_stage) return MR_EINVAL;
+  unsigned long long h[3] = {0ull, 0ull, 0ull};
+  HIPCHK(c, hipMemcpyAsync(h, c->p.items, sizeof h, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int i = 0; i < 3; i++) per_stage[i] = (int64_t)h[i];
+  return MR_OK;
+}
+
 mr_status mr_timing_start(mr_ctx* c, int kernel_class) {
-  if (!c || kernel_class < MR_KC_STAGE_FINEST || kernel_class > MR_KC_FINALIZE) return MR_EINVAL;
+  if (!c || kernel_class < MR_KC_STAGE_FINEST || kernel_class > MR_KC_STAGE_BULK) return MR_EINVAL;
   c->timed_class = kernel_class;
   c->ev_used = 0;
   return MR_OK;

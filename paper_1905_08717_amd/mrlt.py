@@ -27,8 +27,9 @@ EXPORTS = [
     "mr_get_leaves_inst", "mr_set_leaves", "mr_set_leaves_inst", "mr_stats", "mr_stats_inst",
     "mr_synchronize", "mr_last_error", "mr_destroy", "mr_level_updates", "mr_timing_start",
     "mr_timing_stop", "mr_load_finest_inst", "mr_clear_instance", "mr_instance_flags", "mr_set_eps",
+    "mr_stage_items",
 ]
-KC = {"stage_finest": 1, "stage": 2, "project": 3, "ghost": 4, "remesh": 5, "finalize": 6}
+KC = {"stage_finest": 1, "stage": 2, "project": 3, "ghost": 4, "remesh": 5, "finalize": 6, "stage_bulk": 7}
 
 
 class MrScheme(ctypes.Structure):
@@ -98,6 +99,7 @@ def load_library():
     L.mr_last_error.restype = ctypes.c_char_p
     L.mr_level_updates.argtypes = [vp, i32, ctypes.POINTER(i64)]
     L.mr_timing_start.argtypes = [vp, i32]
+    L.mr_stage_items.argtypes = [vp, ctypes.POINTER(i64)]
     L.mr_timing_stop.argtypes = [vp, dp, ctypes.POINTER(i64)]
     L.mr_load_finest_inst.argtypes = [vp, i32, vp]
     L.mr_clear_instance.argtypes = [vp, i32]
@@ -293,6 +295,12 @@ class Solver:
     def level_updates(self, inst: int = 0):
         arr = (ctypes.c_int64 * (MAXLEV + 1))()
         self._check(load_library().mr_level_updates(self._h, inst, arr), "mr_level_updates")
+        return np.array(arr[:], dtype=np.int64)
+
+    def stage_items(self):
+        """Cumulative leaf-stage updates of the bulk stage kernel, stages 1-3."""
+        arr = (ctypes.c_int64 * 3)()
+        self._check(load_library().mr_stage_items(self._h, arr), "mr_stage_items")
         return np.array(arr[:], dtype=np.int64)
 
     def timing_start(self, kernel_class: str):
