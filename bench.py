@@ -141,7 +141,9 @@ def systems_mode(args):
         solo_reqs = S.batched_euler_requests(args.requests or 256)
         n_solo = min(len(solo_reqs), args.solo_sample)
         a = S.run_one_at_a_time(solo_reqs[:n_solo])
-        same = all(np.array_equal(r.result[0], q.result[0]) and np.array_equal(r.result[1], q.result[1])
+        same = all((r.result is None and q.result is None and r.failed and q.failed) or
+                   (r.result is not None and q.result is not None and
+                    np.array_equal(r.result[0], q.result[0]) and np.array_equal(r.result[1], q.result[1]))
                    for r, q in zip(reqs[:n_solo], solo_reqs[:n_solo]))
         out = {"metric": "batched solves/s", "value": round(b["solves_per_s"], 3), "unit": "solves/s",
                "n_gpus": 1, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
@@ -176,7 +178,7 @@ def main():
     ap.add_argument("--pmc-dir", default="gpurun_out", help="traffic mode: folder of the four counter runs")
     ap.add_argument("--no-single", action="store_true", help="skip the single-solve reference run")
     ap.add_argument("--requests", type=int, default=0)
-    ap.add_argument("--solo-sample", type=int, default=64)
+    ap.add_argument("--solo-sample", type=int, default=32)
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--max-burgers-level", type=int, default=14)
     ap.add_argument("--hbm-budget", type=float, default=64.0, help="GiB for resident solves")

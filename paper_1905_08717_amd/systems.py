@@ -20,6 +20,7 @@ from __future__ import annotations
 import dataclasses
 import heapq
 import math
+import sys
 import time
 from typing import Dict, List, Optional, Tuple
 
@@ -153,6 +154,20 @@ class SlotPool:
         return out
 
 
+class _Progress:
+    """A line on stderr every `every` seconds (long runs stay visibly alive)."""
+
+    def __init__(self, what: str, every: float = 10.0):
+        self.what, self.every = what, every
+        self.t0 = self.last = time.perf_counter()
+
+    def __call__(self, msg: str):
+        now = time.perf_counter()
+        if now - self.last >= self.every:
+            self.last = now
+            print(f"[{self.what}] {now - self.t0:.1f} s: {msg}", file=sys.stderr, flush=True)
+
+
 def run_batched(reqs: List[Request]) -> Dict:
     """Advance all requests to completion, batched by problem class."""
     groups: Dict[tuple, List[Request]] = {}
@@ -166,19 +181,26 @@ def run_batched(reqs: List[Request]) -> Dict:
         pools.append(p)
     done = 0
     steps = 0
-    while done < len(reqs):
+    prog = _Progress("batched")
+    # a request that fails (non-finite state) is retired alone; it counts as
+    # ended but not as solved
+    while done + sum(len(p.failed) for p in pools) < len(reqs):
         for p in pools:
             steps += p.step()
             done += len(p.poll(time.perf_counter() - t0))
+        prog(f"{done}/{len(reqs)} solves done, {steps} slot macro steps")
     el = time.perf_counter() - t0
-    return {"seconds": el, "solves": len(reqs), "solves_per_s": len(reqs) / el, "slot_macro_steps": steps}
+    failed = sum(len(p.failed) for p in pools)
+    return {"seconds": el, "solves": done, "failed": failed, "solves_per_s": done / el,
+            "slot_macro_steps": steps}
 
 
 def run_one_at_a_time(reqs: List[Request]) -> Dict:
     """The plain GPU form: every request alone in a batch of one."""
     pools: Dict[tuple, SlotPool] = {}
     t0 = time.perf_counter()
-    for r in reqs:
+    prog = _Progress("one-at-a-time")
+    for k, r in enumerate(reqs):
         key = class_key(r.cfg)
         if key not in pools:
             pools[key] = SlotPool(r.cfg, 1, eps=[r.eps])
@@ -187,8 +209,11 @@ def run_one_at_a_time(reqs: List[Request]) -> Dict:
         while p.active():
             p.step()
             p.poll(time.perf_counter() - t0)
+            prog(f"solve {k + 1}/{len(reqs)}")
     el = time.perf_counter() - t0
-    return {"seconds": el, "solves": len(reqs), "solves_per_s": len(reqs) / el}
+    failed = sum(len(p.failed) for p in pools.values())
+    done = len(reqs) - failed
+    return {"seconds": el, "solves": done, "failed": failed, "solves_per_s": done / el}
 
 
 def serve(reqs: List[Request], hbm_budget: float, max_slots: int = 64) -> Dict:
@@ -203,7 +228,8 @@ def serve(reqs: List[Request], hbm_budget: float, max_slots: int = 64) -> Dict:
     t0 = time.perf_counter()
     finished: List[Request] = []
     nxt = 0
-    while len(finished) < len(reqs):
+    prog = _Progress("served")
+    while len(finished) + sum(len(p.failed) for p in pools.values()) < len(reqs):
         now = time.perf_counter() - t0
         while nxt < len(pending) and pending[nxt].arrival <= now:
             queue.append(pending[nxt])
@@ -233,13 +259,16 @@ def serve(reqs: List[Request], hbm_budget: float, max_slots: int = 64) -> Dict:
             stepped += p.step()
             for r in p.poll(time.perf_counter() - t0, keep_result=False):
                 finished.append(r)
+        prog(f"{len(finished)}/{len(reqs)} finished, {len(queue)} queued, {nxt} arrived")
         if stepped == 0 and nxt < len(pending) and not queue:
             wait = pending[nxt].arrival - (time.perf_counter() - t0)
             if wait > 0:
                 time.sleep(min(wait, 0.01))
     makespan = time.perf_counter() - t0
     lat = np.array([r.done_at - r.arrival for r in finished])
-    return {"requests": len(reqs), "makespan_s": makespan, "solves_per_s": len(reqs) / makespan,
+    failed = sum(len(p.failed) for p in pools.values())
+    return {"requests": len(reqs), "failed": failed, "makespan_s": makespan,
+            "solves_per_s": len(finished) / makespan,
             "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
             "admission_stalls": stalls, "classes": len(pools), "hbm_reserved_bytes": used}
 
