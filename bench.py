@@ -129,6 +129,54 @@ def traffic_record(args):
     print(json.dumps(rec), flush=True)
 
 
+def paper_tables(args):
+    """The paper's own 2D workloads (Sec. 5) on this GPU: inviscid Burgers
+    with Dirichlet boundary (t_f 0.9) and Euler Lax-Liu configuration 6
+    (t_f 0.25), fixed eps = 0.01, Courant number 0.5, finest levels L; each
+    with MRLT/NERK2, MRLT/NERK3 and the uniform scheme (eps = 0: every cell
+    is a leaf of level L, identical to FV on the finest grid).  Reports the
+    GPU time of each adaptive run as % of the uniform one and the mean
+    number of leaves as % of the 4^L finest cells, the paper's "CPU %" and
+    "Mem %" columns measured here."""
+    import torch
+    from paper_1905_08717_amd import mrlt
+    from paper_1905_08717_amd import workloads as W
+
+    def run(cfg, q0):
+        s = mrlt.Solver(cfg)
+        s.load_finest(torch.from_numpy(q0[None]).to("cuda"))
+        it = W.macro_iters(cfg)
+        mem, steps = 0.0, 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t = 0.0
+        while t < cfg["t_final"] * (1 - 1e-12):
+            if cfg["pde"] == "burgers":
+                dt = W.burgers_dt(cfg)
+            else:
+                dt = W.euler_dt(cfg, float(s.max_wavespeed()[0]), t)
+            s.lt_step(dt)
+            t += it * dt
+            mem += sum(s.stats()["leaves"])
+            steps += 1
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, mem / steps / (1 << (2 * cfg["L"])), steps
+
+    rows = []
+    for L in [int(x) for x in args.levels.split(",")]:
+        for name, mk, q0fn in (("burgers2d", W.burgers_2d, W.burgers_sinsin),
+                               ("laxliu6", W.euler_laxliu6, lambda L_: W.euler_quadrants(L_, W.LAXLIU6))):
+            q0 = q0fn(L)
+            for rk in (2, 3):
+                fv_t, _, _ = run(dict(mk(L=L, eps=0.0), rk=rk), q0)
+                mr_t, mem, steps = run(dict(mk(L=L), rk=rk), q0)
+                rows.append({"problem": name, "L": L, "method": f"MRLT/NERK{rk}", "gpu_s": round(mr_t, 3),
+                             "fv_gpu_s": round(fv_t, 3), "time_pct_of_fv": round(100 * mr_t / fv_t, 1),
+                             "mem_pct_of_fv": round(100 * mem, 1), "macro_steps": steps})
+                print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    print(json.dumps({"mode": "paper", "eps": 0.01, "rows": rows}), flush=True)
+
+
 def systems_mode(args):
     """Batched (256 uneven 2D Euler four-quadrant solves) or served (Poisson
     arrivals of Burgers / Nagumo requests) forms; one JSON line."""
@@ -174,7 +222,9 @@ def main():
     ap.add_argument("--batch", type=int, default=512)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", choices=["throughput", "batched", "served", "copycal", "traffic"], default="throughput")
+    ap.add_argument("--mode", choices=["throughput", "batched", "served", "copycal", "traffic", "paper"],
+                    default="throughput")
+    ap.add_argument("--levels", default="8,9,10", help="paper mode: finest levels")
     ap.add_argument("--pmc-dir", default="gpurun_out", help="traffic mode: folder of the four counter runs")
     ap.add_argument("--no-single", action="store_true", help="skip the single-solve reference run")
     ap.add_argument("--requests", type=int, default=0)
@@ -193,6 +243,9 @@ def main():
         return
     if args.mode == "traffic":
         traffic_record(args)
+        return
+    if args.mode == "paper":
+        paper_tables(args)
         return
     if args.mode != "throughput":
         systems_mode(args)

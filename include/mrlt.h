@@ -48,7 +48,12 @@ typedef enum {
 } mr_status;
 
 enum { MR_PDE_ADVECTION = 0, MR_PDE_BURGERS = 1, MR_PDE_NAGUMO = 2, MR_PDE_EULER = 3, MR_PDE_LINEAR = 4 };
-enum { MR_BC_PERIODIC = 0, MR_BC_NEUMANN = 1 };
+/* Boundary conditions per axis (both sides the same kind): periodic wrap;
+ * homogeneous Neumann, stencil cells outside mirror evenly (q_{-1} = q_0,
+ * q_{-2} = q_1); homogeneous Dirichlet (Q = 0 on the boundary, the paper's
+ * 2D Burgers problem of Sec. 5), mirror cells enter with the opposite sign
+ * (q_{-1} = -q_0, q_{-2} = -q_1); scalar PDEs only.                       */
+enum { MR_BC_PERIODIC = 0, MR_BC_NEUMANN = 1, MR_BC_DIRICHLET = 2 };
 
 #define MR_MAXLEV 24
 
@@ -66,8 +71,8 @@ enum { MR_BC_PERIODIC = 0, MR_BC_NEUMANN = 1 };
  *  thresh  1: eps_l = 2^{d(l-L)} eps for details of level l, 0: fixed eps
  *  reflux  1: conservative correction of coarse leaves at level interfaces
  *  remesh  1: remesh the evolved levels every iteration, 0: frozen tree
- *  bc      per dimension, low/high side: periodic or homogeneous Neumann
- *          (even reflection); periodic must be set on both sides
+ *  bc      per dimension, low/high side: MR_BC_PERIODIC, MR_BC_NEUMANN or
+ *          MR_BC_DIRICHLET (see above); both sides of an axis the same
  *  lo, hi  box, per dimension
  *  detail_scale  per component divisor in the detail norm (0 -> 1.0)     */
 typedef struct {
@@ -142,8 +147,9 @@ mr_status mr_lt_step_batch(mr_ctx* c, const double* dt_L);
  * q_out: device, [n_inst][m][2^{dL}], x fastest.                          */
 mr_status mr_reconstruct(mr_ctx* c, double* q_out);
 
-/* CFL helper: per instance the maximum over leaves of |u| (Burgers),
- * sum_i (|u_i| + c) (Euler), sum_i |a_i| (advection), 0 otherwise.
+/* CFL helper: per instance the maximum over leaves of sum_i |f_i'(q)|:
+ * d |u| (Burgers), sum_i (|u_i| + c) (Euler), sum_i |a_i| (advection), 0
+ * otherwise (diffusion and reaction limits are the caller's).
  * out: host array of n_inst values.                                        */
 mr_status mr_max_wavespeed(mr_ctx* c, double* out);
 

@@ -110,11 +110,22 @@ static void ccoord(const mro_ctx* c, int lev, int64_t i, int* x) {
 }
 
 /* Stencil coordinate: periodic wraps, homogeneous Neumann reflects evenly
- * (q_{-1} = q_0, q_{-2} = q_1), the reading of the paper's Neumann BC.   */
+ * (q_{-1} = q_0, q_{-2} = q_1), the reading of the paper's Neumann BC.
+ * Homogeneous Dirichlet (Q = 0 on the boundary, Sec. 5 2D Burgers) uses the
+ * same mirror cell with the sign flipped (q_{-1} = -q_0, q_{-2} = -q_1):
+ * see stencil_flip.                                                        */
 static int map_stencil(const mro_ctx* c, int a, int i, int n) {
   if (i < 0) return c->s.bc[a][0] == MRO_BC_PERIODIC ? i + n : -1 - i;
   if (i >= n) return c->s.bc[a][1] == MRO_BC_PERIODIC ? i - n : 2 * n - 1 - i;
   return i;
+}
+
+/* 1 when stencil coordinate i along axis a lies outside the domain on a
+ * Dirichlet side: the mirrored value enters with its sign flipped.        */
+static int stencil_flip(const mro_ctx* c, int a, int i, int n) {
+  if (i < 0) return c->s.bc[a][0] == MRO_BC_DIRICHLET;
+  if (i >= n) return c->s.bc[a][1] == MRO_BC_DIRICHLET;
+  return 0;
 }
 
 /* Neighbourhood coordinate in the remesh rules: wraps when periodic and is
@@ -256,14 +267,21 @@ static int gather3(mro_ctx* c, int lev, const int* x, int stage, slot_fn pick, d
       for (int ox = -1; ox <= 1; ox++) {
         int y[3] = {0, 0, 0};
         int off[3] = {ox, oy, oz};
-        for (int a = 0; a < d; a++) y[a] = map_stencil(c, a, x[a] + off[a], n);
+        int flip = 0;
+        for (int a = 0; a < d; a++) {
+          y[a] = map_stencil(c, a, x[a] + off[a], n);
+          flip ^= stencil_flip(c, a, x[a] + off[a], n);
+        }
         int64_t i = cidx(c, lev, y);
         int st = c->lv[lev].st[i];
         if (st == ABSENT) return 0;
         int sl = pick(c, lev, st, stage);
         if (sl < 0) return 0;
         int s = (ox + 1) + 3 * (oy + 1) + 9 * (oz + 1);
-        for (int k = 0; k < c->m; k++) S[k * 27 + s] = SL(c, lev, sl, k, i);
+        for (int k = 0; k < c->m; k++) {
+          double v = SL(c, lev, sl, k, i);
+          S[k * 27 + s] = flip ? -v : v;
+        }
       }
   return 1;
 }
@@ -509,6 +527,8 @@ static int leaf_face_flux(mro_ctx* c, int lev, const int* x, int dir, int side, 
       int y[3] = {x[0], x[1], x[2]};
       y[dir] = map_stencil(c, dir, a - 1 + j, n);
       stage_value(c, lev, y, stage, cells + j * m);
+      if (stencil_flip(c, dir, a - 1 + j, n))
+        for (int k = 0; k < m; k++) cells[j * m + k] = -cells[j * m + k];
     }
     face_flux(c, lev, dir, cells, F);
     return 0;
@@ -1172,6 +1192,11 @@ int mro_init(int dim, int L, double eps, const mro_scheme* s, mro_ctx** out) {
   if (L - s->l0 > 20) return MRO_EINVAL;
   for (int a = 0; a < dim; a++) {
     if ((s->bc[a][0] == MRO_BC_PERIODIC) != (s->bc[a][1] == MRO_BC_PERIODIC)) return MRO_EINVAL;
+    for (int side = 0; side < 2; side++) {
+      if (s->bc[a][side] < MRO_BC_PERIODIC || s->bc[a][side] > MRO_BC_DIRICHLET) return MRO_EINVAL;
+      /* a homogeneous Dirichlet value is meaningful for a scalar field only */
+      if (s->bc[a][side] == MRO_BC_DIRICHLET && s->pde == MRO_PDE_EULER) return MRO_EINVAL;
+    }
     if (!(s->hi[a] > s->lo[a])) return MRO_EINVAL;
   }
   mro_ctx* c = (mro_ctx*)calloc(1, sizeof *c);
@@ -1318,10 +1343,13 @@ int mro_reconstruct(mro_ctx* c, double* q_out) {
         for (int oz = (d > 2 ? -1 : 0); oz <= (d > 2 ? 1 : 0); oz++)
           for (int oy = (d > 1 ? -1 : 0); oy <= (d > 1 ? 1 : 0); oy++)
             for (int ox = -1; ox <= 1; ox++) {
-              int off[3] = {ox, oy, oz}, y[3] = {0, 0, 0};
-              for (int a = 0; a < d; a++) y[a] = map_stencil(c, a, p[a] + off[a], np);
-              S[(ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)] =
-                  prev[(int64_t)k * c->lv[lev - 1].ncell + cidx(c, lev - 1, y)];
+              int off[3] = {ox, oy, oz}, y[3] = {0, 0, 0}, flip = 0;
+              for (int a = 0; a < d; a++) {
+                y[a] = map_stencil(c, a, p[a] + off[a], np);
+                flip ^= stencil_flip(c, a, p[a] + off[a], np);
+              }
+              const double v = prev[(int64_t)k * c->lv[lev - 1].ncell + cidx(c, lev - 1, y)];
+              S[(ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)] = flip ? -v : v;
             }
         int cb = (x[0] & 1) | ((x[1] & 1) << 1) | ((x[2] & 1) << 2);
         cur[(int64_t)k * LV->ncell + i] = predict1(d, S, cb);
@@ -1346,7 +1374,8 @@ int mro_max_wavespeed(mro_ctx* c, double* out) {
       double q[5], v = 0.0;
       for (int k = 0; k < m; k++) q[k] = SL(c, lev, S_Q0, k, i);
       if (c->s.pde == MRO_PDE_BURGERS) {
-        v = fabs(q[0]);
+        /* f_i(u) = u^2/2 in every direction: sum_i |f_i'(u)| */
+        for (int j = 0; j < d; j++) v = (j == 0) ? fabs(q[0]) : (v + fabs(q[0]));
       } else if (c->s.pde == MRO_PDE_EULER) {
         double w[5];
         euler_prim(d, c->s.gamma - 1.0, q, w);

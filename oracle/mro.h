@@ -26,7 +26,7 @@ enum { MRO_OK = 0, MRO_EINVAL = -1, MRO_ENOMEM = -2, MRO_ESTATE = -4,
 enum { MRO_PDE_ADVECTION = 0, MRO_PDE_BURGERS = 1, MRO_PDE_NAGUMO = 2,
        MRO_PDE_EULER = 3, MRO_PDE_LINEAR = 4 };
 
-enum { MRO_BC_PERIODIC = 0, MRO_BC_NEUMANN = 1 };
+enum { MRO_BC_PERIODIC = 0, MRO_BC_NEUMANN = 1, MRO_BC_DIRICHLET = 2 /* homogeneous, scalar PDEs */ };
 
 #define MRO_MAXLEV 30
 

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libmro.so")
 SRC = os.path.join(HERE, "mro.c")
 
 PDE = {"advection": 0, "burgers": 1, "nagumo": 2, "euler": 3, "linear": 4}
-BC = {"periodic": 0, "neumann": 1}
+BC = {"periodic": 0, "neumann": 1, "dirichlet": 2}
 
 OK, EINVAL, ENOMEM, ESTATE, ENONFINITE = 0, -1, -2, -4, -5
 MAXLEV = 30

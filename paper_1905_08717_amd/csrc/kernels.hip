@@ -91,6 +91,12 @@ __device__ __forceinline__ int map_st(int i, int n, int per) {
   if (i >= n) return per ? i - n : 2 * n - 1 - i;
   return i;
 }
+// 1 when stencil coordinate i lies outside on an axis with homogeneous
+// Dirichlet conditions: the mirror cell of map_st enters with its sign
+// flipped (q_{-1} = -q_0, q_{-2} = -q_1)
+__device__ __forceinline__ bool st_flip(int i, int n, int dirichlet) {
+  return dirichlet && (i < 0 || i >= n);
+}
 // neighbourhood coordinate: wraps when periodic, -1 outside otherwise
 __device__ __forceinline__ int map_nb(int i, int n, int per) {
   if (i < 0) return per ? i + n : -1;
@@ -158,9 +164,13 @@ __device__ __forceinline__ bool gather27(const Geo& g, const Dev& p, const doubl
         int y[3] = {map_st(x[0] + ox, n, g.periodic[0]), 0, 0};
         if (D > 1) y[1] = map_st(x[1] + oy, n, g.periodic[1]);
         if (D > 2) y[2] = map_st(x[2] + oz, n, g.periodic[2]);
+        bool fl = st_flip(x[0] + ox, n, g.dirichlet[0]);
+        if (D > 1) fl = fl != st_flip(x[1] + oy, n, g.dirichlet[1]);
+        if (D > 2) fl = fl != st_flip(x[2] + oz, n, g.dirichlet[2]);
         const int64_t G = ibase + (int64_t)menc<D>(y);
         ok = ok && (p.st[G] != ST_ABSENT);
-        S[(ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)] = src[(int64_t)k * g.Ntot + G];
+        const double v = src[(int64_t)k * g.Ntot + G];
+        S[(ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)] = fl ? -v : v;
       }
   return ok;
 }
@@ -384,7 +394,11 @@ __global__ void k_recon_level(Geo g, Dev p, int lev, double* dense) {
             int y[3] = {map_st(px[0] + ox, n, g.periodic[0]), 0, 0};
             if (D > 1) y[1] = map_st(px[1] + oy, n, g.periodic[1]);
             if (D > 2) y[2] = map_st(px[2] + oz, n, g.periodic[2]);
-            S[(ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)] = dense[(int64_t)k * g.Ntot + ibp + (int64_t)menc<D>(y)];
+            bool fl = st_flip(px[0] + ox, n, g.dirichlet[0]);
+            if (D > 1) fl = fl != st_flip(px[1] + oy, n, g.dirichlet[1]);
+            if (D > 2) fl = fl != st_flip(px[2] + oz, n, g.dirichlet[2]);
+            const double v = dense[(int64_t)k * g.Ntot + ibp + (int64_t)menc<D>(y)];
+            S[(ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)] = fl ? -v : v;
           }
       pred_terms<D>(S, T);
       dense[(int64_t)k * g.Ntot + G] = pred_child<D>(T, cb);
@@ -738,9 +752,13 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
           if ((PDE == PDE_NAGUMO || PDE == PDE_LINEAR) && (o == -2 || o == 2)) continue;
           int y[3] = {x[0], x[1], x[2]};
           y[dir] = map_st(x[dir] + o, n, g.periodic[dir]);
+          const bool fl = st_flip(x[dir] + o, n, g.dirichlet[dir]);
           const int64_t Gy = o == 0 ? G : ib + (int64_t)menc<D>(y);
 #pragma unroll
-          for (int k = 0; k < M; k++) c5[o + 2][k] = cur[(int64_t)k * NT + Gy];
+          for (int k = 0; k < M; k++) {
+            const double v = cur[(int64_t)k * NT + Gy];
+            c5[o + 2][k] = fl ? -v : v;
+          }
         }
         if (PDE == PDE_NAGUMO || PDE == PDE_LINEAR) {
 #pragma unroll
@@ -1967,7 +1985,8 @@ __global__ void k_wavespeed(Geo g, Dev p, int lev, unsigned long long* out) {
     double q[5], v = 0.0;
     for (int k = 0; k < g.m; k++) q[k] = p.q[SL_Q0][(int64_t)k * g.Ntot + G];
     if (g.pde == PDE_BURGERS) {
-      v = fabs(q[0]);
+      // f_i(u) = u^2/2 in every direction: sum_i |f_i'(u)|
+      for (int j = 0; j < D; j++) v = (j == 0) ? fabs(q[0]) : (v + fabs(q[0]));
     } else if (g.pde == PDE_EULER) {
       double w[5];
       euler_prim<D>(g.gamma - 1.0, q, w);

@@ -39,6 +39,7 @@ struct Geo {
   int rk;  // 3: compact RK3 (NERK3), 2: compact RK2 (NERK2)
   int lt;  // 1: local time stepping, 0: one global step for every level
   int periodic[3];
+  int dirichlet[3];  // homogeneous Dirichlet on both sides of the axis
   int64_t n[MRD_MAXLEV + 1];     // cells per instance at level l (2^{d l})
   int64_t off[MRD_MAXLEV + 1];   // first global index of level l
   int64_t Ntot;                  // total cells over levels and instances

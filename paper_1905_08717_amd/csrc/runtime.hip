@@ -298,7 +298,10 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
     return MR_EINVAL;
   if (s->recon < 0 || s->recon > 2) return MR_EINVAL;
   for (int a = 0; a < dim; a++) {
-    if ((s->bc[a][0] == MR_BC_PERIODIC) != (s->bc[a][1] == MR_BC_PERIODIC)) return MR_EINVAL;
+    // one kind of condition per axis (both sides); Dirichlet for scalar fields
+    if (s->bc[a][0] != s->bc[a][1]) return MR_EINVAL;
+    if (s->bc[a][0] < MR_BC_PERIODIC || s->bc[a][0] > MR_BC_DIRICHLET) return MR_EINVAL;
+    if (s->bc[a][0] == MR_BC_DIRICHLET && s->pde == MR_PDE_EULER) return MR_EINVAL;
     if (!(s->hi[a] > s->lo[a])) return MR_EINVAL;
   }
   for (int i = 0; i < n_inst; i++)
@@ -328,7 +331,10 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
   g.reflux = s->reflux;
   g.rk = s->rk;
   g.lt = s->lt;
-  for (int a = 0; a < 3; a++) g.periodic[a] = a < dim && s->bc[a][0] == MR_BC_PERIODIC;
+  for (int a = 0; a < 3; a++) {
+    g.periodic[a] = a < dim && s->bc[a][0] == MR_BC_PERIODIC;
+    g.dirichlet[a] = a < dim && s->bc[a][0] == MR_BC_DIRICHLET;
+  }
   int64_t off = 0, rc = 0, rf = 0;
   for (int lev = g.l0; lev <= L; lev++) {
     g.n[lev] = (int64_t)1 << (dim * lev);

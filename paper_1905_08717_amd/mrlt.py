@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libmrlt.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENONFINITE, ECAPACITY = 0, -1, -2, -3, -4, -5, -6
 PDE = {"advection": 0, "burgers": 1, "nagumo": 2, "euler": 3, "linear": 4}
-BC = {"periodic": 0, "neumann": 1}
+BC = {"periodic": 0, "neumann": 1, "dirichlet": 2}
 MAXLEV = 24
 
 # every symbol declared in include/mrlt.h

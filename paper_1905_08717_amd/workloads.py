@@ -55,6 +55,33 @@ def euler_1d(L: int = 9, eps: float = 1e-3, l0: int = 2) -> dict:
                 reflux=1, remesh=1, t_final=0.2, cfl=0.5)
 
 
+def burgers_2d(L: int = 9, eps: float = 1e-2, l0: int = 2) -> dict:
+    """The paper's 2D inviscid Burgers problem (Sec. 5): Q_t + (Q^2/2)_x +
+    (Q^2/2)_y = 0 on [0,1]^2, Q0 = sin(2 pi x) sin(2 pi y), homogeneous
+    Dirichlet boundary, Courant number 0.5, fixed threshold eps = 0.01,
+    t_f = 0.9."""
+    return dict(name=f"burgers2d_L{L}", dim=2, L=L, l0=l0, eps=eps, pde="burgers", nu=0.0,
+                bc="dirichlet", lo=[0.0, 0.0, 0.0], hi=[1.0, 1.0, 1.0], recon=1, thresh=0,
+                reflux=1, remesh=1, t_final=0.9, cfl=0.5)
+
+
+def euler_laxliu6(L: int = 9, eps: float = 1e-2, l0: int = 2) -> dict:
+    """The paper's 2D Euler problem (Sec. 5): Lax-Liu configuration 6 on
+    [0,1]^2, Neumann, gamma = 1.4, Courant number 0.5, fixed threshold
+    eps = 0.01, t_f = 0.25."""
+    return dict(name=f"laxliu6_L{L}", dim=2, L=L, l0=l0, eps=eps, pde="euler", gamma=1.4,
+                bc="neumann", lo=[0.0, 0.0, 0.0], hi=[1.0, 1.0, 1.0], recon=1, thresh=0,
+                reflux=1, remesh=1, t_final=0.25, cfl=0.5)
+
+
+def linear_1d_dirichlet(L: int, eps: float = 0.0, l0: int = 2, nu: float = 1.0) -> dict:
+    """Heat equation u_t = nu u_xx on [0,1] with u = 0 at both ends (test
+    problem with a closed-form solution)."""
+    return dict(name=f"heat1d_L{L}", dim=1, L=L, l0=l0, eps=eps, pde="linear", nu=nu, k_react=0.0,
+                bc="dirichlet", lo=[0.0, 0.0, 0.0], hi=[1.0, 1.0, 1.0], recon=1, thresh=1,
+                reflux=1, remesh=1, t_final=0.01, cfl=0.25)
+
+
 def ncomp(cfg: dict) -> int:
     return cfg["dim"] + 2 if cfg["pde"] == "euler" else 1
 
@@ -68,11 +95,11 @@ def macro_iters(cfg: dict) -> int:
 
 
 def burgers_dt(cfg: dict, umax: float = 1.0) -> float:
-    """dt_L for the 1D Burgers configuration: CFL sigma on the finest level
-    with the diffusive term, rounded so that t_final is reached after a whole
-    number of macro steps."""
+    """dt_L for a Burgers configuration: CFL sigma on the finest level (rate
+    d |u|max / dx plus the diffusive term), rounded so that t_final is
+    reached after a whole number of macro steps."""
     dx = 1.0 / (1 << cfg["L"])
-    dt_cfl = cfg["cfl"] / (umax / dx + 2 * cfg["dim"] * cfg["nu"] / dx ** 2)
+    dt_cfl = cfg["cfl"] / (cfg["dim"] * umax / dx + 2 * cfg["dim"] * cfg["nu"] / dx ** 2)
     it = macro_iters(cfg)
     nmac = math.ceil(cfg["t_final"] / (it * dt_cfl))
     return cfg["t_final"] / (nmac * it)
@@ -149,6 +176,26 @@ def nagumo_front(L: int, seed: int = SEED, width: float = 0.02, amp: float = 0.0
     return avg.reshape(1, n * n)
 
 
+def burgers_sinsin(L: int) -> np.ndarray:
+    """Exact cell averages of sin(2 pi x) sin(2 pi y) on [0,1]^2 (a product
+    of the 1D averages)."""
+    a = burgers_sine(L)[0]
+    n = 1 << L
+    return np.outer(a, a).reshape(1, n * n)
+
+
+def sine_half(L: int) -> np.ndarray:
+    """Exact cell averages of sin(pi x) on [0,1]."""
+    n = 1 << L
+    xe = np.arange(n + 1) / n
+    return ((np.cos(np.pi * xe[:-1]) - np.cos(np.pi * xe[1:])) * (n / np.pi)).reshape(1, n)
+
+
+# Lax-Liu configuration 6: (rho, u, v, p) of quadrants 1..4 (the paper's
+# table of initial conditions for the 2D Euler equations)
+LAXLIU6 = ((1.0, 0.75, -0.5, 1.0), (2.0, 0.75, 0.5, 1.0), (1.0, -0.75, 0.5, 1.0), (3.0, -0.75, -0.5, 1.0))
+
+
 def euler_state(rho, u, v, w, p, gamma=1.4, dim=3):
     vel = [u, v, w][:dim]
     E = p / (gamma - 1.0) + 0.5 * rho * sum(x * x for x in vel)
@@ -221,6 +268,10 @@ def euler_shock_tube(L: int, left=(1.0, 0.0, 1.0), right=(0.125, 0.0, 0.1), x0: 
 
 def initial_data(cfg: dict, seed: int = SEED) -> np.ndarray:
     name = cfg["pde"]
+    if cfg.get("name", "").startswith("burgers2d"):
+        return burgers_sinsin(cfg["L"])
+    if cfg.get("name", "").startswith("laxliu6"):
+        return euler_quadrants(cfg["L"], LAXLIU6, cfg.get("gamma", 1.4))
     if name == "burgers":
         return burgers_sine(cfg["L"])
     if name == "nagumo":

@@ -16,6 +16,14 @@ import numpy as np
 def _pad(q: np.ndarray, axis: int, bc: str) -> np.ndarray:
     width = [(0, 0)] * q.ndim
     width[axis] = (2, 2)
+    if bc == "dirichlet":
+        # homogeneous Dirichlet: mirrored cells with the opposite sign
+        P = np.pad(q, width, mode="symmetric")
+        idx = [slice(None)] * q.ndim
+        for sl in (slice(0, 2), slice(-2, None)):
+            idx[axis] = sl
+            P[tuple(idx)] = -P[tuple(idx)]
+        return P
     return np.pad(q, width, mode="wrap" if bc == "periodic" else "symmetric")
 
 

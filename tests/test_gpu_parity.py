@@ -82,6 +82,35 @@ def test_burgers_1d_full_config_to_t_final(mods):
     assert abs(s.stats()["t"] - 0.5) < 1e-12
 
 
+def test_burgers_2d_dirichlet_paper_problem(mods):
+    # the paper's 2D inviscid Burgers problem: homogeneous Dirichlet,
+    # sin(2 pi x) sin(2 pi y), fixed threshold 0.01
+    cfg = W.burgers_2d(L=7)
+    run_pair(mods, cfg, W.burgers_sinsin(7), [W.burgers_dt(cfg)] * 3)
+
+
+def test_burgers_2d_dirichlet_to_t_final(mods):
+    cfg = W.burgers_2d(L=6)
+    dt = W.burgers_dt(cfg)
+    nmac = round(cfg["t_final"] / (dt * W.macro_iters(cfg)))
+    o, s = run_pair(mods, cfg, W.burgers_sinsin(6), [dt] * nmac)
+    assert abs(s.stats()["t"] - 0.9) < 1e-12
+    rg = s.reconstruct().cpu().numpy()[0]
+    assert np.all(rel_l1(rg, o.reconstruct()) <= 1e-10)
+
+
+def test_laxliu6_paper_problem(mods):
+    cfg = W.euler_laxliu6(L=7)
+    run_pair(mods, cfg, W.euler_quadrants(7, W.LAXLIU6),
+             [lambda o: W.euler_dt(cfg, o.max_wavespeed(), o.stats()["t"])] * 3)
+
+
+def test_heat_1d_dirichlet(mods):
+    cfg = W.linear_1d_dirichlet(9, eps=1e-4)
+    dx = 1.0 / (1 << 9)
+    run_pair(mods, cfg, W.sine_half(9), [0.25 * dx * dx / 2] * 3)
+
+
 @pytest.mark.parametrize("L", [12, 13])
 def test_euler_1d_deep_tree(mods, L):
     # levels with >= 4096 cells take the 16-cell group path of the list

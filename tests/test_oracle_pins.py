@@ -15,6 +15,9 @@
 * Constant states are preserved (all sync coefficients sum to one).
 * Mass is conserved to round-off with the conservative flux accumulation.
 * Table 1 of Sec. 4.5: FV/RK3 order 3, MRLT/NERK3 order 2.
+* Homogeneous Dirichlet (the paper's 2D Burgers problem): eps = 0 is the
+  uniform scheme with odd-mirrored boundary cells, and the heat equation
+  converges at second order to exp(-pi^2 t) sin(pi x).
 * Viscous Burgers converges to the Cole-Hopf solution; the 1D Euler shock
   tube converges to the exact Riemann solution; a planar 3D problem reduces
   to 1D exactly; the spherical 3D problem keeps octahedral symmetry.
@@ -43,6 +46,8 @@ CASES_T5 = [
     ("euler2d", W.euler_2d(L=5, eps=0.0), lambda c: W.euler_quadrants_seeded(5, W.SEED), 1e-3, 1),
     ("euler3d", W.euler_3d(L=4, eps=0.0), lambda c: W.euler_sphere(4), 5e-3, 1),
     ("euler1d", W.euler_1d(L=6, eps=0.0), lambda c: W.euler_shock_tube(6), 1e-3, 2),
+    ("burgers2d_dirichlet", W.burgers_2d(L=5, eps=0.0), lambda c: W.burgers_sinsin(5), 4e-3, 1),
+    ("heat1d_dirichlet", W.linear_1d_dirichlet(L=6), lambda c: W.sine_half(6) + 0.0, 2e-5, 2),
 ]
 
 
@@ -317,6 +322,61 @@ def _burgers_to(oracle_mod, L, eps, nu, t):
     for _ in range(nmac):
         o.lt_step(t / (nmac * it))
     return o.reconstruct()[0]
+
+
+def test_heat_dirichlet_converges_to_closed_form(oracle_mod):
+    """u_t = u_xx on [0,1], u = 0 at both ends, u0 = sin(pi x): the cell
+    averages of exp(-pi^2 t) sin(pi x) are the exact solution.  The scheme
+    is second order in space; a wrong boundary value (even instead of odd
+    mirror, or a sign error) leaves an O(1) boundary error and no order."""
+    t_end = 0.01
+    errs = []
+    for L in (5, 6, 7):
+        cfg = W.linear_1d_dirichlet(L, eps=0.0)
+        dx = 1.0 / (1 << L)
+        it = W.macro_iters(cfg)
+        nmac = math.ceil(t_end / (it * 0.25 * dx * dx / 2))
+        dt = t_end / (nmac * it)
+        o = oracle_mod.Oracle(cfg)
+        o.load_finest(W.sine_half(L))
+        for _ in range(nmac):
+            o.lt_step(dt)
+        got = o.reconstruct()[0]
+        ex = W.sine_half(L)[0] * math.exp(-math.pi ** 2 * t_end)
+        errs.append(np.abs(got - ex).mean())
+    p1, p2 = math.log2(errs[0] / errs[1]), math.log2(errs[1] / errs[2])
+    assert errs[-1] < 2e-5, errs
+    assert 1.7 < p1 < 2.4 and 1.7 < p2 < 2.4, (errs, p1, p2)
+    # adaptive (eps = 1e-4): the thresholding error stays of the order of eps
+    cfg = W.linear_1d_dirichlet(7, eps=1e-4)
+    o = oracle_mod.Oracle(cfg)
+    o.load_finest(W.sine_half(7))
+    it = W.macro_iters(cfg)
+    nmac = math.ceil(t_end / (it * 0.25 / 128 ** 2 / 2))
+    for _ in range(nmac):
+        o.lt_step(t_end / (nmac * it))
+    ex = W.sine_half(7)[0] * math.exp(-math.pi ** 2 * t_end)
+    assert np.abs(o.reconstruct()[0] - ex).mean() < 1e-4
+
+
+def test_dirichlet_changes_only_the_boundary_values(oracle_mod):
+    """Dirichlet and Neumann runs of the same heat problem agree in the
+    interior far from the walls after a short time, and differ next to
+    them (the odd mirror pulls the wall cells towards zero)."""
+    L = 7
+    cfg_d = W.linear_1d_dirichlet(L, eps=0.0)
+    cfg_n = dict(cfg_d, bc="neumann")
+    q0 = np.ones((1, 1 << L))
+    res = []
+    for cfg in (cfg_d, cfg_n):
+        o = oracle_mod.Oracle(cfg)
+        o.load_finest(q0)
+        o.lt_step(1e-6)
+        res.append(o.reconstruct()[0])
+    d, n = res
+    assert np.array_equal(n, q0[0])                    # constant state under Neumann
+    assert d[0] < 0.9 and d[-1] < 0.9                   # pulled down at the walls
+    assert np.array_equal(d[20:-20], n[20:-20])        # untouched in the interior
 
 
 def test_viscous_burgers_converges_to_cole_hopf(oracle_mod):
