@@ -985,6 +985,10 @@ static constexpr uint8_t RF_W = 2;
 // block summaries (4096-cell blocks of a level): any cell exists / is
 // internal / is a leaf
 static constexpr unsigned BS_EXIST = 1u, BS_INT = 2u, BS_LEAF = 4u;
+// level flags (Dev::lflag): a cell / leaf / internal node exists (set by
+// every list compaction from its totals), some W mark exists (set before
+// the apply passes), a cell exists after this remesh's apply pass
+static constexpr unsigned LF_EXIST = 1u, LF_LEAF = 2u, LF_INT = 4u, LF_W = 8u, LF_NEW = 16u;
 static constexpr int GRP = 16;            // cells per lane in the dense passes of large levels
 
 // true when the cell's instance is outside the remesh window
@@ -1079,6 +1083,7 @@ __device__ __forceinline__ T block_exscan(T v, T* sh, T* tot) {
 // flagged in `mask`; returns their number, block-local indices in `items`
 template <int G>
 __device__ __forceinline__ int block_items(uint32_t mask, int* items, int* sh) {
+  if (!__syncthreads_or(mask != 0u)) return 0;  // nothing anywhere: one barrier
   int tot;
   int k = block_exscan<int>(__popc(mask), sh, &tot);
   while (mask) {
@@ -1102,6 +1107,18 @@ __global__ __launch_bounds__(TPB) void k_clear_w(Geo g, Dev p, int lo, int hi) {
     if (t < n256) *reinterpret_cast<uint4*>(p.rf + g.off[lev] + t) = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
     if (threadIdx.x == 0) p.wsum[sb] = 0;
+  }
+}
+
+// before the apply passes of a remesh at la: LF_W on levels la..L-1 from
+// the block W flags, LF_NEW cleared on levels la..L (one workgroup)
+__global__ __launch_bounds__(TPB) void k_level_w(Geo g, Dev p, int la) {
+  for (int lev = la; lev <= g.L; lev++) {
+    int any = 0;
+    if (lev <= g.L - 1)
+      for (int64_t j = g.bs_off[lev] + threadIdx.x; j < g.bs_off[lev + 1]; j += TPB) any |= p.wsum[j];
+    any = __syncthreads_or(any);
+    if (threadIdx.x == 0) p.lflag[lev] = (p.lflag[lev] & ~(LF_W | LF_NEW)) | (any ? LF_W : 0u);
   }
 }
 
@@ -1298,6 +1315,12 @@ __global__ __launch_bounds__(TPB) void k_apply(Geo g, Dev p, int lev, int la) {
   const int64_t nl = g.n[lev], N = g.B * nl;
   uint8_t* stl = p.st + g.off[lev];
   const uint8_t* stp = p.st + g.off[lev - 1];
+  // the whole level stays absent: nothing exists on it and no parent will
+  // be internal (W marks above la, internal nodes on the frozen level)
+  {
+    const unsigned fl = p.lflag[lev], fp = lev > g.l0 ? p.lflag[lev - 1] : 0u;
+    if (!(fl & LF_EXIST) && (lev == la || !(fp & (lev - 1 >= la ? LF_W : LF_INT)))) return;
+  }
   if (threadIdx.x == 0) bor = 0u;
   __syncthreads();
   for (int64_t tb = (int64_t)blockIdx.x * (TPB * G); tb < N; tb += (int64_t)gridDim.x * (TPB * G)) {
@@ -1348,25 +1371,52 @@ __global__ __launch_bounds__(TPB) void k_apply(Geo g, Dev p, int lev, int la) {
         if (bits) atomicOr(&bor, bits);
       }
     }
-    const int cnt = block_items<G>(mask, items, sh);
+    // work items: G = 16, one per sibling group with new cells (one parent
+    // stencil feeds all its new children; the child mask rides in bits
+    // 16-23); G = 1, one per new cell
+    int cnt;
+    if (G == 16) {
+      constexpr uint32_t CM = (1u << (1 << D)) - 1u;
+      uint32_t gmask = 0u;
+#pragma unroll
+      for (int gi = 0; gi < (16 >> D); gi++)
+        if ((mask >> (gi << D)) & CM) gmask |= 1u << gi;
+      cnt = 0;
+      if (__syncthreads_or(gmask != 0u)) {
+        int k = block_exscan<int>(__popc(gmask), sh, &cnt);
+        while (gmask) {
+          const int gi = __builtin_ctz(gmask);
+          gmask &= gmask - 1u;
+          items[k++] = ((int)threadIdx.x * 16 + (gi << D)) | (int)(((mask >> (gi << D)) & CM) << 16);
+        }
+        __syncthreads();
+      }
+    } else {
+      cnt = block_items<G>(mask, items, sh);
+    }
     // G = 16 blocks are the summary blocks; G = 1 levels keep no summary
     if (threadIdx.x == 0) {
       if (G == 16) p.bsum[g.bs_off[lev] + sb] = (uint8_t)bor;
+      if (bor & BS_EXIST) atomicOr(&p.lflag[lev], LF_NEW);
       bor = 0u;
     }
     for (int i = threadIdx.x; i < cnt; i += TPB) {
-      const int64_t t = tb + items[i];
+      const int it = items[i];
+      const int64_t t = tb + (it & 0xffff);  // G = 16: first child of the group
+      const uint32_t cbits = G == 16 ? (uint32_t)(it >> 16) : 1u << (int)(t & ((1 << D) - 1));
       const int64_t inst = t >> (D * lev);
       int x[3];
       mdec<D>((uint64_t)(t & (nl - 1)), x);
       const int px[3] = {x[0] >> 1, x[1] >> 1, x[2] >> 1};
       const int64_t ibp = g.off[lev - 1] + inst * g.n[lev - 1];
-      const int cb = (x[0] & 1) | ((x[1] & 1) << 1) | ((x[2] & 1) << 2);
+      const int64_t c0 = g.off[lev] + (t & ~(int64_t)((1 << D) - 1));  // child 0 of the group
       for (int k = 0; k < g.m; k++) {
         double S[27], T[8];
         if (!gather27<D>(g, p, p.q[SL_Q0], lev - 1, ibp, px, k, S)) flag_bad(p, inst, 32);
         pred_terms<D>(S, T);
-        p.q[SL_Q0][(int64_t)k * g.Ntot + g.off[lev] + t] = pred_child<D>(T, cb);
+#pragma unroll
+        for (int cb = 0; cb < (1 << D); cb++)
+          if ((cbits >> cb) & 1u) p.q[SL_Q0][(int64_t)k * g.Ntot + c0 + cb] = pred_child<D>(T, cb);
       }
     }
     __syncthreads();
@@ -1617,30 +1667,48 @@ __device__ __forceinline__ uint64_t lane_counts(const Geo& g, const Dev& p, cons
   return c;
 }
 
-// full: statuses changed outside the remesh, the summaries are not trusted
+// a level with no cell after this remesh's apply pass lists nothing (not in
+// full mode, where the flags are not trusted)
+__device__ __forceinline__ bool level_empty(const Dev& p, int lev, int full) {
+  return !full && !(p.lflag[lev] & LF_NEW);
+}
+
+// full: statuses changed outside the remesh, the summaries are not trusted.
+// Compaction blocks are taken grid-stride, so an empty level costs a loop
+// step per block, not a workgroup.
 template <int D>
 __global__ __launch_bounds__(TPB) void k_comp_count(Geo g, Dev p, int lo, int full) {
   __shared__ uint64_t sh[TPB];
   const int64_t nbt = g.comp_first[g.L + 1];
-  const int64_t b = g.comp_first[lo] + blockIdx.x;
-  const CompRange r = comp_range(g, lo, b);
-  const bool skip = !full && comp_skip<D>(g, p, r);
-  if (skip) {
-    if (threadIdx.x < NCL) p.bcnt[clist(threadIdx.x) * nbt + b] = 0;
-    return;
-  }
-  uint64_t codes, tot;
-  block_exscan<uint64_t>(lane_counts<D>(g, p, r, false, &codes), sh, &tot);
-  if (threadIdx.x == 0)
+  for (int64_t b = g.comp_first[lo] + blockIdx.x; b < nbt; b += gridDim.x) {
+    const CompRange r = comp_range(g, lo, b);
+    if (level_empty(p, r.lev, full)) continue;
+    if (!full && comp_skip<D>(g, p, r)) {
+      if (threadIdx.x < NCL) p.bcnt[clist(threadIdx.x) * nbt + b] = 0;
+      continue;
+    }
+    uint64_t codes, tot;
+    block_exscan<uint64_t>(lane_counts<D>(g, p, r, false, &codes), sh, &tot);
+    if (threadIdx.x == 0)
 #pragma unroll
-    for (int k = 0; k < NCL; k++) p.bcnt[clist(k) * nbt + b] = (int)((tot >> (16 * k)) & 0xffffull);
+      for (int k = 0; k < NCL; k++) p.bcnt[clist(k) * nbt + b] = (int)((tot >> (16 * k)) & 0xffffull);
+  }
 }
 
 // one workgroup per level: exclusive scans of the block counts of the four
 // lists in place, the list lengths and the leaves per instance
-__global__ __launch_bounds__(TPB) void k_comp_scan(Geo g, Dev p, int lo) {
+__global__ __launch_bounds__(TPB) void k_comp_scan(Geo g, Dev p, int lo, int full) {
   __shared__ int4 sh[TPB];
   const int lev = lo + blockIdx.x;
+  if (level_empty(p, lev, full)) {
+    for (int inst = threadIdx.x; inst < g.B; inst += TPB) p.leafcnt[inst * (MRD_MAXLEV + 1) + lev] = 0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int k = 0; k < NCL; k++) p.lcnt[clist(k) * (MRD_MAXLEV + 1) + lev] = 0;
+      p.lflag[lev] &= ~(LF_EXIST | LF_LEAF | LF_INT);
+    }
+    return;
+  }
   const int64_t nbt = g.comp_first[g.L + 1];
   const int64_t b0 = g.comp_first[lev];
   const int nb = (int)(g.comp_first[lev + 1] - b0);
@@ -1723,6 +1791,10 @@ __global__ __launch_bounds__(TPB) void k_comp_scan(Geo g, Dev p, int lo) {
     p.lcnt[clist(1) * (MRD_MAXLEV + 1) + lev] = tot.y;
     p.lcnt[clist(2) * (MRD_MAXLEV + 1) + lev] = tot.z;
     p.lcnt[clist(3) * (MRD_MAXLEV + 1) + lev] = tot.w;
+    unsigned f = p.lflag[lev] & ~(LF_EXIST | LF_LEAF | LF_INT);
+    if (tot.x) f |= LF_EXIST | LF_LEAF;
+    if (tot.y) f |= LF_EXIST | LF_INT;
+    p.lflag[lev] = f;
   }
   __syncthreads();
   for (int inst = tid; inst < g.B; inst += TPB) {
@@ -1736,39 +1808,42 @@ template <int D>
 __global__ __launch_bounds__(TPB) void k_comp_write(Geo g, Dev p, int lo, int full) {
   __shared__ uint64_t sh[TPB];
   const int64_t nbt = g.comp_first[g.L + 1];
-  const int64_t b = g.comp_first[lo] + blockIdx.x;
-  const CompRange r = comp_range(g, lo, b);
-  if (!full && comp_skip<D>(g, p, r)) return;
-  uint64_t codes, tot;
-  const uint64_t c = lane_counts<D>(g, p, r, false, &codes);
-  const uint64_t ex = block_exscan<uint64_t>(c, sh, &tot);
-  // block summary of a 4096-cell block (levels with >= 4096 cells)
-  if (threadIdx.x == 0 && wide_level(g, r.lev)) {
-    unsigned bits = 0u;
-    if (tot & 0xffffull) bits |= BS_EXIST | BS_LEAF;
-    if ((tot >> 16) & 0xffffull) bits |= BS_EXIST | BS_INT;
-    p.bsum[g.bs_off[r.lev] + (r.tb >> BS_SHIFT)] = (uint8_t)bits;
-  }
-  if (c == 0ull) return;
-  int base[NCL];
+  for (int64_t b = g.comp_first[lo] + blockIdx.x; b < nbt; b += gridDim.x) {
+    const CompRange r = comp_range(g, lo, b);
+    if (level_empty(p, r.lev, full)) continue;
+    if (!full && comp_skip<D>(g, p, r)) continue;
+    uint64_t codes, tot;
+    const uint64_t c = lane_counts<D>(g, p, r, false, &codes);
+    const uint64_t ex = block_exscan<uint64_t>(c, sh, &tot);
+    // block summary of a 4096-cell block (levels with >= 4096 cells)
+    if (threadIdx.x == 0 && wide_level(g, r.lev)) {
+      unsigned bits = 0u;
+      if (tot & 0xffffull) bits |= BS_EXIST | BS_LEAF;
+      if ((tot >> 16) & 0xffffull) bits |= BS_EXIST | BS_INT;
+      p.bsum[g.bs_off[r.lev] + (r.tb >> BS_SHIFT)] = (uint8_t)bits;
+    }
+    if (c == 0ull) continue;  // no barrier follows in this step
+    int base[NCL];
 #pragma unroll
-  for (int k = 0; k < NCL; k++) base[k] = p.bcnt[clist(k) * nbt + b] + (int)((ex >> (16 * k)) & 0xffffull);
-  const int64_t o = g.off[r.lev];
-  for (int j = 0; j < r.cpt; j++) {
-    const uint32_t e = (uint32_t)(codes >> (4 * j)) & 15u;
+    for (int k = 0; k < NCL; k++) base[k] = p.bcnt[clist(k) * nbt + b] + (int)((ex >> (16 * k)) & 0xffffull);
+    const int64_t o = g.off[r.lev];
+    for (int j = 0; j < r.cpt; j++) {
+      const uint32_t e = (uint32_t)(codes >> (4 * j)) & 15u;
 #pragma unroll
-    for (int k = 0; k < NCL; k++)
-      if ((e >> k) & 1u) p.lst[clist(k)][o + base[k]++] = (int)(r.t0 + j);
+      for (int k = 0; k < NCL; k++)
+        if ((e >> k) & 1u) p.lst[clist(k)][o + base[k]++] = (int)(r.t0 + j);
+    }
   }
 }
 
 void launch_compact(const Geo& g, const Dev& p, int lo, bool full, hipStream_t s) {
-  const int64_t nb = g.comp_first[g.L + 1] - g.comp_first[lo];
+  int64_t nb = g.comp_first[g.L + 1] - g.comp_first[lo];
+  if (nb > 8192) nb = 8192;
   const int f = full ? 1 : 0;
   if (g.d == 1) k_comp_count<1><<<(unsigned)nb, TPB, 0, s>>>(g, p, lo, f);
   else if (g.d == 2) k_comp_count<2><<<(unsigned)nb, TPB, 0, s>>>(g, p, lo, f);
   else k_comp_count<3><<<(unsigned)nb, TPB, 0, s>>>(g, p, lo, f);
-  k_comp_scan<<<(unsigned)(g.L - lo + 1), TPB, 0, s>>>(g, p, lo);
+  k_comp_scan<<<(unsigned)(g.L - lo + 1), TPB, 0, s>>>(g, p, lo, f);
   if (g.d == 1) k_comp_write<1><<<(unsigned)nb, TPB, 0, s>>>(g, p, lo, f);
   else if (g.d == 2) k_comp_write<2><<<(unsigned)nb, TPB, 0, s>>>(g, p, lo, f);
   else k_comp_write<3><<<(unsigned)nb, TPB, 0, s>>>(g, p, lo, f);
@@ -1791,6 +1866,10 @@ void launch_recon_level(const Geo& g, const Dev& p, int lev, double* dense, hipS
 void launch_to_rowmajor(const Geo& g, const double* dense, double* out, hipStream_t s) {
   DISPATCH_D(k_to_rowmajor, g.B * g.n[g.L], g, dense, out);
 }
+void launch_level_w(const Geo& g, const Dev& p, int la, hipStream_t s) {
+  k_level_w<<<1, TPB, 0, s>>>(g, p, la);
+}
+
 // remesh table and W flags cleared on levels lo..hi
 void launch_remesh_clear(const Geo& g, const Dev& p, int lo, int hi, hipStream_t s) {
   if (lo > hi) return;

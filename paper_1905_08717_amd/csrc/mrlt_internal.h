@@ -83,6 +83,7 @@ struct Dev {
   int* bcnt;                // [LS_COUNT][blocks] compaction block counts / offsets
   int* leafcnt;             // [B][MRD_MAXLEV + 1] leaves per instance and level
   unsigned long long* items;  // [3] leaf-stage updates of the bulk stage launches, per stage
+  unsigned* lflag;          // [MRD_MAXLEV + 1] level flags (kernels.hip, LF_*)
 };
 
 // ---- launchers (kernels.hip) -------------------------------------------
@@ -100,6 +101,8 @@ void launch_stage(const Geo& g, const Dev& p, int lo, int hi, int stage, int par
 void launch_finalize(const Geo& g, const Dev& p, int lo, int hi, hipStream_t s);
 // remesh byte table cleared on levels lo..hi
 void launch_remesh_clear(const Geo& g, const Dev& p, int lo, int hi, hipStream_t s);
+// level flags before the apply passes of a remesh at la
+void launch_level_w(const Geo& g, const Dev& p, int la, hipStream_t s);
 // details of the internal nodes of levels lo..hi and the seed of W
 void launch_detail_seed(const Geo& g, const Dev& p, int lo, int hi, hipStream_t s);
 // lists of levels lo..L; full: rebuild without trusting the block summaries

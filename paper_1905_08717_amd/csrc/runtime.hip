@@ -126,6 +126,7 @@ void remesh(mr_ctx* c, int la) {
   timed(c, MR_KC_REMESH, [&] { launch_detail_seed(g, c->p, la, g.L - 1, s); });
   for (int lev = g.L - 2; lev >= la; lev--) timed(c, MR_KC_REMESH, [&] { launch_close(g, c->p, lev, s); });
   for (int lev = la; lev <= g.L - 1; lev++) timed(c, MR_KC_REMESH, [&] { launch_prune(g, c->p, lev, la, s); });
+  timed(c, MR_KC_REMESH, [&] { launch_level_w(g, c->p, la, s); });
   for (int lev = la; lev <= g.L; lev++) timed(c, MR_KC_REMESH, [&] { launch_apply(g, c->p, lev, la, s); });
   refresh_lists(c, la, false);
 }
@@ -425,6 +426,7 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
   ALLOC(c->p.bcnt, int, LS_COUNT * (g.comp_first[L + 1] + 1));
   ALLOC(c->p.leafcnt, int, (int64_t)n_inst * (MRD_MAXLEV + 1));
   ALLOC(c->p.items, unsigned long long, 3);
+  ALLOC(c->p.lflag, unsigned, MRD_MAXLEV + 1);
 #undef ALLOC
   c->p.dt = c->dt_d;
   c->p.eps = c->eps_d;
