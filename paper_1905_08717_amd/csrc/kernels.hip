@@ -436,6 +436,13 @@ __global__ void k_to_rowmajor(Geo g, const double* dense, double* out) {
 //   PJ_RK3   Alg. projRK3: q** from the children's stage-3 values, then
 //            eq. rk3proj
 
+// Levels with >= 4096 cells per instance and >= 2^20 cells in all are
+// "wide": their dense passes take 16 cells per lane, their 4096-cell blocks
+// are the compaction blocks, and they keep block summaries.
+__host__ __device__ __forceinline__ bool wide_level(const Geo& g, int lev) {
+  return g.comp_chunk[lev] == (1 << BS_SHIFT) && g.B * g.n[lev] >= ((int64_t)1 << 20);
+}
+
 __device__ __forceinline__ int list_len(const Dev& p, int type, int lev) {
   return p.lcnt[type * (MRD_MAXLEV + 1) + lev];
 }
@@ -809,6 +816,12 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
         }
       }
       if (PDE == PDE_NAGUMO || PDE == PDE_LINEAR) R[0] = R[0] + source<PDE>(g, cur[G]);
+      // the NERK values of a leaf (H1, N14, N34; the theta=1/2 value of RK2)
+      // feed only the virtual cells of the next finer level, whose parent
+      // stencils lie within Chebyshev distance 2 of an internal node of the
+      // leaf's level; with one global step they are not used at all
+      bool nerk = !finest && g.lt;
+      if (!IFACE && nerk && wide_level(g, lev)) nerk = p.nsum[g.bs_off[lev] + (t >> BS_SHIFT)] != 0;
 #pragma unroll
       for (int k = 0; k < M; k++) {
         const int64_t I = (int64_t)k * NT + G;
@@ -818,7 +831,7 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
           // compact RK2; the NERK theta=1/2 value in parts 3/8 and 1/8 (Sec. 3)
           if (stage == 1) {
             p.q[SL_Q1][I] = q0 + (h * r);
-            if (!finest) {
+            if (nerk) {
               p.q[SL_H1][I] = q0 + ((0.5 * h) * r);
               p.q[SL_QH][I] = q0 + ((0.375 * h) * r);
             }
@@ -827,14 +840,14 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
             const double qe = ((0.5 * q0) + (0.5 * q1)) + ((0.5 * h) * r);
             p.q[SL_QE][I] = qe;
             p.q[SL_X2][I] = q1 + (h * r);
-            if (!finest) p.q[SL_QH][I] = p.q[SL_QH][I] + ((0.125 * h) * r);
+            if (nerk) p.q[SL_QH][I] = p.q[SL_QH][I] + ((0.125 * h) * r);
             if (!isfinite(qe)) atomicOr(&p.cnt[inst * CNT_PER_INST + CNT_NONFINITE], 1ull);
           }
           continue;
         }
         if (stage == 1) {
           p.q[SL_Q1][I] = q0 + (h * r);
-          if (!finest) {
+          if (nerk) {
             p.q[SL_H1][I] = q0 + ((0.5 * h) * r);
             p.q[SL_N14][I] = q0 + (((7.0 / 32.0) * h) * r);
             p.q[SL_N34][I] = q0 + (((15.0 / 32.0) * h) * r);
@@ -843,7 +856,7 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
           const double q1 = p.q[SL_Q1][I];
           p.q[SL_QH][I] = ((0.75 * q0) + (0.25 * q1)) + ((0.25 * h) * r);
           p.q[SL_X2][I] = q1 + (h * r);
-          if (!finest) {
+          if (nerk) {
             p.q[SL_N14][I] = p.q[SL_N14][I] + (((1.0 / 32.0) * h) * r);
             p.q[SL_N34][I] = p.q[SL_N34][I] + (((9.0 / 32.0) * h) * r);
           }
@@ -1038,12 +1051,6 @@ __device__ __forceinline__ uint64_t ld_parents(const uint8_t* stp, int64_t t0, i
   return r;
 }
 
-// Levels with >= 4096 cells per instance and >= 2^20 cells in all are
-// "wide": their dense passes take 16 cells per lane, their 4096-cell blocks
-// are the compaction blocks, and they keep block summaries.
-__host__ __device__ __forceinline__ bool wide_level(const Geo& g, int lev) {
-  return g.comp_chunk[lev] == (1 << BS_SHIFT) && g.B * g.n[lev] >= ((int64_t)1 << 20);
-}
 // block summary of a wide level; unknown (all bits) elsewhere
 __device__ __forceinline__ unsigned bsum_of(const Geo& g, const Dev& p, int lev, int64_t sb) {
   return wide_level(g, lev) ? p.bsum[g.bs_off[lev] + sb] : 0xffu;
@@ -1836,6 +1843,37 @@ __global__ __launch_bounds__(TPB) void k_comp_write(Geo g, Dev p, int lo, int fu
   }
 }
 
+// per 4096-cell tile of the wide levels lo..L: 1 when an internal node lies
+// in the tile or in one of its 3^d neighbours (periodic wrap at tile level),
+// i.e. when leaves of the tile may feed the virtual cells of the next level
+template <int D>
+__global__ __launch_bounds__(TPB) void k_nerk_tiles(Geo g, Dev p, int lo) {
+  GSL(j, g.bs_off[g.L + 1] - g.bs_off[lo]) {
+    const int64_t jj = g.bs_off[lo] + j;
+    int lev = lo;
+    while (jj >= g.bs_off[lev + 1]) lev++;
+    if (!wide_level(g, lev)) continue;
+    const int64_t sb = jj - g.bs_off[lev];
+    const uint8_t* bs = p.bsum + g.bs_off[lev];
+    const int64_t tpi = g.n[lev] >> BS_SHIFT;  // tiles per instance
+    const int64_t i0 = sb - (sb & (tpi - 1));
+    const int nt = D == 1 ? (int)tpi : (D == 2 ? (1 << (lev - 6)) : (1 << (lev - 4)));
+    int x[3];
+    mdec<D>((uint64_t)(sb & (tpi - 1)), x);
+    bool in = false;
+#pragma unroll
+    for (int o = 0; o < (D == 1 ? 3 : (D == 2 ? 9 : 27)); o++) {
+      const int ox = o % 3 - 1, oy = D > 1 ? (o / 3) % 3 - 1 : 0, oz = D > 2 ? o / 9 - 1 : 0;
+      int y[3] = {map_nb(x[0] + ox, nt, g.periodic[0]), 0, 0};
+      if (D > 1) y[1] = map_nb(x[1] + oy, nt, g.periodic[1]);
+      if (D > 2) y[2] = map_nb(x[2] + oz, nt, g.periodic[2]);
+      if (y[0] < 0 || y[1] < 0 || y[2] < 0) continue;
+      in = in || (bs[i0 + (int64_t)menc<D>(y)] & BS_INT);
+    }
+    p.nsum[jj] = in ? 1 : 0;
+  }
+}
+
 void launch_compact(const Geo& g, const Dev& p, int lo, bool full, hipStream_t s) {
   int64_t nb = g.comp_first[g.L + 1] - g.comp_first[lo];
   if (nb > 8192) nb = 8192;
@@ -1847,6 +1885,10 @@ void launch_compact(const Geo& g, const Dev& p, int lo, bool full, hipStream_t s
   if (g.d == 1) k_comp_write<1><<<(unsigned)nb, TPB, 0, s>>>(g, p, lo, f);
   else if (g.d == 2) k_comp_write<2><<<(unsigned)nb, TPB, 0, s>>>(g, p, lo, f);
   else k_comp_write<3><<<(unsigned)nb, TPB, 0, s>>>(g, p, lo, f);
+  const int ntb = blocks_for(g.bs_off[g.L + 1] - g.bs_off[lo]);
+  if (g.d == 1) k_nerk_tiles<1><<<ntb, TPB, 0, s>>>(g, p, lo);
+  else if (g.d == 2) k_nerk_tiles<2><<<ntb, TPB, 0, s>>>(g, p, lo);
+  else k_nerk_tiles<3><<<ntb, TPB, 0, s>>>(g, p, lo);
 }
 
 #define DISPATCH_D(kern, n, ...)                                                  \

@@ -410,6 +410,7 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
   ALLOC(c->p.rf, uint8_t, g.Ntot);
   ALLOC(c->p.bsum, uint8_t, g.bs_off[L + 1]);
   ALLOC(c->p.wsum, uint8_t, g.bs_off[L + 1]);
+  ALLOC(c->p.nsum, uint8_t, g.bs_off[L + 1]);
   for (int sl = 0; sl < SL_COUNT; sl++) ALLOC(c->p.q[sl], double, (int64_t)g.m * g.Ntot);
   ALLOC(c->p.regc, double, g.rc_off[L]);
   ALLOC(c->p.regf, double, g.rf_off[L]);

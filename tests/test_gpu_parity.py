@@ -221,6 +221,38 @@ def test_batch_instances_equal_solo_runs(mods):
             assert compare_state(orc[i], s, inst=i, what=f"instance {i}")
 
 
+@pytest.mark.parametrize("case", ["nagumo2d", "euler3d"])
+def test_wide_batch_against_oracle(mods, case):
+    # levels with >= 2^20 cells over the batch take the block summaries, the
+    # 16-cell groups and the per-tile NERK flags (leaves far from refinement
+    # skip their NERK values); sampled instances against the oracle
+    mro, mrlt = mods
+    if case == "nagumo2d":
+        B, L = 16, 9
+        cfg = W.nagumo_2d(L=L, eps=1e-4)       # leaves down to level 9
+        q = np.stack([W.nagumo_front(L, W.SEED + 100 + i) for i in range(B)])
+        dts = [W.nagumo_dt(cfg)] * 2
+    else:
+        B, L = 32, 6
+        cfg = W.euler_3d(L=L)                  # level 5: 32 * 8^5 = 2^20 cells
+        q = np.stack([W.euler_sphere(L)] * B)
+        dts = [0.8 * W.euler_dt(cfg, 5.0, 0.0)] * 2   # s_max stays below 5
+    s = mrlt.Solver(cfg, n_inst=B)
+    s.load_finest(q)
+    sample = [0, B // 2 - 1, B - 1]
+    orc = {}
+    for i in sample:
+        o = mro.Oracle(cfg)
+        o.load_finest(q[i])
+        orc[i] = o
+    print(f"[parity] wide batch {case} B={B} L={L}", flush=True)
+    for j, dt in enumerate(dts):
+        s.lt_step(dt)
+        for i in sample:
+            orc[i].lt_step(dt)
+            assert compare_state(orc[i], s, inst=i, what=f"instance {i}, macro step {j}")
+
+
 def test_checkpoint_resume_bit_identical(mods):
     _, mrlt = mods
     cfg = W.burgers_1d(L=9)
