@@ -62,6 +62,7 @@ struct mro_ctx {
   level_t lv[MRO_MAXLEV + 1];
   double dx[MRO_MAXLEV + 1][3], invdx[MRO_MAXLEV + 1][3], vol[MRO_MAXLEV + 1];
   double t, dt;
+  double vel[3];    /* advection velocity of the flame PDEs this macro step */
   int lmin;
   int64_t leaf_updates, near_thr, iters;
   int nonfinite, bad;
@@ -470,6 +471,26 @@ static void face_flux(const mro_ctx* c, int lev, int dir, const double* cells, d
       F[0] = -(nudx * (CV(2, 0) - CV(1, 0)));
       break;
     }
+    case MRO_PDE_FLAME:
+    case MRO_PDE_FLAMEBALL: {
+      /* advective part: upwind value of the reconstructed face states (the
+       * MUSCL construction of van Leer); then the two-point diffusive flux,
+       * coefficient 1 for T and 1/Le for Y                                 */
+      double vel = c->vel[dir];
+      for (int k = 0; k < m; k++) {
+        double fadv;
+        if (c->s.recon == 2) {
+          fadv = vel * (0.5 * (CV(1, k) + CV(2, k)));
+        } else {
+          double qL, qR;
+          recon4(c->s.recon, CV(0, k), CV(1, k), CV(2, k), CV(3, k), &qL, &qR);
+          fadv = vel >= 0.0 ? vel * qL : vel * qR;
+        }
+        double dif = k == 0 ? 1.0 : 1.0 / c->s.lewis;
+        F[k] = fadv - ((dif * ix) * (CV(2, k) - CV(1, k)));
+      }
+      break;
+    }
     case MRO_PDE_EULER: {
       int d = c->d;
       double gm1 = c->s.gamma - 1.0;
@@ -484,14 +505,79 @@ static void face_flux(const mro_ctx* c, int lev, int dir, const double* cells, d
 }
 
 static int has_source(const mro_ctx* c) {
-  return c->s.pde == MRO_PDE_NAGUMO || c->s.pde == MRO_PDE_LINEAR;
+  return c->s.pde == MRO_PDE_NAGUMO || c->s.pde == MRO_PDE_LINEAR || c->s.pde == MRO_PDE_FLAME ||
+         c->s.pde == MRO_PDE_FLAMEBALL;
 }
 
-/* Pointwise source at the cell average (Sec. 2). */
-static double source(const mro_ctx* c, double u) {
-  if (c->s.pde == MRO_PDE_NAGUMO)
-    return ((c->s.k_react * u) * (1.0 - u)) * (u - c->s.a_react);
-  return c->s.k_react * u;
+/* Reaction rate of the one-dimensional flame (Sec. 5): equal heat and mass
+ * diffusion, Y = 1 - T, written as the paper gives it in terms of 1 - T.   */
+static double omega_flame(const mro_ctx* c, double T) {
+  double ze = c->s.ze, u = 1.0 - T;
+  return ((0.5 * (ze * ze)) * u) * exp((ze * u) / ((c->s.tau * u) - 1.0));
+}
+
+/* Reaction rate of the flame ball (Sec. 5, three-dimensional case).       */
+static double omega_ball(const mro_ctx* c, double T, double Y) {
+  double ze = c->s.ze, le = c->s.lewis;
+  return (((ze * ze) / (2.0 * le)) * Y) * exp((ze * (T - 1.0)) / (1.0 + (c->s.tau * (T - 1.0))));
+}
+
+/* Radiative heat loss (Stefan-Boltzmann, Sec. 5).                          */
+static double radiation(const mro_ctx* c, double T) {
+  double a = (T + (1.0 / c->s.tau)) - 1.0, b = (1.0 / c->s.tau) - 1.0;
+  return c->s.kappa * (((a * a) * (a * a)) - ((b * b) * (b * b)));
+}
+
+static double reaction_rate(const mro_ctx* c, const double* q) {
+  return c->s.pde == MRO_PDE_FLAME ? omega_flame(c, q[0]) : omega_ball(c, q[0], q[1]);
+}
+
+/* Pointwise source at the cell average (Sec. 2), added to R per component. */
+static void add_source(const mro_ctx* c, const double* q, double* R) {
+  switch (c->s.pde) {
+    case MRO_PDE_NAGUMO:
+      R[0] = R[0] + (((c->s.k_react * q[0]) * (1.0 - q[0])) * (q[0] - c->s.a_react));
+      break;
+    case MRO_PDE_LINEAR:
+      R[0] = R[0] + (c->s.k_react * q[0]);
+      break;
+    case MRO_PDE_FLAME:
+      R[0] = R[0] + omega_flame(c, q[0]);
+      break;
+    case MRO_PDE_FLAMEBALL: {
+      double w = omega_ball(c, q[0], q[1]);
+      R[0] = R[0] + (w - radiation(c, q[0]));
+      R[1] = R[1] - w;
+      break;
+    }
+  }
+}
+
+/* Flame velocity v_f: the reaction rate integrated over the leaves (cell
+ * average times cell volume), divided by the cross-section normal to axis
+ * 0.  Summed level by level in cell order.                                */
+static double flame_speed(const mro_ctx* c) {
+  double s = 0.0, area = 1.0;
+  for (int a = 1; a < c->d; a++) area = area * (c->s.hi[a] - c->s.lo[a]);
+  for (int lev = c->l0; lev <= c->L; lev++) {
+    const level_t* LV = &c->lv[lev];
+    for (int64_t i = 0; i < LV->ncell; i++) {
+      if (LV->st[i] != LEAF) continue;
+      double q[2];
+      for (int k = 0; k < c->m; k++) q[k] = LV->slot[S_Q0][(int64_t)k * LV->ncell + i];
+      s = s + (reaction_rate(c, q) * c->vol[lev]);
+    }
+  }
+  return s / area;
+}
+
+/* Advection velocity of the flame PDEs for the coming macro step.          */
+static void set_velocity(mro_ctx* c) {
+  for (int a = 0; a < 3; a++) c->vel[a] = c->s.adv_vel[a];
+  if ((c->s.pde == MRO_PDE_FLAME || c->s.pde == MRO_PDE_FLAMEBALL) && c->s.flame_speed != 0) {
+    c->vel[0] = (double)c->s.flame_speed * flame_speed(c);
+    c->vel[1] = c->vel[2] = 0.0;
+  }
 }
 
 /* ----------------------------------------------------------------------- */
@@ -608,8 +694,9 @@ static void stage_level(mro_ctx* c, int lev, int stage) {
     }
     if (has_source(c)) {
       int sl = slot_own(LEAF, stage);
-      double u = SL(c, lev, sl, 0, i);
-      R[0] = R[0] + source(c, u);
+      double q[5];
+      for (int k = 0; k < m; k++) q[k] = SL(c, lev, sl, k, i);
+      add_source(c, q, R);
     }
     for (int k = 0; k < m; k++) {
       double q0 = SL(c, lev, S_Q0, k, i);
@@ -1187,8 +1274,12 @@ int mro_init(int dim, int L, double eps, const mro_scheme* s, mro_ctx** out) {
   *out = NULL;
   if (dim < 1 || dim > 3 || !(eps >= 0.0)) return MRO_EINVAL;
   if (s->l0 < 2 || L < s->l0 || L > MRO_MAXLEV || (int64_t)dim * L > 40) return MRO_EINVAL;
-  if ((s->rk != 2 && s->rk != 3) || (s->lt != 0 && s->lt != 1) || s->pde < 0 || s->pde > MRO_PDE_LINEAR)
+  if ((s->rk != 2 && s->rk != 3) || (s->lt != 0 && s->lt != 1) || s->pde < 0 || s->pde > MRO_PDE_FLAMEBALL)
     return MRO_EINVAL;
+  int flame = s->pde == MRO_PDE_FLAME || s->pde == MRO_PDE_FLAMEBALL;
+  if (flame && !(s->ze > 0.0 && s->tau > 0.0 && s->tau < 1.0 && s->lewis > 0.0 && s->kappa >= 0.0))
+    return MRO_EINVAL;
+  if (s->flame_speed < -1 || s->flame_speed > 1 || (s->flame_speed != 0 && !flame)) return MRO_EINVAL;
   if (L - s->l0 > 20) return MRO_EINVAL;
   for (int a = 0; a < dim; a++) {
     if ((s->bc[a][0] == MRO_BC_PERIODIC) != (s->bc[a][1] == MRO_BC_PERIODIC)) return MRO_EINVAL;
@@ -1206,7 +1297,8 @@ int mro_init(int dim, int L, double eps, const mro_scheme* s, mro_ctx** out) {
   c->l0 = s->l0;
   c->s = *s;
   c->eps = eps;
-  c->m = s->pde == MRO_PDE_EULER ? dim + 2 : 1;
+  c->m = s->pde == MRO_PDE_EULER ? dim + 2 : (s->pde == MRO_PDE_FLAMEBALL ? 2 : 1);
+  for (int a = 0; a < 3; a++) c->vel[a] = s->adv_vel[a];
   c->nsub = 1 << (dim - 1);
   for (int k = 0; k < c->m; k++)
     if (!(c->s.detail_scale[k] > 0.0)) c->s.detail_scale[k] = 1.0;
@@ -1307,6 +1399,7 @@ int mro_lt_step(mro_ctx* c, double dt) {
   if (c->bad || c->nonfinite) return MRO_ESTATE;
   int64_t N = (int64_t)1 << (c->L - c->l0);
   c->dt = dt;
+  set_velocity(c);
   for (int64_t n = 0; n < N; n++) {
     lt_iteration(c, n, N);
     if (c->bad) break;
@@ -1363,8 +1456,16 @@ int mro_reconstruct(mro_ctx* c, double* q_out) {
   return finish(c);
 }
 
+int mro_flame_speed(mro_ctx* c, double* vf) {
+  if (!c || !vf) return MRO_EINVAL;
+  if (c->s.pde != MRO_PDE_FLAME && c->s.pde != MRO_PDE_FLAMEBALL) return MRO_EINVAL;
+  *vf = flame_speed(c);
+  return MRO_OK;
+}
+
 int mro_max_wavespeed(mro_ctx* c, double* out) {
   if (!c || !out) return MRO_EINVAL;
+  set_velocity(c);
   double mx = 0.0;
   int d = c->d, m = c->m;
   for (int lev = c->l0; lev <= c->L; lev++) {
@@ -1383,6 +1484,8 @@ int mro_max_wavespeed(mro_ctx* c, double* out) {
         for (int j = 0; j < d; j++) v = (j == 0) ? (fabs(w[1]) + a) : (v + (fabs(w[1 + j]) + a));
       } else if (c->s.pde == MRO_PDE_ADVECTION) {
         for (int j = 0; j < d; j++) v = v + fabs(c->s.adv_vel[j]);
+      } else if (c->s.pde == MRO_PDE_FLAME || c->s.pde == MRO_PDE_FLAMEBALL) {
+        for (int j = 0; j < d; j++) v = v + fabs(c->vel[j]);
       }
       if (v > mx) mx = v;
     }

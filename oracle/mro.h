@@ -24,7 +24,9 @@ enum { MRO_OK = 0, MRO_EINVAL = -1, MRO_ENOMEM = -2, MRO_ESTATE = -4,
        MRO_ENONFINITE = -5 };
 
 enum { MRO_PDE_ADVECTION = 0, MRO_PDE_BURGERS = 1, MRO_PDE_NAGUMO = 2,
-       MRO_PDE_EULER = 3, MRO_PDE_LINEAR = 4 };
+       MRO_PDE_EULER = 3, MRO_PDE_LINEAR = 4,
+       MRO_PDE_FLAME = 5,      /* Sec. 5 one-dimensional flame: T, Y = 1 - T */
+       MRO_PDE_FLAMEBALL = 6   /* Sec. 5 three-dimensional flame ball: T, Y */ };
 
 enum { MRO_BC_PERIODIC = 0, MRO_BC_NEUMANN = 1, MRO_BC_DIRICHLET = 2 /* homogeneous, scalar PDEs */ };
 
@@ -43,6 +45,13 @@ typedef struct {
   double lo[3], hi[3];
   double nu, k_react, a_react, gamma, adv_vel[3];
   double detail_scale[5];
+  /* reaction-diffusion flames (Sec. 5): Zeldovich number, temperature
+   * ratio tau, Lewis number, radiation coefficient kappa.  flame_speed 0:
+   * the advection velocity is adv_vel; +1 / -1: it is +v_f / -v_f along
+   * axis 0 with v_f the integral of the reaction rate over the domain (per
+   * unit cross-section), taken at the start of every macro step.          */
+  double ze, tau, lewis, kappa;
+  int32_t flame_speed;
 } mro_scheme;
 
 typedef struct {
@@ -65,6 +74,7 @@ int  mro_adapt(mro_ctx* c);
 int  mro_lt_step(mro_ctx* c, double dt_L);
 int  mro_reconstruct(mro_ctx* c, double* q_out);      /* [m][2^{dL}] x fastest */
 int  mro_max_wavespeed(mro_ctx* c, double* out);
+int  mro_flame_speed(mro_ctx* c, double* vf);         /* integral of omega */
 int  mro_get_leaves(mro_ctx* c, uint64_t* keys, double* q, int64_t cap, int64_t* n);
 int  mro_set_leaves(mro_ctx* c, const uint64_t* keys, const double* q, int64_t n, double t);
 int  mro_stats(mro_ctx* c, mro_stats_t* out);

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libmro.so")
 SRC = os.path.join(HERE, "mro.c")
 
-PDE = {"advection": 0, "burgers": 1, "nagumo": 2, "euler": 3, "linear": 4}
+PDE = {"advection": 0, "burgers": 1, "nagumo": 2, "euler": 3, "linear": 4, "flame": 5, "flameball": 6}
 BC = {"periodic": 0, "neumann": 1, "dirichlet": 2}
 
 OK, EINVAL, ENOMEM, ESTATE, ENONFINITE = 0, -1, -2, -4, -5
@@ -35,6 +35,8 @@ class Scheme(ctypes.Structure):
         ("nu", ctypes.c_double), ("k_react", ctypes.c_double), ("a_react", ctypes.c_double),
         ("gamma", ctypes.c_double), ("adv_vel", ctypes.c_double * 3),
         ("detail_scale", ctypes.c_double * 5),
+        ("ze", ctypes.c_double), ("tau", ctypes.c_double), ("lewis", ctypes.c_double),
+        ("kappa", ctypes.c_double), ("flame_speed", ctypes.c_int32),
     ]
 
 
@@ -83,6 +85,7 @@ def lib():
         L.mro_lt_step.argtypes = [vp, dbl]
         L.mro_reconstruct.argtypes = [vp, dp]
         L.mro_max_wavespeed.argtypes = [vp, dp]
+        L.mro_flame_speed.argtypes = [vp, dp]
         L.mro_get_leaves.argtypes = [vp, u64p, dp, i64, ctypes.POINTER(i64)]
         L.mro_set_leaves.argtypes = [vp, u64p, dp, i64, dbl]
         L.mro_stats.argtypes = [vp, ctypes.POINTER(Stats)]
@@ -117,8 +120,9 @@ def make_scheme(cfg: dict) -> Scheme:
     bc = cfg.get("bc", "periodic")
     for a in range(3):
         b = bc[a] if isinstance(bc, (list, tuple)) else bc
-        s.bc[a][0] = BC[b]
-        s.bc[a][1] = BC[b]
+        lo_hi = b if isinstance(b, (list, tuple)) else (b, b)   # per side or both
+        s.bc[a][0] = BC[lo_hi[0]]
+        s.bc[a][1] = BC[lo_hi[1]]
         s.lo[a] = cfg.get("lo", [0.0] * 3)[a] if a < d else 0.0
         s.hi[a] = cfg.get("hi", [1.0] * 3)[a] if a < d else 1.0
     s.nu = cfg.get("nu", 0.0)
@@ -131,6 +135,11 @@ def make_scheme(cfg: dict) -> Scheme:
     sc = cfg.get("detail_scale", [1.0] * 5)
     for k in range(5):
         s.detail_scale[k] = sc[k]
+    s.ze = cfg.get("ze", 0.0)
+    s.tau = cfg.get("tau", 0.0)
+    s.lewis = cfg.get("lewis", 1.0)
+    s.kappa = cfg.get("kappa", 0.0)
+    s.flame_speed = cfg.get("flame_speed", 0)
     return s
 
 
@@ -188,6 +197,13 @@ class Oracle:
     def max_wavespeed(self) -> float:
         v = ctypes.c_double()
         self._check(lib().mro_max_wavespeed(self._h, ctypes.byref(v)), "mro_max_wavespeed")
+        return v.value
+
+    def flame_speed(self) -> float:
+        """v_f of the current leaves: the reaction rate integrated over the
+        domain per unit cross-section (Sec. 5)."""
+        v = ctypes.c_double()
+        self._check(lib().mro_flame_speed(self._h, ctypes.byref(v)), "mro_flame_speed")
         return v.value
 
     def get_leaves(self):

@@ -82,8 +82,32 @@ def linear_1d_dirichlet(L: int, eps: float = 0.0, l0: int = 2, nu: float = 1.0) 
                 reflux=1, remesh=1, t_final=0.01, cfl=0.25)
 
 
+def flame_1d(L: int = 11, eps: float = 1e-2, l0: int = 2, flame_speed: int = -1) -> dict:
+    """1D premixed flame of Sec. 5: T_t + v T_x = T_xx + omega(T) on (-15, 15),
+    Ze = 10, tau = 0.8, dT/dx = 0 at x = -15, T = 0 at x = 15.  v = -v_f
+    (flame_speed -1, the frame that moves with the front) or +v_f (+1, the
+    sign as printed), v_f the integral of omega, per macro step."""
+    return dict(name=f"flame1d_L{L}", dim=1, L=L, l0=l0, eps=eps, pde="flame", ze=10.0, tau=0.8,
+                lewis=1.0, kappa=0.0, flame_speed=flame_speed, bc=[("neumann", "dirichlet"), "neumann", "neumann"],
+                lo=[-15.0, 0.0, 0.0], hi=[15.0, 1.0, 1.0], adv_vel=[0.0, 0.0, 0.0], recon=1,
+                thresh=1, reflux=1, remesh=1, t_final=5.0, cfl=0.5)
+
+
+def flame_ball_3d(L: int = 7, eps: float = 1e-2, l0: int = 2, half_width: float = 15.0) -> dict:
+    """3D flame ball of Sec. 5: T and Y with Lewis number 0.3 and radiation
+    kappa = 0.1, Ze = 10, tau = 0.64, Neumann; the box (-15, 15)^3 (the
+    paper does not state it; the 1D flame's interval on every axis)."""
+    w = half_width
+    return dict(name=f"flameball3d_L{L}", dim=3, L=L, l0=l0, eps=eps, pde="flameball", ze=10.0,
+                tau=0.64, lewis=0.3, kappa=0.1, flame_speed=0, bc="neumann", lo=[-w, -w, -w],
+                hi=[w, w, w], adv_vel=[0.0, 0.0, 0.0], recon=1, thresh=1, reflux=1, remesh=1,
+                t_final=5.0, cfl=0.1)
+
+
 def ncomp(cfg: dict) -> int:
-    return cfg["dim"] + 2 if cfg["pde"] == "euler" else 1
+    if cfg["pde"] == "euler":
+        return cfg["dim"] + 2
+    return 2 if cfg["pde"] == "flameball" else 1
 
 
 # ---------------------------------------------------------------------------
@@ -111,6 +135,25 @@ def nagumo_dt(cfg: dict) -> float:
     dx = 1.0 / (1 << cfg["L"])
     dt_cfl = cfg["cfl"] / (2 * cfg["dim"] / dx ** 2 + 0.8 * cfg["k_react"])
     it = macro_iters(cfg)
+    nmac = math.ceil(cfg["t_final"] / (it * dt_cfl))
+    return cfg["t_final"] / (nmac * it)
+
+
+def flame_dt(cfg: dict, vmax: float = 1.5) -> float:
+    """dt_L for the flame problems: Courant number sigma on the finest level
+    for the fastest diffusion (coefficient max(1, 1/Le)) plus advection at
+    speed vmax; and the coarsest level's local step 2^{L-l0} dt_L within the
+    RK3 stability interval of the burnt-gas relaxation, whose rate is
+    Ze^2 / (2 Le) (it binds only on coarse finest levels, never at the
+    paper's L); rounded to a whole number of macro steps up to t_final."""
+    dx = (cfg["hi"][0] - cfg["lo"][0]) / (1 << cfg["L"])
+    le = cfg.get("lewis", 1.0)
+    dmax = max(1.0, 1.0 / le)
+    vel = vmax if cfg.get("flame_speed", 0) else sum(abs(v) for v in cfg["adv_vel"][:cfg["dim"]])
+    it = macro_iters(cfg)
+    dt_cfl = cfg["cfl"] / (2 * cfg["dim"] * dmax / dx ** 2 + vel / dx)
+    dt_src = 2.0 / (cfg["ze"] ** 2 / (2 * le) * (it if cfg.get("lt", 1) else 1))
+    dt_cfl = min(dt_cfl, dt_src)
     nmac = math.ceil(cfg["t_final"] / (it * dt_cfl))
     return cfg["t_final"] / (nmac * it)
 
@@ -266,6 +309,50 @@ def euler_shock_tube(L: int, left=(1.0, 0.0, 1.0), right=(0.125, 0.0, 0.1), x0: 
     return q
 
 
+def flame_front(L: int, lo: float = -15.0, hi: float = 15.0, x0: float = 1.0) -> np.ndarray:
+    """Sec. 5 one-dimensional flame: T = 1 for x <= x0, exp(x0 - x) beyond;
+    exact cell averages."""
+    n = 1 << L
+    dx = (hi - lo) / n
+    a = lo + dx * np.arange(n)
+    b = a + dx
+    burnt = np.clip(np.minimum(b, x0) - a, 0.0, None)            # part with x <= x0
+    s = np.maximum(a, x0)
+    fresh = np.where(b > x0, np.exp(x0 - s) - np.exp(x0 - b), 0.0)
+    return ((burnt + fresh) / dx).reshape(1, n)
+
+
+def flame_ball(L: int, lo: float = -15.0, hi: float = 15.0, lewis: float = 0.3, r0: float = 1.0,
+               axes=(1.5, 1.5, 3.0), theta: float = math.pi / 3, phi: float = math.pi / 4) -> np.ndarray:
+    """Sec. 5 three-dimensional flame ball: ellipsoidal radius r of the
+    rotated coordinates; T = 1, Y = 0 for r <= r0, else T = exp(1 - r/r0),
+    Y = 1 - exp(Le (1 - r/r0)); 4^3 Gauss-Legendre averages."""
+    n = 1 << L
+    xc, dx = _centers(n, lo, hi)
+    g, w = _GL4
+    pts = xc[:, None] + 0.5 * dx * g[None, :]   # (n,4)
+    ww = w * 0.5
+    ct, st, cp, sp = math.cos(theta), math.sin(theta), math.cos(phi), math.sin(phi)
+    T = np.zeros((n, n, n))
+    Y = np.zeros((n, n, n))
+    for a in range(4):
+        x = pts[None, None, :, a]
+        for b in range(4):
+            y = pts[None, :, None, b]
+            for c in range(4):
+                z = pts[:, None, None, c]
+                X1 = x * ct - y * st
+                u = x * st + y * ct
+                Y1 = u * cp - z * sp
+                Z1 = u * sp + z * cp
+                r = np.sqrt((X1 / axes[0]) ** 2 + (Y1 / axes[1]) ** 2 + (Z1 / axes[2]) ** 2)
+                out = r > r0
+                wt = ww[a] * ww[b] * ww[c]
+                T += wt * np.where(out, np.exp(1.0 - r / r0), 1.0)
+                Y += wt * np.where(out, 1.0 - np.exp(lewis * (1.0 - r / r0)), 0.0)
+    return np.stack([T.reshape(-1), Y.reshape(-1)])
+
+
 def initial_data(cfg: dict, seed: int = SEED) -> np.ndarray:
     name = cfg["pde"]
     if cfg.get("name", "").startswith("burgers2d"):
@@ -276,6 +363,10 @@ def initial_data(cfg: dict, seed: int = SEED) -> np.ndarray:
         return burgers_sine(cfg["L"])
     if name == "nagumo":
         return nagumo_front(cfg["L"], seed)
+    if name == "flame":
+        return flame_front(cfg["L"], cfg["lo"][0], cfg["hi"][0])
+    if name == "flameball":
+        return flame_ball(cfg["L"], cfg["lo"][0], cfg["hi"][0], cfg.get("lewis", 0.3))
     if name == "euler" and cfg["dim"] == 3:
         return euler_sphere(cfg["L"], cfg.get("gamma", 1.4))
     if name == "euler" and cfg["dim"] == 2:

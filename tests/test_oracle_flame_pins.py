@@ -1,0 +1,182 @@
+"""Pins of the oracle's reaction-diffusion flame problems (Sec. 5).
+
+* The paper writes the reaction rate twice: in terms of 1 - T for the
+  one-dimensional flame and in terms of (T, Y) with the Lewis number for the
+  flame ball.  With Y = 1 - T, Le = 1 and no radiation the two must give the
+  same temperature field.
+* A spatially uniform state feels no flux, so every leaf follows the
+  ODE T' = omega - s(T), Y' = -omega: checked against scipy's integrator.
+* With Y = 0 there is no reaction; without radiation T obeys
+  T_t + v T_x = T_xx and Y obeys Y_t = Y_xx / Le.  On a full tree with
+  first-order upwinding a Fourier mode of the cell averages is an
+  eigenvector of the discrete operator, so the compact RK3 step multiplies
+  it by the amplification polynomial exactly.
+* The flame velocity v_f is the integral of the reaction rate: the planar
+  flame of the one-dimensional case travels at about v_f in the rest frame,
+  stands still in the frame moving at -v_f, and v_f approaches the
+  large-activation-energy flame speed 1 of this normalisation of omega.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1905_08717_amd import workloads as W
+
+
+def _front(q, lo, hi):
+    """Position where T first drops below 1/2 (linear interpolation)."""
+    T = q[0]
+    n = T.size
+    dx = (hi - lo) / n
+    i = int(np.argmax(T < 0.5))
+    x0 = lo + (i - 0.5) * dx
+    return x0 + dx * (T[i - 1] - 0.5) / (T[i - 1] - T[i])
+
+
+def test_two_written_forms_of_the_rate_agree(oracle_mod):
+    """1D flame (T only, omega written with 1 - T) against the flame-ball
+    model (T and Y) with Y = 1 - T, Le = 1, kappa = 0, tau = 0.8, both in
+    the frame moving with the front and Neumann on both sides."""
+    L = 8
+    front = W.flame_1d(L=L, eps=1e-3)
+    front["bc"] = "neumann"
+    ball = dict(front, pde="flameball", lewis=1.0, kappa=0.0)
+    T0 = W.flame_front(L)
+    a = oracle_mod.Oracle(front)
+    b = oracle_mod.Oracle(ball)
+    a.load_finest(T0)
+    b.load_finest(np.concatenate([T0, 1.0 - T0]))
+    assert abs(a.flame_speed() - b.flame_speed()) < 1e-12 * a.flame_speed()
+    dt = W.flame_dt(front)
+    for _ in range(6):
+        a.lt_step(dt)
+        b.lt_step(dt)
+    ta, tb = a.reconstruct()[0], b.reconstruct()
+    assert np.abs(ta - tb[0]).max() < 1e-10
+    assert np.abs(tb[0] + tb[1] - 1.0).max() < 1e-10     # T + Y = 1 is kept
+    assert np.abs(ta).max() > 0.99 and ta.min() < 0.01
+
+
+@pytest.mark.parametrize("T0,Y0", [(0.9, 0.3), (0.6, 0.8), (1.2, 0.0)])
+def test_uniform_state_follows_the_source_ode(oracle_mod, T0, Y0):
+    """Flame ball, Le = 0.3, kappa = 0.1, tau = 0.64 (the paper's values):
+    a uniform state in a Neumann box integrates omega and s exactly as the
+    ODE does (RK3 error only).  (1.2, 0) has no reaction: pure radiation."""
+    from scipy.integrate import solve_ivp
+
+    cfg = W.flame_ball_3d(L=4, eps=1e-3)
+    cfg.update(dim=1, bc="neumann", lo=[0.0] * 3, hi=[1.0] * 3)
+    ze, tau, le, kap = cfg["ze"], cfg["tau"], cfg["lewis"], cfg["kappa"]
+    n = 1 << 4
+    o = oracle_mod.Oracle(cfg)
+    o.load_finest(np.stack([np.full(n, T0), np.full(n, Y0)]))
+    dt, nmac = 2.5e-5, 40
+    for _ in range(nmac):
+        o.lt_step(dt)
+    t_end = o.stats()["t"]
+
+    def rhs(_t, z):
+        T, Y = z
+        w = ze * ze / (2 * le) * Y * math.exp(ze * (T - 1) / (1 + tau * (T - 1)))
+        s = kap * ((T + 1 / tau - 1) ** 4 - (1 / tau - 1) ** 4)
+        return [w - s, -w]
+
+    ref = solve_ivp(rhs, (0.0, t_end), [T0, Y0], method="DOP853", rtol=1e-13, atol=1e-14).y[:, -1]
+    got = o.reconstruct()
+    assert np.ptp(got[0]) == 0.0 and np.ptp(got[1]) == 0.0
+    assert abs(got[0, 0] - ref[0]) < 1e-7 and abs(got[1, 0] - ref[1]) < 1e-7, (got[:, 0], ref)
+    assert abs(got[0, 0] - T0) > 1e-4                  # something happened
+
+
+def _rk3_amp(z):
+    return 1.0 + z + z * z / 2.0 + z ** 3 / 6.0
+
+
+@pytest.mark.parametrize("comp,vel", [(0, 0.0), (1, 0.0), (0, 0.7), (0, -0.4)])
+def test_fourier_mode_closed_form(oracle_mod, comp, vel):
+    """Y = 0 (no reaction), kappa = 0: on a full periodic tree with
+    first-order upwinding, cell averages A Re(exp(i k x_j)) evolve by
+    Re(P(dt lambda)^N A exp(i k x_j)), lambda = -v (1 - e^{-i k dx}) / dx
+    (upwind for v > 0, mirrored for v < 0) - c (2 - 2 cos k dx) / dx^2,
+    c = 1 for T and 1/Le for Y."""
+    L = 6
+    n = 1 << L
+    cfg = W.flame_ball_3d(L=L, eps=0.0)
+    cfg.update(dim=1, bc="periodic", lo=[0.0] * 3, hi=[1.0] * 3, kappa=0.0, recon=0,
+               adv_vel=[vel, 0.0, 0.0])
+    dx = 1.0 / n
+    k = 2 * math.pi * 3
+    xc = (np.arange(n) + 0.5) * dx
+    A = math.sin(k * dx / 2) / (k * dx / 2)           # cell average of cos(k x)
+    q = np.zeros((2, n))
+    q[comp] = 0.5 + 0.25 * A * np.cos(k * xc)
+    if comp == 0:
+        q[1] = 0.0                                     # no fuel: no reaction
+    else:
+        q[0] = 0.0                                     # cold: omega ~ 1e-10 Y
+    o = oracle_mod.Oracle(cfg)
+    o.load_finest(q)
+    c = 1.0 if comp == 0 else 1.0 / cfg["lewis"]
+    ek = np.exp(1j * k * dx)
+    if vel >= 0:
+        lam = -vel * (1 - 1 / ek) / dx
+    else:
+        lam = -vel * (ek - 1) / dx
+    lam = lam - c * (2 - 2 * math.cos(k * dx)) / dx ** 2
+    dt = 0.2 * dx * dx / c
+    nmac = 3
+    for _ in range(nmac):
+        o.lt_step(dt)
+    N = nmac * W.macro_iters(cfg)
+    ex = 0.5 + 0.25 * A * np.real(_rk3_amp(dt * lam) ** N * np.exp(1j * k * xc))
+    got = o.reconstruct()[comp]
+    tol = 1e-12 if comp == 0 else 1e-9                 # cold-gas reaction rate ~ 1.4e-10
+    assert np.abs(got - ex).max() < tol, np.abs(got - ex).max()
+    assert np.abs(got - q[comp]).max() > 1e-3
+
+
+@pytest.fixture(scope="module")
+def flame_runs(oracle_mod):
+    """1D flame, L = 9, to t = 2 in the rest frame (flame_speed 0), in the
+    frame moving with the front (-1) and with the printed sign (+1)."""
+    out = {}
+    for fs in (0, -1, 1):
+        cfg = W.flame_1d(L=9, eps=1e-3, flame_speed=fs)
+        o = oracle_mod.Oracle(cfg)
+        o.load_finest(W.flame_front(9))
+        dt = W.flame_dt(cfg)
+        hist = []
+        while o.stats()["t"] < 2.0 - 1e-9:
+            vf = o.flame_speed()
+            o.lt_step(dt)
+            hist.append((o.stats()["t"], _front(o.reconstruct(), -15.0, 15.0), vf))
+        out[fs] = np.array(hist)
+    return out
+
+
+def test_flame_speed_and_front_motion(flame_runs):
+    rest, moving, printed = flame_runs[0], flame_runs[-1], flame_runs[1]
+    # after the ignition transient (t > 1): v_f near the asymptotic value 1
+    late = moving[moving[:, 0] > 1.0]
+    vf = late[:, 2].mean()
+    assert 0.85 < vf < 1.0, vf
+    # the front holds its place in the moving frame (within a cell width)
+    assert np.ptp(late[:, 1]) < 30.0 / 512, np.ptp(late[:, 1])
+    # in the rest frame it runs at v_f (integral balance of the PDE) ...
+    lr = rest[rest[:, 0] > 1.0]
+    speed = np.polyfit(lr[:, 0], lr[:, 1], 1)[0]
+    assert abs(speed - lr[:, 2].mean()) < 0.03 * speed, (speed, lr[:, 2].mean())
+    # ... and with the printed sign at about twice that
+    lp = printed[printed[:, 0] > 1.0]
+    speed2 = np.polyfit(lp[:, 0], lp[:, 1], 1)[0]
+    assert abs(speed2 - 2 * lp[:, 2].mean()) < 0.05 * speed2, (speed2, lp[:, 2].mean())
+
+
+def test_flame_parameters_validated(oracle_mod):
+    for bad in (dict(tau=1.0), dict(ze=0.0), dict(lewis=-1.0), dict(flame_speed=2)):
+        cfg = dict(W.flame_1d(L=5), **bad)
+        with pytest.raises(oracle_mod.OracleError):
+            oracle_mod.Oracle(cfg)
+    with pytest.raises(oracle_mod.OracleError):
+        oracle_mod.Oracle(dict(W.nagumo_2d(L=4), flame_speed=1))
