@@ -47,12 +47,14 @@ typedef enum {
   MR_ECAPACITY = -6    /* output buffer too small */
 } mr_status;
 
-enum { MR_PDE_ADVECTION = 0, MR_PDE_BURGERS = 1, MR_PDE_NAGUMO = 2, MR_PDE_EULER = 3, MR_PDE_LINEAR = 4 };
-/* Boundary conditions per axis (both sides the same kind): periodic wrap;
- * homogeneous Neumann, stencil cells outside mirror evenly (q_{-1} = q_0,
- * q_{-2} = q_1); homogeneous Dirichlet (Q = 0 on the boundary, the paper's
- * 2D Burgers problem of Sec. 5), mirror cells enter with the opposite sign
- * (q_{-1} = -q_0, q_{-2} = -q_1); scalar PDEs only.                       */
+enum { MR_PDE_ADVECTION = 0, MR_PDE_BURGERS = 1, MR_PDE_NAGUMO = 2, MR_PDE_EULER = 3, MR_PDE_LINEAR = 4,
+       MR_PDE_FLAME = 5, MR_PDE_FLAMEBALL = 6 };
+/* Boundary conditions per side of an axis: periodic wrap (both sides or
+ * neither); homogeneous Neumann, stencil cells outside mirror evenly
+ * (q_{-1} = q_0, q_{-2} = q_1); homogeneous Dirichlet (Q = 0 on the
+ * boundary: the paper's 2D Burgers problem and the 1D flame's T(15) = 0,
+ * Sec. 5), mirror cells enter with the opposite sign (q_{-1} = -q_0,
+ * q_{-2} = -q_1); every field, not for the Euler system.                  */
 enum { MR_BC_PERIODIC = 0, MR_BC_NEUMANN = 1, MR_BC_DIRICHLET = 2 };
 
 #define MR_MAXLEV 24
@@ -61,7 +63,13 @@ enum { MR_BC_PERIODIC = 0, MR_BC_NEUMANN = 1, MR_BC_DIRICHLET = 2 };
  *  pde     advection (m=1, flux a.q), Burgers (m=1, u^2/2 - nu u_x, exact
  *          Godunov advective flux), Nagumo (m=1, -nu grad u, source
  *          k u (1-u)(u-a)), Euler (m=d+2: rho, rho u_i, E; AUSM+), linear
- *          (m=1, -nu grad u, source k u)
+ *          (m=1, -nu grad u, source k u); the flames of Sec. 5: flame (m=1:
+ *          T; T_t + v.grad T = Lap T + omega(T), omega = Ze^2/2 (1-T)
+ *          exp(Ze (1-T) / (tau (1-T) - 1))), flameball (m=2: T, Y;
+ *          T_t + v.grad T = Lap T + omega - s(T), Y_t + v.grad Y = Lap Y / Le
+ *          - omega, omega = Ze^2/(2 Le) Y exp(Ze (T-1) / (1 + tau (T-1))),
+ *          s = kappa ((T + 1/tau - 1)^4 - (1/tau - 1)^4)); advective flux:
+ *          upwind value of the reconstructed face states
  *  rk      3 (MRLT/NERK3: compact RK3 with NERK partials at theta 1/4, 3/4)
  *          or 2 (MRLT/NERK2: compact RK2 with the NERK theta = 1/2 value), Sec. 3
  *  lt      1: local time stepping (MRLT, Sec. 4); 0: one global step dt_L
@@ -72,15 +80,23 @@ enum { MR_BC_PERIODIC = 0, MR_BC_NEUMANN = 1, MR_BC_DIRICHLET = 2 };
  *  reflux  1: conservative correction of coarse leaves at level interfaces
  *  remesh  1: remesh the evolved levels every iteration, 0: frozen tree
  *  bc      per dimension, low/high side: MR_BC_PERIODIC, MR_BC_NEUMANN or
- *          MR_BC_DIRICHLET (see above); both sides of an axis the same
+ *          MR_BC_DIRICHLET (see above)
  *  lo, hi  box, per dimension
- *  detail_scale  per component divisor in the detail norm (0 -> 1.0)     */
+ *  detail_scale  per component divisor in the detail norm (0 -> 1.0)
+ *  ze, tau, lewis, kappa  flames: Zeldovich number, temperature ratio
+ *          (0 < tau < 1), Lewis number, radiation coefficient (>= 0)
+ *  flame_speed  flames: 0 the velocity is adv_vel; +1 / -1 it is +v_f / -v_f
+ *          along axis 0, v_f the integral of omega over the leaves per unit
+ *          cross-section, taken at the start of every macro step (Sec. 5;
+ *          -1 is the frame that moves with a front burning towards +x)    */
 typedef struct {
   int32_t pde, rk, lt, l0, recon, thresh, reflux, remesh;
   int32_t bc[3][2];
   double lo[3], hi[3];
   double nu, k_react, a_react, gamma, adv_vel[3];
   double detail_scale[5];
+  double ze, tau, lewis, kappa;
+  int32_t flame_speed;
 } mr_scheme;
 
 typedef struct {
@@ -148,10 +164,18 @@ mr_status mr_lt_step_batch(mr_ctx* c, const double* dt_L);
 mr_status mr_reconstruct(mr_ctx* c, double* q_out);
 
 /* CFL helper: per instance the maximum over leaves of sum_i |f_i'(q)|:
- * d |u| (Burgers), sum_i (|u_i| + c) (Euler), sum_i |a_i| (advection), 0
- * otherwise (diffusion and reaction limits are the caller's).
+ * d |u| (Burgers), sum_i (|u_i| + c) (Euler), sum_i |a_i| (advection and
+ * flames, with the frame velocity of the current leaves when flame_speed is
+ * set), 0 otherwise (diffusion and reaction limits are the caller's).
  * out: host array of n_inst values.                                        */
 mr_status mr_max_wavespeed(mr_ctx* c, double* out);
+
+/* Flame velocity of Sec. 5, v_f = integral of the reaction rate omega over
+ * the domain, per unit cross-section normal to axis 0: per instance the sum
+ * over its current leaves of omega(cell average) times the cell volume, in a
+ * fixed order.  Flame problems only (else MR_EINVAL).
+ * vf: host array of n_inst values.                                         */
+mr_status mr_flame_speed(mr_ctx* c, double* vf);
 
 /* Leaves of instance 0 (or `inst`) sorted by (level, Morton key):
  * key = level << 56 | morton, values q[k * n + i] (host buffers).  With

@@ -91,11 +91,11 @@ __device__ __forceinline__ int map_st(int i, int n, int per) {
   if (i >= n) return per ? i - n : 2 * n - 1 - i;
   return i;
 }
-// 1 when stencil coordinate i lies outside on an axis with homogeneous
-// Dirichlet conditions: the mirror cell of map_st enters with its sign
-// flipped (q_{-1} = -q_0, q_{-2} = -q_1)
+// 1 when stencil coordinate i lies outside on a side with homogeneous
+// Dirichlet conditions (mask bit 0: low side, bit 1: high side): the mirror
+// cell of map_st enters with its sign flipped (q_{-1} = -q_0, q_{-2} = -q_1)
 __device__ __forceinline__ bool st_flip(int i, int n, int dirichlet) {
-  return dirichlet && (i < 0 || i >= n);
+  return (i < 0 && (dirichlet & 1)) || (i >= n && (dirichlet & 2));
 }
 // neighbourhood coordinate: wraps when periodic, -1 outside otherwise
 __device__ __forceinline__ int map_nb(int i, int n, int per) {
@@ -270,22 +270,42 @@ __device__ __forceinline__ void ausm_plus(int dir, double gamma, const double* w
 
 template <int D, int PDE>
 struct NC {
-  static constexpr int M = (PDE == PDE_EULER) ? D + 2 : 1;
+  static constexpr int M = (PDE == PDE_EULER) ? D + 2 : (PDE == PDE_FLAMEBALL ? 2 : 1);
 };
 
 // how far along an axis a leaf's stencil reads: 2 with the MUSCL
-// reconstruction, 1 for two-point diffusion, first order or centred fluxes
+// reconstruction, 1 for two-point diffusion (no advection), first order or
+// centred fluxes
 __host__ __device__ __forceinline__ int stencil_reach(const Geo& g) {
-  return (g.pde == PDE_NAGUMO || g.pde == PDE_LINEAR || g.recon != 1) ? 1 : 2;
+  return (g.two_point || g.recon != 1) ? 1 : 2;
 }
 
-// flux across the face between cells a and a+1 along dir; c holds a-1..a+2
+template <int PDE>
+__host__ __device__ __forceinline__ constexpr bool is_flame() {
+  return PDE == PDE_FLAME || PDE == PDE_FLAMEBALL;
+}
+
+// fluxes that read only the two cells next to the face
+template <int PDE>
+__device__ __forceinline__ bool two_point(const Geo& g) {
+  return PDE == PDE_NAGUMO || PDE == PDE_LINEAR || (is_flame<PDE>() && g.two_point);
+}
+
+// advection velocity along dir of instance inst: the flames' frame velocity
+// (+-v_f along axis 0, set at the start of each macro step) or the fixed one
+template <int PDE>
+__device__ __forceinline__ double adv_velocity(const Geo& g, const Dev& p, int64_t inst, int dir) {
+  if (is_flame<PDE>() && g.flame_speed) return dir == 0 ? p.vel[inst] : 0.0;
+  return g.adv[dir];
+}
+
+// flux across the face between cells a and a+1 along dir; c holds a-1..a+2;
+// vel is the advection velocity along dir (advection and flames)
 template <int D, int PDE>
-__device__ __forceinline__ void face_flux(const Geo& g, int lev, int dir,
+__device__ __forceinline__ void face_flux(const Geo& g, int lev, int dir, double vel,
                                           const double (*c)[NC<D, PDE>::M], double* F) {
   const double ix = g.invdx[lev][dir];
   if (PDE == PDE_ADVECTION) {
-    const double vel = g.adv[dir];
     if (g.recon == 2) {
       F[0] = vel * (0.5 * (c[1][0] + c[2][0]));
     } else {
@@ -305,6 +325,23 @@ __device__ __forceinline__ void face_flux(const Geo& g, int lev, int dir,
   } else if (PDE == PDE_NAGUMO || PDE == PDE_LINEAR) {
     const double nudx = g.nu * ix;
     F[0] = -(nudx * (c[2][0] - c[1][0]));
+  } else if (is_flame<PDE>()) {
+    // upwind value of the reconstructed face states, then the two-point
+    // diffusive flux (coefficient 1 for T, 1/Le for Y)
+    constexpr int M = NC<D, PDE>::M;
+#pragma unroll
+    for (int k = 0; k < M; k++) {
+      double fadv;
+      if (g.recon == 2) {
+        fadv = vel * (0.5 * (c[1][k] + c[2][k]));
+      } else {
+        double qL, qR;
+        recon4(g.recon, c[0][k], c[1][k], c[2][k], c[3][k], qL, qR);
+        fadv = vel >= 0.0 ? vel * qL : vel * qR;
+      }
+      const double dif = k == 0 ? 1.0 : 1.0 / g.lewis;
+      F[k] = fadv - ((dif * ix) * (c[2][k] - c[1][k]));
+    }
   } else {
     constexpr int M = D + 2;
     const double gm1 = g.gamma - 1.0;
@@ -318,9 +355,45 @@ __device__ __forceinline__ void face_flux(const Geo& g, int lev, int dir,
 }
 
 template <int PDE>
-__device__ __forceinline__ double source(const Geo& g, double u) {
-  if (PDE == PDE_NAGUMO) return ((g.k_react * u) * (1.0 - u)) * (u - g.a_react);
-  return g.k_react * u;
+__host__ __device__ __forceinline__ constexpr bool has_source() {
+  return PDE == PDE_NAGUMO || PDE == PDE_LINEAR || is_flame<PDE>();
+}
+
+// reaction rate of the flames (Sec. 5): the 1D flame's form in u = 1 - T
+// (Y = 1 - T, unit Lewis number); the flame ball's in (T, Y)
+__device__ __forceinline__ double omega_front(const Geo& g, double T) {
+  const double u = 1.0 - T;
+  return ((0.5 * (g.ze * g.ze)) * u) * exp((g.ze * u) / ((g.tau * u) - 1.0));
+}
+__device__ __forceinline__ double omega_ball(const Geo& g, double T, double Y) {
+  const double tm1 = T - 1.0;
+  return (((g.ze * g.ze) / (2.0 * g.lewis)) * Y) * exp((g.ze * tm1) / (1.0 + (g.tau * tm1)));
+}
+// radiative loss kappa ((T + 1/tau - 1)^4 - (1/tau - 1)^4)
+__device__ __forceinline__ double radiation(const Geo& g, double T) {
+  const double a = (T + (1.0 / g.tau)) - 1.0, b = (1.0 / g.tau) - 1.0;
+  return g.kappa * (((a * a) * (a * a)) - ((b * b) * (b * b)));
+}
+template <int PDE>
+__device__ __forceinline__ double reaction_rate(const Geo& g, const double* q) {
+  if (PDE == PDE_FLAME) return omega_front(g, q[0]);
+  return omega_ball(g, q[0], q[1]);
+}
+
+// pointwise source at the cell average, added to R
+template <int PDE>
+__device__ __forceinline__ void add_source(const Geo& g, const double* q, double* R) {
+  if (PDE == PDE_NAGUMO) {
+    R[0] = R[0] + (((g.k_react * q[0]) * (1.0 - q[0])) * (q[0] - g.a_react));
+  } else if (PDE == PDE_LINEAR) {
+    R[0] = R[0] + (g.k_react * q[0]);
+  } else if (PDE == PDE_FLAME) {
+    R[0] = R[0] + omega_front(g, q[0]);
+  } else if (PDE == PDE_FLAMEBALL) {
+    const double w = omega_ball(g, q[0], q[1]);
+    R[0] = R[0] + (w - radiation(g, q[0]));
+    R[1] = R[1] - w;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -659,7 +732,7 @@ __device__ __forceinline__ void refined_flux(const Geo& g, const Dev& p, int lev
         c[0][k] = fin[0][k]; c[1][k] = fin[1][k]; c[2][k] = own[0][k]; c[3][k] = own[1][k];
       }
     }
-    face_flux<D, PDE>(g, lev + 1, dir, c, Fb);
+    face_flux<D, PDE>(g, lev + 1, dir, adv_velocity<PDE>(g, p, inst, dir), c, Fb);
 #pragma unroll
     for (int k = 0; k < M; k++) Fs[k] = (b == 0) ? Fb[k] : (Fs[k] + Fb[k]);
   }
@@ -733,7 +806,7 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
           sts[dir][side] = sv;
           refined = refined || sv == ST_INTERNAL;
         }
-      if (!IFACE && !finest && !refined && (PDE != PDE_NAGUMO && PDE != PDE_LINEAR) && g.recon == 1) {
+      if (!IFACE && !finest && !refined && (PDE != PDE_NAGUMO && PDE != PDE_LINEAR) && stencil_reach(g) == 2) {
 #pragma unroll
         for (int dir = 0; dir < D; dir++)
 #pragma unroll
@@ -756,7 +829,7 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
 #pragma unroll
         for (int o = -2; o <= 2; o++) {
           // two-point diffusion needs only the face neighbours
-          if ((PDE == PDE_NAGUMO || PDE == PDE_LINEAR) && (o == -2 || o == 2)) continue;
+          if (two_point<PDE>(g) && (o == -2 || o == 2)) continue;
           int y[3] = {x[0], x[1], x[2]};
           y[dir] = map_st(x[dir] + o, n, g.periodic[dir]);
           const bool fl = st_flip(x[dir] + o, n, g.dirichlet[dir]);
@@ -767,10 +840,11 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
             c5[o + 2][k] = fl ? -v : v;
           }
         }
-        if (PDE == PDE_NAGUMO || PDE == PDE_LINEAR) {
+        if (two_point<PDE>(g)) {
 #pragma unroll
           for (int k = 0; k < M; k++) c5[0][k] = c5[4][k] = 0.0;
         }
+        const double vel = adv_velocity<PDE>(g, p, inst, dir);
         double Fm[M], Fp[M];
 #pragma unroll
         for (int side = 0; side < 2; side++) {
@@ -778,7 +852,7 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
           if (IFACE && sts[dir][side] == ST_INTERNAL)
             refined_flux<D, PDE>(g, p, lev, stage, inst, x, dir, side, nbs[dir][side], F);
           else
-            face_flux<D, PDE>(g, lev, dir, c5 + side, F);
+            face_flux<D, PDE>(g, lev, dir, vel, c5 + side, F);
         }
 #pragma unroll
         for (int k = 0; k < M; k++) {
@@ -815,7 +889,12 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
           }
         }
       }
-      if (PDE == PDE_NAGUMO || PDE == PDE_LINEAR) R[0] = R[0] + source<PDE>(g, cur[G]);
+      if (has_source<PDE>()) {
+        double qs[M];
+#pragma unroll
+        for (int k = 0; k < M; k++) qs[k] = cur[(int64_t)k * NT + G];
+        add_source<PDE>(g, qs, R);
+      }
       // the NERK values of a leaf (H1, N14, N34; the theta=1/2 value of RK2)
       // feed only the virtual cells of the next finer level, whose parent
       // stencils lie within Chebyshev distance 2 of an internal node of the
@@ -892,6 +971,8 @@ static void stage_d(const Geo& g, const Dev& p, int lo, int hi, int stage, int p
     case PDE_BURGERS: stage_dp<D, PDE_BURGERS>(g, p, lo, hi, stage, part, s); break;
     case PDE_NAGUMO: stage_dp<D, PDE_NAGUMO>(g, p, lo, hi, stage, part, s); break;
     case PDE_EULER: stage_dp<D, PDE_EULER>(g, p, lo, hi, stage, part, s); break;
+    case PDE_FLAME: stage_dp<D, PDE_FLAME>(g, p, lo, hi, stage, part, s); break;
+    case PDE_FLAMEBALL: stage_dp<D, PDE_FLAMEBALL>(g, p, lo, hi, stage, part, s); break;
     default: stage_dp<D, PDE_LINEAR>(g, p, lo, hi, stage, part, s); break;
   }
 }
@@ -2115,6 +2196,10 @@ __global__ void k_wavespeed(Geo g, Dev p, int lev, unsigned long long* out) {
       for (int j = 0; j < D; j++) v = (j == 0) ? (fabs(w[1]) + a) : (v + (fabs(w[1 + j]) + a));
     } else if (g.pde == PDE_ADVECTION) {
       for (int j = 0; j < D; j++) v = v + fabs(g.adv[j]);
+    } else if (g.pde == PDE_FLAME || g.pde == PDE_FLAMEBALL) {
+      if (g.flame_speed) v = fabs(p.vel[inst]);
+      else
+        for (int j = 0; j < D; j++) v = v + fabs(g.adv[j]);
     }
     atomicMax(&out[inst], (unsigned long long)__double_as_longlong(v));
   }
@@ -2122,6 +2207,71 @@ __global__ void k_wavespeed(Geo g, Dev p, int lev, unsigned long long* out) {
 
 void launch_wavespeed(const Geo& g, const Dev& p, int lev, unsigned long long* out, hipStream_t s) {
   DISPATCH_D(k_wavespeed, g.B * g.n[lev], g, p, lev, out);
+}
+
+// flame velocity v_f (Sec. 5): the reaction rate at every leaf times the leaf
+// volume, summed per compaction block (blocks never straddle instances) and
+// then per instance over its blocks in level and block order, divided by the
+// cross-section normal to axis 0.  Fixed summation order: reproducible.
+template <int PDE>
+__global__ __launch_bounds__(TPB) void k_flame_part(Geo g, Dev p) {
+  __shared__ double sh[TPB];
+  const int64_t b = blockIdx.x;
+  int lev = g.l0;
+  while (lev < g.L && b >= g.comp_first[lev + 1]) lev++;
+  const int64_t ch = g.comp_chunk[lev];
+  const int64_t G0 = g.off[lev] + (b - g.comp_first[lev]) * ch;
+  double s = 0.0;
+  for (int64_t j = threadIdx.x; j < ch; j += TPB) {
+    const int64_t G = G0 + j;
+    if (p.st[G] != ST_LEAF) continue;
+    double q[2];
+    q[0] = p.q[SL_Q0][G];
+    q[1] = PDE == PDE_FLAMEBALL ? p.q[SL_Q0][g.Ntot + G] : 0.0;
+    s = s + (reaction_rate<PDE>(g, q) * g.vol[lev]);
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = TPB / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) p.vfpart[b] = sh[0];
+}
+
+__global__ __launch_bounds__(TPB) void k_flame_sum(Geo g, Dev p) {
+  __shared__ double sh[TPB];
+  const int64_t inst = blockIdx.x;
+  int64_t tot = 0;
+  for (int lev = g.l0; lev <= g.L; lev++) tot += g.n[lev] / g.comp_chunk[lev];
+  double s = 0.0;
+  for (int64_t j = threadIdx.x; j < tot; j += TPB) {
+    int lev = g.l0;
+    int64_t jj = j;
+    while (jj >= g.n[lev] / g.comp_chunk[lev]) {
+      jj -= g.n[lev] / g.comp_chunk[lev];
+      lev++;
+    }
+    s = s + p.vfpart[g.comp_first[lev] + inst * (g.n[lev] / g.comp_chunk[lev]) + jj];
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = TPB / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double vf = sh[0] / g.flame_area;
+    p.vel[g.B + inst] = vf;
+    p.vel[inst] = (double)g.flame_speed * vf;
+  }
+}
+
+void launch_flame_speed(const Geo& g, const Dev& p, hipStream_t s) {
+  const int64_t nb = g.comp_first[g.L + 1];
+  if (g.pde == PDE_FLAME) k_flame_part<PDE_FLAME><<<nb, TPB, 0, s>>>(g, p);
+  else k_flame_part<PDE_FLAMEBALL><<<nb, TPB, 0, s>>>(g, p);
+  k_flame_sum<<<g.B, TPB, 0, s>>>(g, p);
 }
 
 __global__ __launch_bounds__(TPB) void k_mass_partial(Geo g, Dev p, int64_t base, int64_t n, double vol,

@@ -23,7 +23,8 @@ enum { ST_ABSENT = 0, ST_LEAF = 1, ST_INTERNAL = 2 };
 // theta=1/2 projection and the end value of Sec. 4.3 during Case B.
 enum { SL_Q0 = 0, SL_Q1, SL_H1, SL_N14, SL_N34, SL_QH, SL_QE, SL_X2, SL_Q1REF, SL_COUNT };
 
-enum { PDE_ADVECTION = 0, PDE_BURGERS = 1, PDE_NAGUMO = 2, PDE_EULER = 3, PDE_LINEAR = 4 };
+enum { PDE_ADVECTION = 0, PDE_BURGERS = 1, PDE_NAGUMO = 2, PDE_EULER = 3, PDE_LINEAR = 4,
+       PDE_FLAME = 5, PDE_FLAMEBALL = 6 };
 
 // projection kinds (one kernel, selected by mode)
 enum { PJ_Q0 = 0, PJ_CASEB, PJ_REF2, PJ_RK2, PJ_REF3, PJ_RK3, PJ_ST2, PJ_ST3 };
@@ -39,7 +40,8 @@ struct Geo {
   int rk;  // 3: compact RK3 (NERK3), 2: compact RK2 (NERK2)
   int lt;  // 1: local time stepping, 0: one global step for every level
   int periodic[3];
-  int dirichlet[3];  // homogeneous Dirichlet on both sides of the axis
+  int dirichlet[3];  // homogeneous Dirichlet sides of the axis: bit 0 low, bit 1 high
+  int two_point;     // the fluxes read only the two cells next to a face
   int64_t n[MRD_MAXLEV + 1];     // cells per instance at level l (2^{d l})
   int64_t off[MRD_MAXLEV + 1];   // first global index of level l
   int64_t Ntot;                  // total cells over levels and instances
@@ -49,6 +51,11 @@ struct Geo {
   double vol[MRD_MAXLEV + 1];
   double nu, k_react, a_react, gamma, adv[3];
   double scale[5];
+  // flames: Zeldovich number, temperature ratio, Lewis number, radiation
+  // coefficient; flame_speed 0: velocity adv, +-1: +-v_f along axis 0
+  double ze, tau, lewis, kappa;
+  double flame_area;  // cross-section normal to axis 0 (v_f per unit area)
+  int flame_speed;
   // list compaction: level l is cut into blocks of comp_chunk[l] cells (a
   // power of two <= 4096 that never straddles two instances); its blocks are
   // comp_first[l] .. comp_first[l+1]-1 of a global block numbering
@@ -85,6 +92,8 @@ struct Dev {
   int* leafcnt;             // [B][MRD_MAXLEV + 1] leaves per instance and level
   unsigned long long* items;  // [3] leaf-stage updates of the bulk stage launches, per stage
   unsigned* lflag;          // [MRD_MAXLEV + 1] level flags (kernels.hip, LF_*)
+  double* vel;              // [2B] flames: velocity along axis 0 this macro step, then v_f
+  double* vfpart;           // [compaction blocks] flames: partial integrals of omega
 };
 
 // ---- launchers (kernels.hip) -------------------------------------------
@@ -106,6 +115,8 @@ void launch_remesh_clear(const Geo& g, const Dev& p, int lo, int hi, hipStream_t
 void launch_level_w(const Geo& g, const Dev& p, int la, hipStream_t s);
 // details of the internal nodes of levels lo..hi and the seed of W
 void launch_detail_seed(const Geo& g, const Dev& p, int lo, int hi, hipStream_t s);
+// flames: v_f of every instance from its leaves; vel = flame_speed * v_f
+void launch_flame_speed(const Geo& g, const Dev& p, hipStream_t s);
 // lists of levels lo..L; full: rebuild without trusting the block summaries
 void launch_compact(const Geo& g, const Dev& p, int lo, bool full, hipStream_t s);
 void launch_close(const Geo& g, const Dev& p, int lev, hipStream_t s);

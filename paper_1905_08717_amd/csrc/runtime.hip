@@ -295,14 +295,20 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
   if (!s || !eps || dim < 1 || dim > 3 || n_inst < 1) return MR_EINVAL;
   if (s->l0 < 2 || L < s->l0 || L > MR_MAXLEV || L - s->l0 > 20 || dim * L > 40) return MR_EINVAL;
   if ((s->rk != 2 && s->rk != 3) || (s->lt != 0 && s->lt != 1) || s->pde < MR_PDE_ADVECTION ||
-      s->pde > MR_PDE_LINEAR)
+      s->pde > MR_PDE_FLAMEBALL)
     return MR_EINVAL;
   if (s->recon < 0 || s->recon > 2) return MR_EINVAL;
+  const bool flame = s->pde == MR_PDE_FLAME || s->pde == MR_PDE_FLAMEBALL;
+  if (flame && !(s->ze > 0.0 && s->tau > 0.0 && s->tau < 1.0 && s->lewis > 0.0 && s->kappa >= 0.0))
+    return MR_EINVAL;
+  if (s->flame_speed < -1 || s->flame_speed > 1 || (s->flame_speed != 0 && !flame)) return MR_EINVAL;
   for (int a = 0; a < dim; a++) {
-    // one kind of condition per axis (both sides); Dirichlet for scalar fields
-    if (s->bc[a][0] != s->bc[a][1]) return MR_EINVAL;
-    if (s->bc[a][0] < MR_BC_PERIODIC || s->bc[a][0] > MR_BC_DIRICHLET) return MR_EINVAL;
-    if (s->bc[a][0] == MR_BC_DIRICHLET && s->pde == MR_PDE_EULER) return MR_EINVAL;
+    // periodic on both sides or on neither; Dirichlet not for the Euler system
+    if ((s->bc[a][0] == MR_BC_PERIODIC) != (s->bc[a][1] == MR_BC_PERIODIC)) return MR_EINVAL;
+    for (int side = 0; side < 2; side++) {
+      if (s->bc[a][side] < MR_BC_PERIODIC || s->bc[a][side] > MR_BC_DIRICHLET) return MR_EINVAL;
+      if (s->bc[a][side] == MR_BC_DIRICHLET && s->pde == MR_PDE_EULER) return MR_EINVAL;
+    }
     if (!(s->hi[a] > s->lo[a])) return MR_EINVAL;
   }
   for (int i = 0; i < n_inst; i++)
@@ -321,7 +327,7 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
   g.d = dim;
   g.L = L;
   g.l0 = s->l0;
-  g.m = s->pde == MR_PDE_EULER ? dim + 2 : 1;
+  g.m = s->pde == MR_PDE_EULER ? dim + 2 : (s->pde == MR_PDE_FLAMEBALL ? 2 : 1);
   g.nsub = 1 << (dim - 1);
   g.B = n_inst;
   g.i0 = 0;
@@ -334,7 +340,8 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
   g.lt = s->lt;
   for (int a = 0; a < 3; a++) {
     g.periodic[a] = a < dim && s->bc[a][0] == MR_BC_PERIODIC;
-    g.dirichlet[a] = a < dim && s->bc[a][0] == MR_BC_DIRICHLET;
+    g.dirichlet[a] = a < dim ? (s->bc[a][0] == MR_BC_DIRICHLET ? 1 : 0) | (s->bc[a][1] == MR_BC_DIRICHLET ? 2 : 0)
+                             : 0;
   }
   int64_t off = 0, rc = 0, rf = 0;
   for (int lev = g.l0; lev <= L; lev++) {
@@ -391,6 +398,18 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
   g.gamma = s->gamma;
   for (int a = 0; a < 3; a++) g.adv[a] = s->adv_vel[a];
   for (int k = 0; k < 5; k++) g.scale[k] = s->detail_scale[k] > 0.0 ? s->detail_scale[k] : 1.0;
+  g.ze = s->ze;
+  g.tau = s->tau;
+  g.lewis = s->lewis;
+  g.kappa = s->kappa;
+  g.flame_speed = s->flame_speed;
+  g.flame_area = 1.0;
+  for (int a = 1; a < dim; a++) g.flame_area = g.flame_area * (s->hi[a] - s->lo[a]);
+  {
+    bool still = s->flame_speed == 0;
+    for (int a = 0; a < dim; a++) still = still && s->adv_vel[a] == 0.0;
+    g.two_point = s->pde == MR_PDE_NAGUMO || s->pde == MR_PDE_LINEAR || (flame && still);
+  }
 
   c->eps.assign(eps, eps + n_inst);
   c->t.assign(n_inst, 0.0);
@@ -428,6 +447,8 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
   ALLOC(c->p.leafcnt, int, (int64_t)n_inst * (MRD_MAXLEV + 1));
   ALLOC(c->p.items, unsigned long long, 3);
   ALLOC(c->p.lflag, unsigned, MRD_MAXLEV + 1);
+  ALLOC(c->p.vel, double, 2 * n_inst);
+  if (flame) ALLOC(c->p.vfpart, double, g.comp_first[L + 1]);
 #undef ALLOC
   c->p.dt = c->dt_d;
   c->p.eps = c->eps_d;
@@ -547,6 +568,12 @@ mr_status mr_adapt(mr_ctx* c) {
   return adapt_impl(c);
 }
 
+// start of a macro step: the flames' frame velocity from the synchronised
+// leaves (Sec. 5: v_f is the integral of the reaction rate)
+static void macro_begin(mr_ctx* c) {
+  if (c->g.flame_speed) launch_flame_speed(c->g, c->p, c->stream);
+}
+
 mr_status mr_lt_step_batch(mr_ctx* c, const double* dt) {
   if (!c || !dt) return MR_EINVAL;
   if (c->broken) return set_err(c, MR_ESTATE, "context in error state: reload or set leaves");
@@ -561,6 +588,7 @@ mr_status mr_lt_step_batch(mr_ctx* c, const double* dt) {
   if (c->use_graph && c->timed_class == 0 && c->stream != nullptr) {
     if (!c->graph_exec) {
       HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+      macro_begin(c);
       for (int64_t n = 0; n < N; n++) lt_iteration(c, n, N);
       hipGraph_t gr = nullptr;
       HIPCHK(c, hipStreamEndCapture(c->stream, &gr));
@@ -569,6 +597,7 @@ mr_status mr_lt_step_batch(mr_ctx* c, const double* dt) {
     }
     HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
   } else {
+    macro_begin(c);
     for (int64_t n = 0; n < N; n++) lt_iteration(c, n, N);
   }
   mr_status st = check_launch(c, "lt_step");
@@ -597,9 +626,20 @@ mr_status mr_reconstruct(mr_ctx* c, double* q_out) {
   return MR_OK;
 }
 
+mr_status mr_flame_speed(mr_ctx* c, double* vf) {
+  if (!c || !vf) return MR_EINVAL;
+  const Geo& g = c->g;
+  if (g.pde != PDE_FLAME && g.pde != PDE_FLAMEBALL) return set_err(c, MR_EINVAL, "not a flame problem");
+  launch_flame_speed(g, c->p, c->stream);
+  HIPCHK(c, hipMemcpyAsync(vf, c->p.vel + g.B, sizeof(double) * g.B, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return check_launch(c, "flame_speed");
+}
+
 mr_status mr_max_wavespeed(mr_ctx* c, double* out) {
   if (!c || !out) return MR_EINVAL;
   const Geo& g = c->g;
+  if (g.flame_speed) launch_flame_speed(g, c->p, c->stream);
   HIPCHK(c, hipMemsetAsync(c->ws_d, 0, sizeof(unsigned long long) * g.B, c->stream));
   for (int lev = g.l0; lev <= g.L; lev++) launch_wavespeed(g, c->p, lev, c->ws_d, c->stream);
   std::vector<unsigned long long> bits((size_t)g.B);

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmrlt.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENONFINITE, ECAPACITY = 0, -1, -2, -3, -4, -5, -6
-PDE = {"advection": 0, "burgers": 1, "nagumo": 2, "euler": 3, "linear": 4}
+PDE = {"advection": 0, "burgers": 1, "nagumo": 2, "euler": 3, "linear": 4, "flame": 5, "flameball": 6}
 BC = {"periodic": 0, "neumann": 1, "dirichlet": 2}
 MAXLEV = 24
 
@@ -27,7 +27,7 @@ EXPORTS = [
     "mr_get_leaves_inst", "mr_set_leaves", "mr_set_leaves_inst", "mr_stats", "mr_stats_inst",
     "mr_synchronize", "mr_last_error", "mr_destroy", "mr_level_updates", "mr_timing_start",
     "mr_timing_stop", "mr_load_finest_inst", "mr_clear_instance", "mr_instance_flags", "mr_set_eps",
-    "mr_stage_items",
+    "mr_stage_items", "mr_flame_speed",
 ]
 KC = {"stage_finest": 1, "stage": 2, "project": 3, "ghost": 4, "remesh": 5, "finalize": 6, "stage_bulk": 7}
 
@@ -42,6 +42,8 @@ class MrScheme(ctypes.Structure):
         ("nu", ctypes.c_double), ("k_react", ctypes.c_double), ("a_react", ctypes.c_double),
         ("gamma", ctypes.c_double), ("adv_vel", ctypes.c_double * 3),
         ("detail_scale", ctypes.c_double * 5),
+        ("ze", ctypes.c_double), ("tau", ctypes.c_double), ("lewis", ctypes.c_double),
+        ("kappa", ctypes.c_double), ("flame_speed", ctypes.c_int32),
     ]
 
 
@@ -88,6 +90,7 @@ def load_library():
     L.mr_lt_step_batch.argtypes = [vp, dp]
     L.mr_reconstruct.argtypes = [vp, vp]
     L.mr_max_wavespeed.argtypes = [vp, dp]
+    L.mr_flame_speed.argtypes = [vp, dp]
     L.mr_get_leaves.argtypes = [vp, u64p, dp, i64, ctypes.POINTER(i64)]
     L.mr_get_leaves_inst.argtypes = [vp, i32, u64p, dp, i64, ctypes.POINTER(i64)]
     L.mr_set_leaves.argtypes = [vp, u64p, dp, i64, dbl]
@@ -128,8 +131,9 @@ def make_scheme(cfg: dict) -> MrScheme:
     bc = cfg.get("bc", "periodic")
     for a in range(3):
         b = bc[a] if isinstance(bc, (list, tuple)) else bc
-        s.bc[a][0] = BC[b]
-        s.bc[a][1] = BC[b]
+        lo_hi = b if isinstance(b, (list, tuple)) else (b, b)   # per side or both
+        s.bc[a][0] = BC[lo_hi[0]]
+        s.bc[a][1] = BC[lo_hi[1]]
         s.lo[a] = cfg.get("lo", [0.0] * 3)[a] if a < d else 0.0
         s.hi[a] = cfg.get("hi", [1.0] * 3)[a] if a < d else 1.0
     s.nu = cfg.get("nu", 0.0)
@@ -142,6 +146,11 @@ def make_scheme(cfg: dict) -> MrScheme:
     sc = cfg.get("detail_scale", [1.0] * 5)
     for k in range(5):
         s.detail_scale[k] = sc[k]
+    s.ze = cfg.get("ze", 0.0)
+    s.tau = cfg.get("tau", 0.0)
+    s.lewis = cfg.get("lewis", 1.0)
+    s.kappa = cfg.get("kappa", 0.0)
+    s.flame_speed = cfg.get("flame_speed", 0)
     return s
 
 
@@ -260,6 +269,12 @@ class Solver:
     def max_wavespeed(self):
         arr = (ctypes.c_double * self.n_inst)()
         self._check(load_library().mr_max_wavespeed(self._h, arr), "mr_max_wavespeed")
+        return np.array(arr[:])
+
+    def flame_speed(self):
+        """v_f of every instance from its current leaves (flame problems)."""
+        arr = (ctypes.c_double * self.n_inst)()
+        self._check(load_library().mr_flame_speed(self._h, arr), "mr_flame_speed")
         return np.array(arr[:])
 
     def get_leaves(self, inst: int = 0):

@@ -429,3 +429,79 @@ def test_global_time_step_variant(mods, rk):
     cfg = dict(W.euler_2d(L=6), lt=0, rk=rk)
     run_pair(mods, cfg, W.euler_quadrants_seeded(6, W.SEED + 11),
              [lambda o: 0.8 * W.euler_dt(cfg, o.max_wavespeed(), o.stats()["t"])] * 2)
+
+
+# ---------------------------------------------------------------------------
+# reaction-diffusion flames (Sec. 5)
+
+def _check_flame_speed(o, s, inst=0):
+    vo, vg = o.flame_speed(), s.flame_speed()[inst]
+    assert abs(vg - vo) <= 1e-12 * abs(vo), (vg, vo)
+
+
+@pytest.mark.parametrize("rk,lt,fs", [(3, 1, -1), (3, 1, 0), (3, 1, 1), (2, 1, -1), (3, 0, -1), (2, 0, 0)])
+def test_flame_1d_paper_problem(mods, rk, lt, fs):
+    # the 1D flame at the paper's coarsest finest level L = 11 (Neumann at
+    # x = -15, T = 0 at x = 15, eps = 1e-2), in the frame moving with the
+    # front (-1), at rest (0) and with the printed sign (+1)
+    cfg = dict(W.flame_1d(L=11, flame_speed=fs), rk=rk, lt=lt)
+    o, s = run_pair(mods, cfg, W.flame_front(11), [W.flame_dt(cfg)] * 4)
+    _check_flame_speed(o, s)
+
+
+@pytest.mark.parametrize("L", [5, 6])
+def test_flame_ball_3d(mods, L):
+    # the 3D flame ball (Lewis number 0.3, radiation, eps = 1e-2)
+    cfg = W.flame_ball_3d(L=L)
+    o, s = run_pair(mods, cfg, W.flame_ball(L), [W.flame_dt(cfg)] * 2)
+    _check_flame_speed(o, s)
+
+
+def _wrinkled_front_2d(L, lo=-15.0, hi=15.0, amp=1.5):
+    # T = 1 behind x0(y) = 1 + amp sin(2 pi y / 30), exp(x0 - x) ahead
+    # (point values at the cell centres)
+    n = 1 << L
+    xc = lo + (np.arange(n) + 0.5) * (hi - lo) / n
+    x0 = 1.0 + amp * np.sin(2 * np.pi * (xc - lo) / (hi - lo))
+    T = np.where(xc[None, :] <= x0[:, None], 1.0, np.exp(x0[:, None] - xc[None, :]))
+    return T.reshape(1, -1)
+
+
+@pytest.mark.parametrize("pde", ["flame", "flameball"])
+def test_flame_2d_wrinkled_front(mods, pde):
+    # a wrinkled planar front in 2D, frame moving with it (v_f per unit
+    # length of the front); the flame-ball model with Y = 1 - T and Le = 0.3
+    L = 7
+    cfg = W.flame_1d(L=L, eps=1e-2, flame_speed=-1)
+    cfg.update(name=f"{pde}2d", dim=2, pde=pde, lo=[-15.0, -15.0, 0.0], hi=[15.0, 15.0, 1.0],
+               bc=[("neumann", "dirichlet"), "periodic", "neumann"])
+    q0 = _wrinkled_front_2d(L)
+    if pde == "flameball":
+        cfg.update(lewis=0.3, kappa=0.1, tau=0.64, bc=[("neumann", "neumann"), "periodic", "neumann"])
+        q0 = np.concatenate([q0, 1.0 - q0])
+    o, s = run_pair(mods, cfg, q0, [W.flame_dt(cfg)] * 3)
+    _check_flame_speed(o, s)
+
+
+def test_flame_batch_of_thresholds(mods):
+    # three 1D flames with eps 1e-2, 3e-3, 1e-3 in one batch: different trees
+    # and different v_f per instance, each against its own oracle run
+    mro, mrlt = mods
+    cfg = W.flame_1d(L=11)
+    eps = [1e-2, 3e-3, 1e-3]
+    q0 = W.flame_front(11)
+    s = mrlt.Solver(cfg, n_inst=3, eps=eps)
+    s.load_finest(np.stack([q0] * 3))
+    orc = []
+    for e in eps:
+        o = mro.Oracle(dict(cfg, eps=e))
+        o.load_finest(q0)
+        orc.append(o)
+    dt = W.flame_dt(cfg)
+    print("[parity] flame batch of thresholds", flush=True)
+    for j in range(3):
+        s.lt_step(dt)
+        for i, o in enumerate(orc):
+            o.lt_step(dt)
+            assert compare_state(o, s, inst=i, what=f"instance {i}, macro step {j}")
+            _check_flame_speed(o, s, inst=i)
