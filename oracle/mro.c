@@ -1046,6 +1046,11 @@ static int nb_valid(mro_ctx* c, int lev, int64_t j, void* ud) {
 /* One remesh in which levels below la are frozen: the set of nodes at
  * levels <= la does not change, internal status may change at levels >= la.
  *   1. significant internal nodes P (detail > eps_{l(P)+1}) at [la, L-1];
+ *      the flags of the frozen level la-1 are those of its last remesh
+ *      (Sec. 4, adapting the grid during local time stepping: apart from
+ *      splitting and merging only between scales at the same instant, the
+ *      remesh is the multiresolution one, so a significant node of the
+ *      frozen level still keeps its children refined);
  *   2. safety: existing nodes within distance 1 of P (space) and the
  *      children of P if they are below L (scale);
  *   3. closure: the least set W containing those seeds with the tree rule
@@ -1060,7 +1065,7 @@ static void remesh(mro_ctx* c, int la) {
   if (la > L - 1) return;
   for (int lev = c->l0; lev <= L; lev++) {
     memset(c->lv[lev].W, 0, (size_t)c->lv[lev].ncell);
-    memset(c->lv[lev].sig, 0, (size_t)c->lv[lev].ncell);
+    if (lev >= la) memset(c->lv[lev].sig, 0, (size_t)c->lv[lev].ncell);
     memset(c->lv[lev].fresh, 0, (size_t)c->lv[lev].ncell);
   }
   /* 1. significance */
@@ -1081,15 +1086,18 @@ static void remesh(mro_ctx* c, int la) {
     }
     c->near_thr += near;
   }
-  /* 2. seeds: significance, space safety and scale safety */
-  for (int lev = la; lev <= L - 1; lev++) {
+  /* 2. seeds: significance, space safety and scale safety; of the frozen
+   * level la-1 only its scale safety reaches the levels that may change */
+  for (int lev = (la > c->l0 ? la - 1 : la); lev <= L - 1; lev++) {
     level_t* LV = &c->lv[lev];
     for (int64_t i = 0; i < LV->ncell; i++) {
-      if (!LV->sig[i]) continue;
-      LV->W[i] = 1;
+      if (!LV->sig[i] || (lev < la && LV->st[i] != INTERNAL)) continue;
       int x[3];
       ccoord(c, lev, i, x);
-      for_nbrs(c, lev, x, 1, nb_exists_mark, NULL);
+      if (lev >= la) {
+        LV->W[i] = 1;
+        for_nbrs(c, lev, x, 1, nb_exists_mark, NULL);
+      }
       if (lev + 1 <= L - 1) {
         for (int cb = 0; cb < (1 << c->d); cb++) {
           int y[3] = {2 * x[0] + (cb & 1), 2 * x[1] + ((cb >> 1) & 1), 2 * x[2] + ((cb >> 2) & 1)};

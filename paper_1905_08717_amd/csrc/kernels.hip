@@ -1210,8 +1210,13 @@ __global__ __launch_bounds__(TPB) void k_level_w(Geo g, Dev p, int la) {
   }
 }
 
+// Internal nodes of levels lo..hi: lo = la evaluates details from la on;
+// lo = la - 1 also visits the frozen level la - 1, whose nodes keep the
+// significance of their last evaluation (sigt) and pass on only their scale
+// safety (Sec. 4: apart from which scales may split or merge, the LT remesh
+// is the multiresolution remesh).
 template <int D>
-__global__ __launch_bounds__(TPB) void k_detail_seed(Geo g, Dev p, int lo, int hi) {
+__global__ __launch_bounds__(TPB) void k_detail_seed(Geo g, Dev p, int lo, int hi, int la) {
   __shared__ int s_cnt[MRD_MAXLEV + 1];
   const int64_t ntot = flat_setup(p, LS_INTERNAL, lo, hi, s_cnt);
   GSL(i, ntot) {
@@ -1223,6 +1228,18 @@ __global__ __launch_bounds__(TPB) void k_detail_seed(Geo g, Dev p, int lo, int h
       const int64_t t = p.lst[LS_INTERNAL][g.off[lev] + kk];
       if (inst_of_window_skip(g, t, D * lev)) continue;
       const int64_t inst = t >> (D * lev);
+      if (lev < la) {
+        // frozen level: scale safety of a node significant at its last remesh
+        if (!p.sigt[g.off[lev] + t] || lev + 1 > g.L - 1) continue;
+        uint32_t need = 0u;
+#pragma unroll
+        for (int cb = 0; cb < (1 << D); cb++)
+          if (!(p.rf[g.off[lev + 1] + (t << D) + cb] & RF_W)) need |= 1u << cb;
+#pragma unroll
+        for (int cb = 0; cb < (1 << D); cb++)
+          if ((need >> cb) & 1u) mark_w(g, p, lev + 1, (t << D) + cb);
+        continue;
+      }
       const int64_t ib = g.off[lev] + inst * nl;
       int x[3];
       mdec<D>((uint64_t)(t & (nl - 1)), x);
@@ -1245,6 +1262,7 @@ __global__ __launch_bounds__(TPB) void k_detail_seed(Geo g, Dev p, int lo, int h
         sig = Dm > e;
         if (fabs(Dm - e) <= 1e-12 * e) atomicAdd(&p.cnt[inst * CNT_PER_INST + CNT_NEAR], 1ull);
       }
+      p.sigt[g.off[lev] + t] = sig ? 1 : 0;
       if (!sig) continue;
       // targets: the 3^d neighbourhood (existing cells; the node itself is
       // internal) and, below L-1, the 2^d children
@@ -1443,6 +1461,8 @@ __global__ __launch_bounds__(TPB) void k_apply(Geo g, Dev p, int lev, int la) {
               nw = ps == ST_INTERNAL ? ((lev <= g.L - 1 && w) ? ST_INTERNAL : ST_LEAF) : ST_ABSENT;
             }
             if (lev > la && old == ST_ABSENT && nw != ST_ABSENT) mask |= 1u << j;
+            // a node that turns internal has no significance of its own yet
+            if (nw == ST_INTERNAL && old != ST_INTERNAL) p.sigt[g.off[lev] + t] = 0;
           }
           if (j < 8) nlo |= (uint64_t)nw << (8 * j);
           else nhi |= (uint64_t)nw << (8 * (j - 8));
@@ -2000,9 +2020,10 @@ void launch_remesh_clear(const Geo& g, const Dev& p, int lo, int hi, hipStream_t
   if (nb > 2048) nb = 2048;
   k_clear_w<<<(unsigned)nb, TPB, 0, s>>>(g, p, lo, hi);
 }
-void launch_detail_seed(const Geo& g, const Dev& p, int lo, int hi, hipStream_t s) {
-  if (lo > hi) return;
-  DISPATCH_D(k_detail_seed, g.B * g.n[hi], g, p, lo, hi);
+void launch_detail_seed(const Geo& g, const Dev& p, int la, int hi, hipStream_t s) {
+  if (la > hi) return;
+  const int lo = la > g.l0 ? la - 1 : la;
+  DISPATCH_D(k_detail_seed, g.B * g.n[hi], g, p, lo, hi, la);
 }
 // dense passes: 16 cells per lane on levels with >= 2^20 cells (where the
 // block summaries let whole blocks be skipped), one cell per lane below (so

@@ -77,6 +77,7 @@ enum { LS_LEAF = 0, LS_INTERNAL = 1, LS_GHOST = 2, LS_IFACE = 3, LS_COUNT = 4 };
 struct Dev {
   uint8_t* st;     // status per cell
   uint8_t* rf;     // remesh scratch: bit1 member of W (nodes that will be internal)
+  uint8_t* sigt;   // per internal node: significant at the last remesh that evaluated its level
   uint8_t* bsum;   // per 4096-cell block: 1 a cell exists, 2 one is internal, 4 one is a leaf
   uint8_t* wsum;   // per 4096-cell block: 1 when the block may hold W marks
   uint8_t* nsum;   // per 4096-cell block: 1 when an internal node is in it or a neighbour block
@@ -113,8 +114,9 @@ void launch_finalize(const Geo& g, const Dev& p, int lo, int hi, hipStream_t s);
 void launch_remesh_clear(const Geo& g, const Dev& p, int lo, int hi, hipStream_t s);
 // level flags before the apply passes of a remesh at la
 void launch_level_w(const Geo& g, const Dev& p, int la, hipStream_t s);
-// details of the internal nodes of levels lo..hi and the seed of W
-void launch_detail_seed(const Geo& g, const Dev& p, int lo, int hi, hipStream_t s);
+// details of the internal nodes of levels la..hi and the seed of W, with the
+// scale safety of the frozen level la - 1
+void launch_detail_seed(const Geo& g, const Dev& p, int la, int hi, hipStream_t s);
 // flames: v_f of every instance from its leaves; vel = flame_speed * v_f
 void launch_flame_speed(const Geo& g, const Dev& p, hipStream_t s);
 // lists of levels lo..L; full: rebuild without trusting the block summaries

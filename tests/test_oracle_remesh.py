@@ -7,8 +7,12 @@ significant internal nodes (detail > eps_{l+1}), space safety (existing
 neighbours at distance 1), scale safety (children below L), then the least
 set closed under the tree rule and the radius-2 grading rule, then the
 greatest subset in which every rule still holds with frozen existence at the
-lowest changeable level.  This file recomputes that by naive, randomly
-ordered fixed-point iteration and compares the oracle's result.
+lowest changeable level.  The frozen level just below keeps the significance
+flags of its last remesh, and their scale safety still seeds its children
+(Sec. 4: apart from splitting and merging only between scales at the same
+instant, the remesh is the multiresolution one).  This file recomputes that
+by naive, randomly ordered fixed-point iteration and compares the oracle's
+result.
 """
 import itertools
 
@@ -45,7 +49,10 @@ def _nbrs(dim, lev, x, r, periodic):
             yield tuple(y)
 
 
-def brute_remesh(dim, L, l0, la, st, D, eps, thresh, periodic, rng):
+def brute_remesh(dim, L, l0, la, st, D, eps, thresh, periodic, rng, frozen_sig=()):
+    """frozen_sig: the significant nodes of level la-1 at its last remesh
+    (only those still internal count).  Returns the new statuses and the
+    significant nodes of levels la..L-1."""
     eps_l = (lambda lam: eps * 2.0 ** (dim * (lam - L))) if thresh else (lambda lam: eps)
     sig = set()
     for lev in range(la, L):
@@ -57,6 +64,8 @@ def brute_remesh(dim, L, l0, la, st, D, eps, thresh, periodic, rng):
         for y in _nbrs(dim, lev, x, 1, periodic):
             if st[lev][_idx(dim, lev, y)] != ABSENT:
                 Wset.add((lev, y))
+    scale = set(sig) | {(lev, x) for lev, x in frozen_sig if st[lev][_idx(dim, lev, x)] == INTERNAL}
+    for lev, x in scale:
         if lev + 1 <= L - 1:
             for cb in range(1 << dim):
                 Wset.add((lev + 1, tuple(2 * x[a] + ((cb >> a) & 1) for a in range(dim))))
@@ -105,7 +114,7 @@ def brute_remesh(dim, L, l0, la, st, D, eps, thresh, periodic, rng):
                     new[lev][i] = INTERNAL if (lev <= L - 1 and (lev, x) in Wset) else LEAF
                 else:
                     new[lev][i] = ABSENT
-    return new
+    return new, sig
 
 
 def grading_ok(dim, L, l0, st, periodic):
@@ -148,10 +157,14 @@ def test_remesh_matches_brute_force_fixed_point(oracle_mod, dim, L, bc, eps, thr
     q0 = f.transpose(*reversed(range(dim))).reshape(1, -1)
     o.load_finest(q0)
     periodic = bc == "periodic"
-    for la in [l0, l0 + 1, L - 2, L - 1, l0]:
+    last_sig = {}   # level -> significant nodes at that level's last remesh
+    for la in [l0, l0 + 1, L - 2, L - 1, l0, L - 2, l0 + 1]:
         st = {lev: o.level(lev)[0] for lev in range(l0, L + 1)}
         D = {lev: o.details(lev) for lev in range(l0, L)}
-        expect = brute_remesh(dim, L, l0, la, st, D, eps, thresh, periodic, rng)
+        frozen = last_sig.get(la - 1, set())
+        expect, sig = brute_remesh(dim, L, l0, la, st, D, eps, thresh, periodic, rng, frozen)
+        for lev in range(la, L):
+            last_sig[lev] = {(lv, x) for lv, x in sig if lv == lev}
         o.remesh(la)
         got = {lev: o.level(lev)[0] for lev in range(l0, L + 1)}
         for lev in range(l0, L + 1):
@@ -187,3 +200,26 @@ def test_adapt_keeps_all_with_eps_zero(oracle_mod):
     o.load_finest(W.nagumo_front(5))
     st = o.stats()
     assert st["leaves"][5] == 1024 and sum(st["leaves"]) == 1024
+
+
+@pytest.mark.parametrize("case", ["nagumo2d", "flameball3d", "euler2d"])
+def test_remesh_of_synchronised_data_keeps_the_adapted_tree(oracle_mod, case):
+    """Without time evolution, a remesh with levels below la frozen must give
+    the tree that the full remesh gave (Sec. 4: apart from which scales may
+    split or merge, the LT remesh is the multiresolution remesh).  Dropping
+    the frozen level's scale safety would merge every node that only its
+    significant parent kept refined."""
+    if case == "nagumo2d":
+        cfg, q0 = W.nagumo_2d(L=7), W.nagumo_front(7)
+    elif case == "flameball3d":
+        cfg, q0 = W.flame_ball_3d(L=5), W.flame_ball(5)
+    else:
+        cfg, q0 = W.euler_2d(L=6), W.euler_quadrants_seeded(6, W.SEED)
+    o = oracle_mod.Oracle(cfg)
+    o.load_finest(q0)
+    L, l0 = cfg["L"], cfg["l0"]
+    ref = {lev: o.level(lev)[0].copy() for lev in range(l0, L + 1)}
+    for la in list(range(l0 + 1, L)) + [l0]:
+        o.remesh(la)
+        for lev in range(l0, L + 1):
+            assert np.array_equal(o.level(lev)[0], ref[lev]), (la, lev)
