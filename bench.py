@@ -177,6 +177,71 @@ def paper_tables(args):
     print(json.dumps({"mode": "paper", "eps": 0.01, "rows": rows}), flush=True)
 
 
+def flame_tables(args):
+    """The paper's reaction-diffusion problems (Sec. 5) on this GPU: the 1D
+    flame (Ze 10, tau 0.8, Courant number 0.5, t_f 5, finest levels from
+    --flame-levels) in the frame moving with the front, and the 3D flame ball
+    (Le 0.3, kappa 0.1, tau 0.64, Courant number 0.1, t_f 5, L 7 on
+    (-15, 15)^3), eps = 0.01.  Methods: MR/RK2 and MR/RK3 (one global step),
+    MRLT/NERK2 and MRLT/NERK3, and the uniform scheme of the same RK order
+    (eps = 0).  Per method: GPU time as % of the uniform run, mean leaves as
+    % of the finest cells, and the discrete L1 error of T, Y and omega
+    against the uniform run (x 1e-4, the paper's unit)."""
+    import torch
+    from paper_1905_08717_amd import mrlt
+    from paper_1905_08717_amd import workloads as W
+
+    def omega(cfg, q):
+        ze, tau = cfg["ze"], cfg["tau"]
+        if cfg["pde"] == "flame":
+            u = 1.0 - q[0]
+            return 0.5 * ze * ze * u * np.exp(ze * u / (tau * u - 1.0))
+        le = cfg["lewis"]
+        return ze * ze / (2 * le) * q[1] * np.exp(ze * (q[0] - 1.0) / (1.0 + tau * (q[0] - 1.0)))
+
+    def run(cfg, q0, dt):
+        s = mrlt.Solver(cfg)
+        s.load_finest(torch.from_numpy(q0[None]).to("cuda"))
+        it = W.macro_iters(cfg)
+        nmac = int(round(cfg["t_final"] / (it * dt)))
+        mem = 0.0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for j in range(nmac):
+            s.lt_step(dt)
+            mem += sum(s.stats()["leaves"])
+            if (j + 1) % max(1, nmac // 4) == 0:
+                print(f"[flames] {cfg['name']} rk={cfg.get('rk', 3)} lt={cfg.get('lt', 1)} eps={cfg['eps']} "
+                      f"step {j + 1}/{nmac}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        q = s.reconstruct().cpu().numpy()[0]
+        s.close()
+        fields = {"T": q[0], "Y": (1.0 - q[0]) if cfg["pde"] == "flame" else q[1], "omega": omega(cfg, q)}
+        return el, mem / nmac / (1 << (cfg["dim"] * cfg["L"])), nmac, fields
+
+    cases = [("flame1d", W.flame_1d(L=L), W.flame_front(L)) for L in
+             [int(x) for x in args.flame_levels.split(",") if x]]
+    if args.flame_ball_level:
+        Lb = args.flame_ball_level
+        cases.append(("flameball3d", W.flame_ball_3d(L=Lb), W.flame_ball(Lb)))
+    rows = []
+    for name, base, q0 in cases:
+        dt = W.flame_dt(base)
+        for rk in (2, 3):
+            fv_t, _, _, ref = run(dict(base, rk=rk, eps=0.0), q0, dt)
+            for lt in (0, 1):
+                el, mem, nmac, f = run(dict(base, rk=rk, lt=lt), q0, dt)
+                err = {k: round(1e4 * float(np.abs(f[k] - ref[k]).mean()), 4) for k in f}
+                method = f"MRLT/NERK{rk}" if lt else f"MR/RK{rk}"
+                rows.append({"problem": name, "L": base["L"], "method": method, "gpu_s": round(el, 3),
+                             "fv_gpu_s": round(fv_t, 3), "time_pct_of_fv": round(100 * el / fv_t, 1),
+                             "mem_pct_of_fv": round(100 * mem, 2), "l1_err_x1e4_vs_fv": err,
+                             "macro_steps": nmac, "dt_L": dt})
+                print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    print(json.dumps({"mode": "flames", "eps": 0.01, "rows": rows}), flush=True)
+
+
 def systems_mode(args):
     """Batched (256 uneven 2D Euler four-quadrant solves) or served (Poisson
     arrivals of Burgers / Nagumo requests) forms; one JSON line."""
@@ -222,9 +287,12 @@ def main():
     ap.add_argument("--batch", type=int, default=512)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", choices=["throughput", "batched", "served", "copycal", "traffic", "paper"],
+    ap.add_argument("--mode", choices=["throughput", "batched", "served", "copycal", "traffic", "paper",
+                                       "flames"],
                     default="throughput")
     ap.add_argument("--levels", default="8,9,10", help="paper mode: finest levels")
+    ap.add_argument("--flame-levels", default="11,12", help="flames mode: finest levels of the 1D flame")
+    ap.add_argument("--flame-ball-level", type=int, default=7, help="flames mode: 3D flame ball L (0: skip)")
     ap.add_argument("--pmc-dir", default="gpurun_out", help="traffic mode: folder of the four counter runs")
     ap.add_argument("--no-single", action="store_true", help="skip the single-solve reference run")
     ap.add_argument("--requests", type=int, default=0)
@@ -246,6 +314,9 @@ def main():
         return
     if args.mode == "paper":
         paper_tables(args)
+        return
+    if args.mode == "flames":
+        flame_tables(args)
         return
     if args.mode != "throughput":
         systems_mode(args)
