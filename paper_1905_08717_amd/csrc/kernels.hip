@@ -1149,22 +1149,30 @@ __device__ __forceinline__ void mark_w(const Geo& g, const Dev& p, int lev, int6
 // only): one memory round trip per item, and no atomic for a mark that is
 // already there.
 
-// exclusive scan over the 256 threads of a block; *tot receives the total
+// exclusive scan over the 256 threads of a block: a shuffle scan inside
+// each 64-lane wave, the wave totals through shared memory (sh: TPB / 64
+// entries); *tot receives the block total.  Two barriers.
 template <class T>
 __device__ __forceinline__ T block_exscan(T v, T* sh, T* tot) {
-  const int tid = threadIdx.x;
-  sh[tid] = v;
-  __syncthreads();
-  for (int o = 1; o < TPB; o <<= 1) {
-    const T a = tid >= o ? sh[tid - o] : (T)0;
-    __syncthreads();
-    sh[tid] += a;
-    __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  T x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const T u = __shfl_up(x, (unsigned)o, 64);
+    if (lane >= o) x += u;
   }
-  const T incl = sh[tid];
-  *tot = sh[TPB - 1];
+  if (lane == 63) sh[wv] = x;
   __syncthreads();
-  return incl - v;
+  T pre = (T)0, all = (T)0;
+#pragma unroll
+  for (int w = 0; w < TPB / 64; w++) {
+    const T s = sh[w];
+    if (w < wv) pre += s;
+    all += s;
+  }
+  *tot = all;
+  __syncthreads();  // sh is free again on return
+  return pre + x - v;
 }
 
 // block-wide gather of work cells: lane i offers the cells of its group
@@ -1786,7 +1794,7 @@ __device__ __forceinline__ bool level_empty(const Dev& p, int lev, int full) {
 // step per block, not a workgroup.
 template <int D>
 __global__ __launch_bounds__(TPB) void k_comp_count(Geo g, Dev p, int lo, int full) {
-  __shared__ uint64_t sh[TPB];
+  __shared__ uint64_t sh[TPB / 64];
   const int64_t nbt = g.comp_first[g.L + 1];
   for (int64_t b = g.comp_first[lo] + blockIdx.x; b < nbt; b += gridDim.x) {
     const CompRange r = comp_range(g, lo, b);
@@ -1797,16 +1805,24 @@ __global__ __launch_bounds__(TPB) void k_comp_count(Geo g, Dev p, int lo, int fu
     }
     uint64_t codes, tot;
     block_exscan<uint64_t>(lane_counts<D>(g, p, r, false, &codes), sh, &tot);
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
+      const int64_t nsbt = g.sb_first[g.L + 1];
+      const int64_t sbi = g.sb_first[r.lev] + ((b - g.comp_first[r.lev]) >> g.sb_shift[r.lev]);
 #pragma unroll
-      for (int k = 0; k < NCL; k++) p.bcnt[clist(k) * nbt + b] = (int)((tot >> (16 * k)) & 0xffffull);
+      for (int k = 0; k < NCL; k++) {
+        const int cnt = (int)((tot >> (16 * k)) & 0xffffull);
+        p.bcnt[clist(k) * nbt + b] = cnt;
+        if (cnt) atomicAdd(&p.sbcnt[clist(k) * nsbt + sbi], cnt);
+      }
+    }
   }
 }
 
-// one workgroup per level: exclusive scans of the block counts of the four
-// lists in place, the list lengths and the leaves per instance
+// one workgroup per level: exclusive scans of the superblock sums of the
+// four lists (which it clears for the next compaction), the list lengths,
+// the level flags and the leaves per instance
 __global__ __launch_bounds__(TPB) void k_comp_scan(Geo g, Dev p, int lo, int full) {
-  __shared__ int4 sh[TPB];
+  __shared__ int4 sh[TPB / 64];
   const int lev = lo + blockIdx.x;
   if (level_empty(p, lev, full)) {
     for (int inst = threadIdx.x; inst < g.B; inst += TPB) p.leafcnt[inst * (MRD_MAXLEV + 1) + lev] = 0;
@@ -1817,82 +1833,50 @@ __global__ __launch_bounds__(TPB) void k_comp_scan(Geo g, Dev p, int lo, int ful
     }
     return;
   }
-  const int64_t nbt = g.comp_first[g.L + 1];
-  const int64_t b0 = g.comp_first[lev];
-  const int nb = (int)(g.comp_first[lev + 1] - b0);
-  const int bpi = (int)(g.n[lev] / g.comp_chunk[lev]);  // blocks per instance
-  int* bc[NCL];
+  const int64_t nsbt = g.sb_first[g.L + 1];
+  const int64_t s0 = g.sb_first[lev];
+  const int ns = (int)(g.sb_first[lev + 1] - s0);
+  const int spi = (int)((g.n[lev] / g.comp_chunk[lev]) >> g.sb_shift[lev]);  // superblocks per instance
+  int* sc[NCL];
+  int* so[NCL];
 #pragma unroll
-  for (int k = 0; k < NCL; k++) bc[k] = p.bcnt + clist(k) * nbt + b0;
-  const int per = (nb + TPB - 1) / TPB;
-  const int j0 = threadIdx.x * per;
-  const int j1 = j0 + per < nb ? j0 + per : nb;
-  // the thread's blocks in chunks of 16, all loads of a chunk in flight at once
-  constexpr int PMAX = 16;
-  int4 v[PMAX];
-  int4 loc = make_int4(0, 0, 0, 0);
-  if (per <= PMAX) {
-#pragma unroll
-    for (int q = 0; q < PMAX; q++) {
-      const int j = j0 + q;
-      v[q] = j < j1 ? make_int4(bc[0][j], bc[1][j], bc[2][j], bc[3][j]) : make_int4(0, 0, 0, 0);
-    }
-#pragma unroll
-    for (int q = 0; q < PMAX; q++) {
-      loc.x += v[q].x; loc.y += v[q].y; loc.z += v[q].z; loc.w += v[q].w;
-    }
-  } else {
-    for (int jc = j0; jc < j1; jc += PMAX) {
-      int4 w[PMAX];
-#pragma unroll
-      for (int q = 0; q < PMAX; q++) {
-        const int j = jc + q;
-        w[q] = j < j1 ? make_int4(bc[0][j], bc[1][j], bc[2][j], bc[3][j]) : make_int4(0, 0, 0, 0);
-      }
-#pragma unroll
-      for (int q = 0; q < PMAX; q++) {
-        loc.x += w[q].x; loc.y += w[q].y; loc.z += w[q].z; loc.w += w[q].w;
-      }
-    }
+  for (int k = 0; k < NCL; k++) {
+    sc[k] = p.sbcnt + clist(k) * nsbt + s0;
+    so[k] = p.sboff + clist(k) * nsbt + s0;
   }
-  // Hillis-Steele scan of the per-thread sums
   const int tid = threadIdx.x;
-  sh[tid] = loc;
-  __syncthreads();
-  for (int o = 1; o < TPB; o <<= 1) {
-    const int4 v = tid >= o ? sh[tid - o] : make_int4(0, 0, 0, 0);
-    __syncthreads();
-    sh[tid].x += v.x; sh[tid].y += v.y; sh[tid].z += v.z; sh[tid].w += v.w;
-    __syncthreads();
+  const int per = (ns + TPB - 1) / TPB;
+  const int j0 = tid * per;
+  const int j1 = j0 + per < ns ? j0 + per : ns;
+  // pass 1: the thread's sums; pass 2: its offsets (and the sums cleared)
+  int4 loc = make_int4(0, 0, 0, 0);
+  for (int j = j0; j < j1; j++) {
+    loc.x += sc[0][j]; loc.y += sc[1][j]; loc.z += sc[2][j]; loc.w += sc[3][j];
   }
-  const int4 incl = sh[tid], tot = sh[TPB - 1];
-  int4 run = make_int4(incl.x - loc.x, incl.y - loc.y, incl.z - loc.z, incl.w - loc.w);
-  if (per <= PMAX) {
+  int4 tot;
+  const int lane = tid & 63, wv = tid >> 6;
+  int4 x = loc;
 #pragma unroll
-    for (int q = 0; q < PMAX; q++) {
-      const int j = j0 + q;
-      if (j < j1) {
-        bc[0][j] = run.x; bc[1][j] = run.y; bc[2][j] = run.z; bc[3][j] = run.w;
-      }
-      run.x += v[q].x; run.y += v[q].y; run.z += v[q].z; run.w += v[q].w;
-    }
-  } else {
-    for (int jc = j0; jc < j1; jc += PMAX) {
-      int4 w[PMAX];
+  for (int o = 1; o < 64; o <<= 1) {
+    const int ux = __shfl_up(x.x, (unsigned)o, 64), uy = __shfl_up(x.y, (unsigned)o, 64);
+    const int uz = __shfl_up(x.z, (unsigned)o, 64), uw = __shfl_up(x.w, (unsigned)o, 64);
+    if (lane >= o) { x.x += ux; x.y += uy; x.z += uz; x.w += uw; }
+  }
+  if (lane == 63) sh[wv] = x;
+  __syncthreads();
+  int4 run = make_int4(x.x - loc.x, x.y - loc.y, x.z - loc.z, x.w - loc.w);
+  tot = make_int4(0, 0, 0, 0);
 #pragma unroll
-      for (int q = 0; q < PMAX; q++) {
-        const int j = jc + q;
-        w[q] = j < j1 ? make_int4(bc[0][j], bc[1][j], bc[2][j], bc[3][j]) : make_int4(0, 0, 0, 0);
-      }
-#pragma unroll
-      for (int q = 0; q < PMAX; q++) {
-        const int j = jc + q;
-        if (j < j1) {
-          bc[0][j] = run.x; bc[1][j] = run.y; bc[2][j] = run.z; bc[3][j] = run.w;
-        }
-        run.x += w[q].x; run.y += w[q].y; run.z += w[q].z; run.w += w[q].w;
-      }
-    }
+  for (int w = 0; w < TPB / 64; w++) {
+    const int4 s = sh[w];
+    if (w < wv) { run.x += s.x; run.y += s.y; run.z += s.z; run.w += s.w; }
+    tot.x += s.x; tot.y += s.y; tot.z += s.z; tot.w += s.w;
+  }
+  for (int j = j0; j < j1; j++) {
+    const int4 v = make_int4(sc[0][j], sc[1][j], sc[2][j], sc[3][j]);
+    so[0][j] = run.x; so[1][j] = run.y; so[2][j] = run.z; so[3][j] = run.w;
+    sc[0][j] = 0; sc[1][j] = 0; sc[2][j] = 0; sc[3][j] = 0;
+    run.x += v.x; run.y += v.y; run.z += v.z; run.w += v.w;
   }
   if (tid == 0) {
     p.lcnt[clist(0) * (MRD_MAXLEV + 1) + lev] = tot.x;
@@ -1904,17 +1888,18 @@ __global__ __launch_bounds__(TPB) void k_comp_scan(Geo g, Dev p, int lo, int ful
     if (tot.y) f |= LF_EXIST | LF_INT;
     p.lflag[lev] = f;
   }
-  __syncthreads();
+  __syncthreads();  // the offsets of every thread are written
   for (int inst = tid; inst < g.B; inst += TPB) {
-    const int s = bc[0][(int64_t)inst * bpi];
-    const int e = inst + 1 < g.B ? bc[0][(int64_t)(inst + 1) * bpi] : tot.x;
+    const int s = so[0][(int64_t)inst * spi];
+    const int e = inst + 1 < g.B ? so[0][(int64_t)(inst + 1) * spi] : tot.x;
     p.leafcnt[inst * (MRD_MAXLEV + 1) + lev] = e - s;
   }
 }
 
 template <int D>
 __global__ __launch_bounds__(TPB) void k_comp_write(Geo g, Dev p, int lo, int full) {
-  __shared__ uint64_t sh[TPB];
+  __shared__ uint64_t sh[TPB / 64];
+  __shared__ int4 s_pre;
   const int64_t nbt = g.comp_first[g.L + 1];
   for (int64_t b = g.comp_first[lo] + blockIdx.x; b < nbt; b += gridDim.x) {
     const CompRange r = comp_range(g, lo, b);
@@ -1923,6 +1908,36 @@ __global__ __launch_bounds__(TPB) void k_comp_write(Geo g, Dev p, int lo, int fu
     uint64_t codes, tot;
     const uint64_t c = lane_counts<D>(g, p, r, false, &codes);
     const uint64_t ex = block_exscan<uint64_t>(c, sh, &tot);
+    // list offsets of the block: its superblock's plus the counts of the
+    // preceding blocks of the superblock (fewer than 64: wave 0 sums them)
+    int4 pre = make_int4(0, 0, 0, 0);
+    if (tot != 0ull) {
+      const int64_t bl = b - g.comp_first[r.lev];
+      const int sh2 = g.sb_shift[r.lev];
+      const int64_t bs = g.comp_first[r.lev] + ((bl >> sh2) << sh2);
+      const int nprev = (int)(b - bs);
+      if (threadIdx.x < 64) {
+        int4 v = make_int4(0, 0, 0, 0);
+        if ((int)threadIdx.x < nprev) {
+          const int64_t j = bs + threadIdx.x;
+          v = make_int4(p.bcnt[clist(0) * nbt + j], p.bcnt[clist(1) * nbt + j], p.bcnt[clist(2) * nbt + j],
+                        p.bcnt[clist(3) * nbt + j]);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          v.x += __shfl_xor(v.x, o, 64); v.y += __shfl_xor(v.y, o, 64);
+          v.z += __shfl_xor(v.z, o, 64); v.w += __shfl_xor(v.w, o, 64);
+        }
+        if (threadIdx.x == 0) s_pre = v;
+      }
+      __syncthreads();
+      pre = s_pre;
+      const int64_t sbi = g.sb_first[r.lev] + (bl >> sh2);
+      const int64_t nsbt = g.sb_first[g.L + 1];
+      pre.x += p.sboff[clist(0) * nsbt + sbi]; pre.y += p.sboff[clist(1) * nsbt + sbi];
+      pre.z += p.sboff[clist(2) * nsbt + sbi]; pre.w += p.sboff[clist(3) * nsbt + sbi];
+      __syncthreads();  // s_pre is free again
+    }
     // block summary of a 4096-cell block (levels with >= 4096 cells)
     if (threadIdx.x == 0 && wide_level(g, r.lev)) {
       unsigned bits = 0u;
@@ -1931,9 +1946,9 @@ __global__ __launch_bounds__(TPB) void k_comp_write(Geo g, Dev p, int lo, int fu
       p.bsum[g.bs_off[r.lev] + (r.tb >> BS_SHIFT)] = (uint8_t)bits;
     }
     if (c == 0ull) continue;  // no barrier follows in this step
-    int base[NCL];
+    int base[NCL] = {pre.x, pre.y, pre.z, pre.w};
 #pragma unroll
-    for (int k = 0; k < NCL; k++) base[k] = p.bcnt[clist(k) * nbt + b] + (int)((ex >> (16 * k)) & 0xffffull);
+    for (int k = 0; k < NCL; k++) base[k] += (int)((ex >> (16 * k)) & 0xffffull);
     const int64_t o = g.off[r.lev];
     for (int j = 0; j < r.cpt; j++) {
       const uint32_t e = (uint32_t)(codes >> (4 * j)) & 15u;

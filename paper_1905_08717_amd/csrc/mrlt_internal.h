@@ -61,6 +61,10 @@ struct Geo {
   // comp_first[l] .. comp_first[l+1]-1 of a global block numbering
   int64_t comp_first[MRD_MAXLEV + 2];
   int comp_chunk[MRD_MAXLEV + 1];
+  // superblocks of 2^sb_shift[l] compaction blocks (at most 64, never
+  // straddling an instance): level l's are sb_first[l] .. sb_first[l+1]-1
+  int64_t sb_first[MRD_MAXLEV + 2];
+  int sb_shift[MRD_MAXLEV + 1];
   // 4096-cell blocks of level l (one summary byte each) start at bs_off[l]
   int64_t bs_off[MRD_MAXLEV + 2];
   // instances [i0, i1) that the remesh sweeps may change (all of them inside a
@@ -89,7 +93,9 @@ struct Dev {
   unsigned long long* cnt;  // [B][CNT_PER_INST]
   int* lst[LS_COUNT];       // level l's list starts at off[l], capacity B n[l]
   int* lcnt;                // [LS_COUNT][MRD_MAXLEV + 1] list lengths
-  int* bcnt;                // [LS_COUNT][blocks] compaction block counts / offsets
+  int* bcnt;                // [LS_COUNT][blocks] compaction block counts
+  int* sbcnt;               // [LS_COUNT][superblocks] their sums (zero between compactions)
+  int* sboff;               // [LS_COUNT][superblocks] list offset of each superblock
   int* leafcnt;             // [B][MRD_MAXLEV + 1] leaves per instance and level
   unsigned long long* items;  // [3] leaf-stage updates of the bulk stage launches, per stage
   unsigned* lflag;          // [MRD_MAXLEV + 1] level flags (kernels.hip, LF_*)

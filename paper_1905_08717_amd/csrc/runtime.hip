@@ -385,6 +385,16 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
       nb += g.B * g.n[lev] / ch;
     }
     g.comp_first[L + 1] = nb;
+    int64_t ns = 0;
+    for (int lev = g.l0; lev <= L; lev++) {
+      const int64_t bpi = g.n[lev] / g.comp_chunk[lev];  // blocks per instance
+      int sh = 0;
+      while (sh < 6 && ((int64_t)2 << sh) <= bpi) sh++;
+      g.sb_shift[lev] = sh;
+      g.sb_first[lev] = ns;
+      ns += (g.B * bpi) >> sh;
+    }
+    g.sb_first[L + 1] = ns;
     for (int lev = g.l0; lev <= L; lev++)
       if (g.B * g.n[lev] >= ((int64_t)1 << 31)) {
         (void)hipStreamDestroy(c->own_stream);
@@ -445,6 +455,8 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
   for (int k = 0; k < LS_COUNT; k++) ALLOC(c->p.lst[k], int, g.Ntot);
   ALLOC(c->p.lcnt, int, LS_COUNT * (MRD_MAXLEV + 1));
   ALLOC(c->p.bcnt, int, LS_COUNT * (g.comp_first[L + 1] + 1));
+  ALLOC(c->p.sbcnt, int, LS_COUNT * (g.sb_first[L + 1] + 1));
+  ALLOC(c->p.sboff, int, LS_COUNT * (g.sb_first[L + 1] + 1));
   ALLOC(c->p.leafcnt, int, (int64_t)n_inst * (MRD_MAXLEV + 1));
   ALLOC(c->p.items, unsigned long long, 3);
   ALLOC(c->p.lflag, unsigned, MRD_MAXLEV + 1);
