@@ -1646,19 +1646,10 @@ __device__ __forceinline__ uint64_t group_codes(const Geo& g, const Dev& p, int 
   const int64_t nl = g.n[lev];
   const uint8_t* stl = p.st + g.off[lev];
   GroupNbhd h;
+  // the group, its parents and its 2d face-adjacent groups are loaded
+  // together (one memory round trip), whether or not they are needed
   h.c = *reinterpret_cast<const uint4*>(stl + t0);
   const uint64_t par = lev > g.l0 ? ld_parents<D>(p.st + g.off[lev - 1], t0, g.B * nl) : 0ull;
-  bool par_leaf = false;
-#pragma unroll
-  for (int k = 0; k < (16 >> D); k++) par_leaf = par_leaf || ((par >> (8 * k)) & 0xff) == ST_LEAF;
-  const bool any_leaf = any16(h.c, 0x01010101u);
-  uint64_t codes = 0ull;
-  if (!any_leaf && !par_leaf) {
-#pragma unroll
-    for (int j = 0; j < 16; j++)
-      if (byte_of(h.c, j) == ST_INTERNAL) codes |= (uint64_t)CODE_INT << (4 * j);
-    return codes;
-  }
   const int n = 1 << lev;
   const int64_t ib = g.off[lev] + (t0 >> (D * lev)) * nl;
   int x0[3];
@@ -1677,6 +1668,17 @@ __device__ __forceinline__ uint64_t group_codes(const Geo& g, const Dev& p, int 
       const uint4 v = *reinterpret_cast<const uint4*>(p.st + ib + (int64_t)menc<D>(y));
       if (s) { h.p[a] = v; h.vp[a] = true; } else { h.m[a] = v; h.vm[a] = true; }
     }
+  }
+  bool par_leaf = false;
+#pragma unroll
+  for (int k = 0; k < (16 >> D); k++) par_leaf = par_leaf || ((par >> (8 * k)) & 0xff) == ST_LEAF;
+  const bool any_leaf = any16(h.c, 0x01010101u);
+  uint64_t codes = 0ull;
+  if (!any_leaf && !par_leaf) {
+#pragma unroll
+    for (int j = 0; j < 16; j++)
+      if (byte_of(h.c, j) == ST_INTERNAL) codes |= (uint64_t)CODE_INT << (4 * j);
+    return codes;
   }
   // virtual cells need a leaf of the level within two cells, interface
   // leaves an internal face neighbour: both read the loaded neighbourhood
@@ -1805,6 +1807,21 @@ __global__ __launch_bounds__(TPB) void k_comp_count(Geo g, Dev p, int lo, int fu
     }
     uint64_t codes, tot;
     block_exscan<uint64_t>(lane_counts<D>(g, p, r, false, &codes), sh, &tot);
+    // the codes, one byte per cell, for the write pass
+    if (r.act) {
+      uint8_t* cc = p.ccode + g.off[r.lev] + r.t0;
+      if (r.cpt == GRP) {
+        uint32_t w[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          const uint32_t h = (uint32_t)(codes >> (16 * q));
+          w[q] = (h & 15u) | (((h >> 4) & 15u) << 8) | (((h >> 8) & 15u) << 16) | (((h >> 12) & 15u) << 24);
+        }
+        *reinterpret_cast<uint4*>(cc) = make_uint4(w[0], w[1], w[2], w[3]);
+      } else {
+        for (int j = 0; j < r.cpt; j++) cc[j] = (uint8_t)((codes >> (4 * j)) & 15u);
+      }
+    }
     if (threadIdx.x == 0) {
       const int64_t nsbt = g.sb_first[g.L + 1];
       const int64_t sbi = g.sb_first[r.lev] + ((b - g.comp_first[r.lev]) >> g.sb_shift[r.lev]);
@@ -1904,9 +1921,29 @@ __global__ __launch_bounds__(TPB) void k_comp_write(Geo g, Dev p, int lo, int fu
   for (int64_t b = g.comp_first[lo] + blockIdx.x; b < nbt; b += gridDim.x) {
     const CompRange r = comp_range(g, lo, b);
     if (level_empty(p, r.lev, full)) continue;
-    if (!full && comp_skip<D>(g, p, r)) continue;
-    uint64_t codes, tot;
-    const uint64_t c = lane_counts<D>(g, p, r, false, &codes);
+    // the count pass left the block's counts (zero for skipped blocks) and
+    // every listed cell's code
+    const int n0 = p.bcnt[clist(0) * nbt + b], n1 = p.bcnt[clist(1) * nbt + b];
+    const int n2 = p.bcnt[clist(2) * nbt + b], n3 = p.bcnt[clist(3) * nbt + b];
+    if ((n0 | n1 | n2 | n3) == 0) {
+      if (threadIdx.x == 0 && wide_level(g, r.lev)) p.bsum[g.bs_off[r.lev] + (r.tb >> BS_SHIFT)] = 0;
+      continue;
+    }
+    uint64_t codes = 0ull, c = 0ull, tot;
+    if (r.act) {
+      const uint8_t* cc = p.ccode + g.off[r.lev] + r.t0;
+      if (r.cpt == GRP) {
+        const uint4 v = *reinterpret_cast<const uint4*>(cc);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+#pragma unroll
+          for (int i = 0; i < 4; i++) codes |= (uint64_t)((w[q] >> (8 * i)) & 15u) << (4 * (4 * q + i));
+      } else {
+        for (int j = 0; j < r.cpt; j++) codes |= (uint64_t)(cc[j] & 15u) << (4 * j);
+      }
+      for (int j = 0; j < r.cpt; j++) c += code_count((uint32_t)(codes >> (4 * j)) & 15u);
+    }
     const uint64_t ex = block_exscan<uint64_t>(c, sh, &tot);
     // list offsets of the block: its superblock's plus the counts of the
     // preceding blocks of the superblock (fewer than 64: wave 0 sums them)

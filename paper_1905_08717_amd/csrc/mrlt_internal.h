@@ -82,6 +82,7 @@ struct Dev {
   uint8_t* st;     // status per cell
   uint8_t* rf;     // remesh scratch: bit1 member of W (nodes that will be internal)
   uint8_t* sigt;   // per internal node: significant at the last remesh that evaluated its level
+  uint8_t* ccode;  // list codes per cell, from the compaction's count pass to its write pass
   uint8_t* bsum;   // per 4096-cell block: 1 a cell exists, 2 one is internal, 4 one is a leaf
   uint8_t* wsum;   // per 4096-cell block: 1 when the block may hold W marks
   uint8_t* nsum;   // per 4096-cell block: 1 when an internal node is in it or a neighbour block

@@ -438,6 +438,7 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
   ALLOC(c->p.st, uint8_t, g.Ntot);
   ALLOC(c->p.rf, uint8_t, g.Ntot);
   ALLOC(c->p.sigt, uint8_t, g.Ntot);
+  ALLOC(c->p.ccode, uint8_t, g.Ntot);
   ALLOC(c->p.bsum, uint8_t, g.bs_off[L + 1]);
   ALLOC(c->p.wsum, uint8_t, g.bs_off[L + 1]);
   ALLOC(c->p.nsum, uint8_t, g.bs_off[L + 1]);
