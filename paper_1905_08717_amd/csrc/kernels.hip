@@ -85,6 +85,26 @@ __device__ __forceinline__ void mdec(uint64_t k, int* x) {
   }
 }
 
+// Morton bits of axis a (a, a + D, a + 2D, ...)
+template <int D>
+__device__ __forceinline__ constexpr uint64_t axis_mask(int a) {
+  return D == 1 ? ~0ull
+         : D == 2 ? (a == 0 ? 0x5555555555555555ull : 0xaaaaaaaaaaaaaaaaull)
+                  : (a == 0 ? 0x9249249249249249ull : (a == 1 ? 0x2492492492492492ull : 0x4924924924924924ull));
+}
+// key of the cell o cells (|o| <= 2) along axis a from key k, the coordinate
+// staying on the level: an add on the dilated coordinate (the other axes'
+// bits are set to 1 so that carries pass them, or cleared so that borrows
+// do), a few operations instead of a decode and an encode
+template <int D>
+__device__ __forceinline__ uint64_t morton_step(uint64_t k, int a, int o) {
+  if (D == 1) return o > 0 ? k + (uint64_t)o : k - (uint64_t)(-o);
+  const uint64_t m = axis_mask<D>(a);
+  const uint64_t d = (o == 1 || o == -1) ? (1ull << a) : (1ull << (D + a));
+  if (o > 0) return (((k | ~m) + d) & m) | (k & ~m);
+  return (((k & m) - d) & m) | (k & ~m);
+}
+
 // stencil coordinate: periodic wraps, homogeneous Neumann reflects evenly
 __device__ __forceinline__ int map_st(int i, int n, int per) {
   if (i < 0) return per ? i + n : -1 - i;
@@ -102,6 +122,39 @@ __device__ __forceinline__ int map_nb(int i, int n, int per) {
   if (i < 0) return per ? i + n : -1;
   if (i >= n) return per ? i - n : -1;
   return i;
+}
+
+// within-instance key of the stencil cell at offset o along axis a of the
+// cell (coordinates x, key k) on a level of n cells per axis; *fl: the
+// Dirichlet sign flip of a mirrored cell
+template <int D>
+__device__ __forceinline__ uint64_t stencil_key(const Geo& g, const int* x, uint64_t k, int n, int a, int o,
+                                                bool* fl) {
+  const int c = x[a] + o;
+  if (c >= 0 && c < n) {
+    *fl = false;
+    return morton_step<D>(k, a, o);
+  }
+  int y[3] = {x[0], x[1], x[2]};
+  y[a] = map_st(c, n, g.periodic[a]);
+  *fl = st_flip(c, n, g.dirichlet[a]);
+  return menc<D>(y);
+}
+// the same with the neighbourhood mapping: false when outside the domain
+template <int D>
+__device__ __forceinline__ bool nbhd_key(const Geo& g, const int* x, uint64_t k, int n, int a, int o,
+                                         uint64_t* out) {
+  const int c = x[a] + o;
+  if (c >= 0 && c < n) {
+    *out = morton_step<D>(k, a, o);
+    return true;
+  }
+  const int u = map_nb(c, n, g.periodic[a]);
+  if (u < 0) return false;
+  int y[3] = {x[0], x[1], x[2]};
+  y[a] = u;
+  *out = menc<D>(y);
+  return true;
 }
 
 __device__ __forceinline__ void flag_bad(const Dev& p, int64_t inst, unsigned long long code) {
@@ -784,8 +837,9 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
       const int64_t t = p.lst[LS][g.off[lev] + kk];
       const int64_t G = g.off[lev] + t;
       const int64_t inst = t >> (D * lev);
+      const uint64_t key = (uint64_t)(t & (nl - 1));
       int x[3];
-      mdec<D>((uint64_t)(t & (nl - 1)), x);
+      mdec<D>(key, x);
       const int64_t ib = g.off[lev] + inst * nl;
       // status of the 2d face neighbours (3: outside the domain)
       int nbs[D][2];
@@ -797,12 +851,8 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
         for (int side = 0; side < 2; side++) {
           const int nb = map_nb(x[dir] + (side ? 1 : -1), n, g.periodic[dir]);
           nbs[dir][side] = nb;
-          uint8_t sv = 3;
-          if (nb >= 0) {
-            int y[3] = {x[0], x[1], x[2]};
-            y[dir] = nb;
-            sv = p.st[ib + (int64_t)menc<D>(y)];
-          }
+          uint64_t ky;
+          const uint8_t sv = nbhd_key<D>(g, x, key, n, dir, side ? 1 : -1, &ky) ? p.st[ib + (int64_t)ky] : 3;
           sts[dir][side] = sv;
           refined = refined || sv == ST_INTERNAL;
         }
@@ -811,11 +861,9 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
         for (int dir = 0; dir < D; dir++)
 #pragma unroll
           for (int side = 0; side < 2; side++) {
-            const int nb = map_nb(x[dir] + (side ? 2 : -2), n, g.periodic[dir]);
-            if (nb < 0) continue;
-            int y[3] = {x[0], x[1], x[2]};
-            y[dir] = nb;
-            refined = refined || p.st[ib + (int64_t)menc<D>(y)] == ST_INTERNAL;
+            uint64_t ky;
+            if (nbhd_key<D>(g, x, key, n, dir, side ? 2 : -2, &ky))
+              refined = refined || p.st[ib + (int64_t)ky] == ST_INTERNAL;
           }
       }
       if (!IFACE && refined && !finest) continue;  // the interface launch owns it
@@ -830,10 +878,8 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
         for (int o = -2; o <= 2; o++) {
           // two-point diffusion needs only the face neighbours
           if (two_point<PDE>(g) && (o == -2 || o == 2)) continue;
-          int y[3] = {x[0], x[1], x[2]};
-          y[dir] = map_st(x[dir] + o, n, g.periodic[dir]);
-          const bool fl = st_flip(x[dir] + o, n, g.dirichlet[dir]);
-          const int64_t Gy = o == 0 ? G : ib + (int64_t)menc<D>(y);
+          bool fl = false;
+          const int64_t Gy = o == 0 ? G : ib + (int64_t)stencil_key<D>(g, x, key, n, dir, o, &fl);
 #pragma unroll
           for (int k = 0; k < M; k++) {
             const double v = cur[(int64_t)k * NT + Gy];
