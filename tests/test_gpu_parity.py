@@ -221,7 +221,7 @@ def test_batch_instances_equal_solo_runs(mods):
             assert compare_state(orc[i], s, inst=i, what=f"instance {i}")
 
 
-@pytest.mark.parametrize("case", ["nagumo2d", "euler3d"])
+@pytest.mark.parametrize("case", ["nagumo2d", "euler3d", "burgers2d_dirichlet", "burgers2d_periodic"])
 def test_wide_batch_against_oracle(mods, case):
     # levels with >= 2^20 cells over the batch take the block summaries, the
     # 16-cell groups and the per-tile NERK flags (leaves far from refinement
@@ -232,11 +232,18 @@ def test_wide_batch_against_oracle(mods, case):
         cfg = W.nagumo_2d(L=L, eps=1e-4)       # leaves down to level 9
         q = np.stack([W.nagumo_front(L, W.SEED + 100 + i) for i in range(B)])
         dts = [W.nagumo_dt(cfg)] * 2
-    else:
+    elif case == "euler3d":
         B, L = 32, 6
         cfg = W.euler_3d(L=L)                  # level 5: 32 * 8^5 = 2^20 cells
         q = np.stack([W.euler_sphere(L)] * B)
         dts = [0.8 * W.euler_dt(cfg, 5.0, 0.0)] * 2   # s_max stays below 5
+    else:
+        # level 8: 16 * 4^8 = 2^20 cells; the boundary tiles of the wide
+        # passes with odd mirroring or wrap-around
+        B, L = 16, 9
+        cfg = dict(W.burgers_2d(L=L), bc=case.split("_")[1])
+        q = np.stack([W.burgers_sinsin(L) * (1.0 + 0.02 * i) for i in range(B)])
+        dts = [W.burgers_dt(cfg, 1.4)] * 2
     s = mrlt.Solver(cfg, n_inst=B)
     s.load_finest(q)
     sample = [0, B // 2 - 1, B - 1]
