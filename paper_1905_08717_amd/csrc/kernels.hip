@@ -825,16 +825,34 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
   }
   const int64_t NT = g.Ntot;
   const double* cur = p.q[stage == 1 ? SL_Q0 : (stage == 2 ? SL_Q1 : SL_QH)];
+  // bulk leaves: the stencil values of every axis, the neighbour statuses
+  // and the leaf's own slots are all requested before any of them is used
+  // (one memory round trip per leaf), and the next list entry is fetched
+  // while a leaf is processed; a leaf found to be an interface leaf is
+  // computed but not stored.  Wide stencils of many fields load per axis.
+  constexpr bool PRE = !IFACE && D * M <= 6;
   __shared__ int s_cnt[MRD_MAXLEV + 1];
   const int64_t ntot = flat_setup(p, LS, lo, hi, s_cnt);
-  GSL(i, ntot) {
+  const int64_t step = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int lev_n = lo, e_n = 0;
+  if (i < ntot) {
+    int64_t kk = i;
+    lev_n = flat_level(s_cnt, lo, kk);
+    e_n = p.lst[LS][g.off[lev_n] + kk];
+  }
+  for (; i < ntot; i += step) {
     {
-      int64_t kk = i;
-      const int lev = flat_level(s_cnt, lo, kk);
+      const int lev = lev_n;
+      const int64_t t = e_n;
+      if (i + step < ntot) {
+        int64_t kk = i + step;
+        lev_n = flat_level(s_cnt, lo, kk);
+        e_n = p.lst[LS][g.off[lev_n] + kk];
+      }
       const int64_t nl = g.n[lev];
       const int n = 1 << lev;
       const bool finest = lev == g.L;
-      const int64_t t = p.lst[LS][g.off[lev] + kk];
       const int64_t G = g.off[lev] + t;
       const int64_t inst = t >> (D * lev);
       const uint64_t key = (uint64_t)(t & (nl - 1));
@@ -856,7 +874,8 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
           sts[dir][side] = sv;
           refined = refined || sv == ST_INTERNAL;
         }
-      if (!IFACE && !finest && !refined && (PDE != PDE_NAGUMO && PDE != PDE_LINEAR) && stencil_reach(g) == 2) {
+      if (!IFACE && (PRE || (!finest && !refined)) && (PDE != PDE_NAGUMO && PDE != PDE_LINEAR) &&
+          stencil_reach(g) == 2) {
 #pragma unroll
         for (int dir = 0; dir < D; dir++)
 #pragma unroll
@@ -866,7 +885,33 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
               refined = refined || p.st[ib + (int64_t)ky] == ST_INTERNAL;
           }
       }
-      if (!IFACE && refined && !finest) continue;  // the interface launch owns it
+      // stencils of all axes (PRE) and the leaf's own slots
+      double c5a[PRE ? D : 1][5][M];
+      if (PRE) {
+#pragma unroll
+        for (int dir = 0; dir < (PRE ? D : 1); dir++)
+#pragma unroll
+          for (int o = -2; o <= 2; o++) {
+            if (two_point<PDE>(g) && (o == -2 || o == 2)) continue;
+            bool fl = false;
+            const int64_t Gy = o == 0 ? G : ib + (int64_t)stencil_key<D>(g, x, key, n, dir, o, &fl);
+#pragma unroll
+            for (int k = 0; k < M; k++) {
+              const double v = cur[(int64_t)k * NT + Gy];
+              c5a[dir][o + 2][k] = fl ? -v : v;
+            }
+          }
+      }
+      double q0v[M], qsv[M];
+#pragma unroll
+      for (int k = 0; k < M; k++) {
+        const int64_t I = (int64_t)k * NT + G;
+        q0v[k] = p.q[SL_Q0][I];
+        qsv[k] = stage == 2 ? p.q[SL_Q1][I] : (stage == 3 ? p.q[SL_QH][I] : 0.0);
+      }
+      const uint8_t nflag = (!IFACE && !finest && g.lt && wide_level(g, lev)) ? p.nsum[g.bs_off[lev] + (t >> BS_SHIFT)] : 1;
+      if (!PRE && !IFACE && refined && !finest) continue;  // the interface launch owns it
+      const bool active = IFACE || finest || !refined;
       const double h = g.lt ? ldexp(p.dt[inst], g.L - lev) : p.dt[inst];
       // weights b_i of the RK method: RK3 (1/6, 1/6, 2/3), RK2 (1/2, 1/2)
       const double wh = (g.rk == 2 ? 0.5 : (stage == 3 ? C_2_3 : C_1_6)) * h;
@@ -874,16 +919,23 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
 #pragma unroll
       for (int dir = 0; dir < D; dir++) {
         double c5[5][M];
+        if (PRE) {
 #pragma unroll
-        for (int o = -2; o <= 2; o++) {
-          // two-point diffusion needs only the face neighbours
-          if (two_point<PDE>(g) && (o == -2 || o == 2)) continue;
-          bool fl = false;
-          const int64_t Gy = o == 0 ? G : ib + (int64_t)stencil_key<D>(g, x, key, n, dir, o, &fl);
+          for (int o = 0; o < 5; o++)
 #pragma unroll
-          for (int k = 0; k < M; k++) {
-            const double v = cur[(int64_t)k * NT + Gy];
-            c5[o + 2][k] = fl ? -v : v;
+            for (int k = 0; k < M; k++) c5[o][k] = c5a[PRE ? dir : 0][o][k];
+        } else {
+#pragma unroll
+          for (int o = -2; o <= 2; o++) {
+            // two-point diffusion needs only the face neighbours
+            if (two_point<PDE>(g) && (o == -2 || o == 2)) continue;
+            bool fl = false;
+            const int64_t Gy = o == 0 ? G : ib + (int64_t)stencil_key<D>(g, x, key, n, dir, o, &fl);
+#pragma unroll
+            for (int k = 0; k < M; k++) {
+              const double v = cur[(int64_t)k * NT + Gy];
+              c5[o + 2][k] = fl ? -v : v;
+            }
           }
         }
         if (two_point<PDE>(g)) {
@@ -905,7 +957,7 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
           const double r = (Fm[k] - Fp[k]) * g.invdx[lev][dir];
           R[k] = dir == 0 ? r : (R[k] + r);
         }
-        if (g.reflux) {
+        if (g.reflux && active) {
 #pragma unroll
           for (int side = 0; side < 2; side++) {
             const double* F = side ? Fp : Fm;
@@ -936,21 +988,22 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
         }
       }
       if (has_source<PDE>()) {
+        // the stage value of the leaf itself: q^n, q* or q**
         double qs[M];
 #pragma unroll
-        for (int k = 0; k < M; k++) qs[k] = cur[(int64_t)k * NT + G];
+        for (int k = 0; k < M; k++) qs[k] = stage == 1 ? q0v[k] : qsv[k];
         add_source<PDE>(g, qs, R);
       }
+      if (!active) continue;
       // the NERK values of a leaf (H1, N14, N34; the theta=1/2 value of RK2)
       // feed only the virtual cells of the next finer level, whose parent
       // stencils lie within Chebyshev distance 2 of an internal node of the
       // leaf's level; with one global step they are not used at all
-      bool nerk = !finest && g.lt;
-      if (!IFACE && nerk && wide_level(g, lev)) nerk = p.nsum[g.bs_off[lev] + (t >> BS_SHIFT)] != 0;
+      const bool nerk = !finest && g.lt && nflag != 0;
 #pragma unroll
       for (int k = 0; k < M; k++) {
         const int64_t I = (int64_t)k * NT + G;
-        const double q0 = p.q[SL_Q0][I];
+        const double q0 = q0v[k];
         const double r = R[k];
         if (g.rk == 2) {
           // compact RK2; the NERK theta=1/2 value in parts 3/8 and 1/8 (Sec. 3)
@@ -961,7 +1014,7 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
               p.q[SL_QH][I] = q0 + ((0.375 * h) * r);
             }
           } else {
-            const double q1 = p.q[SL_Q1][I];
+            const double q1 = qsv[k];
             const double qe = ((0.5 * q0) + (0.5 * q1)) + ((0.5 * h) * r);
             p.q[SL_QE][I] = qe;
             p.q[SL_X2][I] = q1 + (h * r);
@@ -978,7 +1031,7 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
             p.q[SL_N34][I] = q0 + (((15.0 / 32.0) * h) * r);
           }
         } else if (stage == 2) {
-          const double q1 = p.q[SL_Q1][I];
+          const double q1 = qsv[k];
           p.q[SL_QH][I] = ((0.75 * q0) + (0.25 * q1)) + ((0.25 * h) * r);
           p.q[SL_X2][I] = q1 + (h * r);
           if (nerk) {
@@ -986,7 +1039,7 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
             p.q[SL_N34][I] = p.q[SL_N34][I] + (((9.0 / 32.0) * h) * r);
           }
         } else {
-          const double qh = p.q[SL_QH][I];
+          const double qh = qsv[k];
           const double qe = ((C_1_3 * q0) + (C_2_3 * qh)) + ((C_2_3 * h) * r);
           p.q[SL_QE][I] = qe;
           if (!isfinite(qe)) atomicOr(&p.cnt[inst * CNT_PER_INST + CNT_NONFINITE], 1ull);
