@@ -456,12 +456,39 @@ def test_flame_1d_paper_problem(mods, rk, lt, fs):
     _check_flame_speed(o, s)
 
 
-@pytest.mark.parametrize("L", [5, 6])
-def test_flame_ball_3d(mods, L):
-    # the 3D flame ball (Lewis number 0.3, radiation, eps = 1e-2)
-    cfg = W.flame_ball_3d(L=L)
+@pytest.mark.parametrize("L,rk,lt", [(5, 3, 1), (6, 3, 1), (5, 2, 1), (5, 3, 0)])
+def test_flame_ball_3d(mods, L, rk, lt):
+    # the 3D flame ball (Lewis number 0.3, radiation, eps = 1e-2), MRLT/NERK3,
+    # MRLT/NERK2 and one global step
+    cfg = dict(W.flame_ball_3d(L=L), rk=rk, lt=lt)
     o, s = run_pair(mods, cfg, W.flame_ball(L), [W.flame_dt(cfg)] * 2)
     _check_flame_speed(o, s)
+
+
+def test_flame_ball_wide_batch(mods):
+    # 32 flame balls of different orientation at L = 5: level 5 holds 2^20
+    # cells over the batch (16-cell groups, block summaries, NERK tile flags
+    # with two fields)
+    mro, mrlt = mods
+    B, L = 32, 5
+    cfg = W.flame_ball_3d(L=L)
+    q = np.stack([W.flame_ball(L, theta=0.3 + 0.05 * i, phi=0.2 + 0.03 * i) for i in range(B)])
+    s = mrlt.Solver(cfg, n_inst=B)
+    s.load_finest(q)
+    sample = [0, 13, 31]
+    orc = {}
+    for i in sample:
+        o = mro.Oracle(cfg)
+        o.load_finest(q[i])
+        orc[i] = o
+    dt = W.flame_dt(cfg)
+    print(f"[parity] flame ball batch B={B} L={L}", flush=True)
+    for j in range(2):
+        s.lt_step(dt)
+        for i in sample:
+            orc[i].lt_step(dt)
+            assert compare_state(orc[i], s, inst=i, what=f"instance {i}, macro step {j}")
+            _check_flame_speed(orc[i], s, inst=i)
 
 
 def _wrinkled_front_2d(L, lo=-15.0, hi=15.0, amp=1.5):

@@ -15,6 +15,7 @@
   flame of the one-dimensional case travels at about v_f in the rest frame,
   stands still in the frame moving at -v_f, and v_f approaches the
   large-activation-energy flame speed 1 of this normalisation of omega.
+* A spherical flame ball centred in the box keeps the octahedral symmetry.
 """
 import math
 
@@ -180,3 +181,25 @@ def test_flame_parameters_validated(oracle_mod):
             oracle_mod.Oracle(cfg)
     with pytest.raises(oracle_mod.OracleError):
         oracle_mod.Oracle(dict(W.nagumo_2d(L=4), flame_speed=1))
+
+
+def test_spherical_flame_ball_keeps_octahedral_symmetry(oracle_mod):
+    """With a = b = c and no rotation the flame ball is a sphere centred in
+    the box: the solution must stay invariant under axis permutations and
+    reflections (a wrong stride, Lewis number or sign on one axis breaks
+    it), also with an adaptive tree."""
+    L = 5
+    n = 1 << L
+    cfg = W.flame_ball_3d(L=L)
+    o = oracle_mod.Oracle(cfg)
+    o.load_finest(W.flame_ball(L, axes=(1.5, 1.5, 1.5), theta=0.0, phi=0.0))
+    dt = W.flame_dt(cfg)
+    for _ in range(3):
+        o.lt_step(dt)
+    assert o.stats()["leaves"][L - 1] > 0          # a multilevel tree
+    r = o.reconstruct()
+    for A in (r[0].reshape(n, n, n), r[1].reshape(n, n, n)):
+        for B in (A.transpose(1, 0, 2), A.transpose(2, 1, 0), A.transpose(0, 2, 1),
+                  A[::-1], A[:, ::-1], A[:, :, ::-1]):
+            assert np.abs(A - B).max() < 1e-12
+    assert r[0].max() > 0.5 and r[1].min() < 0.5
