@@ -466,9 +466,15 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
 #undef ALLOC
   c->p.dt = c->dt_d;
   c->p.eps = c->eps_d;
-  st = hip_check(c, hipMemcpy(c->eps_d, eps, sizeof(double) * n_inst, hipMemcpyHostToDevice), "eps upload");
+  // the zero fills of the allocations are queued on the context's own
+  // non-blocking stream, which does not order with the null stream: the
+  // upload goes behind them on the same stream (a blocking hipMemcpy could
+  // land first and then be zeroed, leaving every threshold at 0)
+  st = hip_check(c, hipMemcpyAsync(c->eps_d, c->eps.data(), sizeof(double) * n_inst, hipMemcpyHostToDevice,
+                                   c->stream),
+                 "eps upload");
   if (st != MR_OK) goto fail;
-  st = hip_check(c, hipDeviceSynchronize(), "init");
+  st = hip_check(c, hipStreamSynchronize(c->stream), "init");
   if (st != MR_OK) goto fail;
   *out = c;
   return MR_OK;

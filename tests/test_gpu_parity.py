@@ -307,6 +307,33 @@ def test_full_size_nagumo_one_macro_step(mods):
     run_pair(mods, cfg, W.nagumo_front(9), [W.nagumo_dt(cfg)])
 
 
+def test_large_batch_thresholds_take_effect(mods):
+    # A batch of 256 full-size Nagumo fronts: the context's allocations are
+    # zero-filled on its stream (several GB here), and the per-instance
+    # thresholds uploaded after them must survive those fills.  Sampled
+    # instances against the oracle after the load and one macro step.
+    mro, mrlt = mods
+    cfg = W.nagumo_2d()            # L=9, 512^2
+    B = 256
+    q = np.stack([W.nagumo_front(9, W.SEED + i) for i in range(B)])
+    s = mrlt.Solver(cfg, n_inst=B)
+    s.load_finest(q)
+    dt = W.nagumo_dt(cfg)
+    sample = (0, 131, B - 1)
+    oracles = []
+    for i in sample:
+        o = mro.Oracle(cfg)
+        o.load_finest(q[i])
+        assert o.stats()["leaves"][9] < (1 << 18) // 4       # an adapted tree
+        assert compare_state(o, s, inst=i, what=f"instance {i} after load")
+        oracles.append(o)
+    s.lt_step(dt)
+    for i, o in zip(sample, oracles):
+        o.lt_step(dt)
+        compare_state(o, s, inst=i, what=f"instance {i} after one macro step")
+    s.close()
+
+
 def test_full_size_euler_3d_properties(mods):
     # 128^3 spherical Riemann problem: one macro step on the GPU (the size the
     # benchmark runs); the oracle is too slow here, so check properties that
