@@ -39,10 +39,11 @@ def leaf_counts(s):
     return tot
 
 
-def stage_traffic(batch):
+def stage_traffic(batch, list_grid):
     """HBM bytes per launch of the bulk stage kernel from the committed
     FETCH_SIZE / WRITE_SIZE counter runs, when they were taken on this batch
-    size and on the current kernel source; otherwise None."""
+    size, this grid of the list-driven kernels and the current kernel
+    source; otherwise None."""
     here = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(here, "profiles", "stage_bulk_traffic.json")
     src = os.path.join(here, "paper_1905_08717_amd", "csrc", "kernels.hip")
@@ -54,6 +55,8 @@ def stage_traffic(batch):
     except (OSError, ValueError):
         return None
     if rec.get("kernels_hip_sha256") != digest or rec.get("batch") != batch:
+        return None
+    if rec.get("launch", {}).get("list_grid") != list_grid:
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -117,13 +120,23 @@ def traffic_record(args):
     w = col(os.path.join(d, "pmc_write", "write_counter_collection.csv"), kern)[-n:]
     fetch = sum(f) / len(f) * sf * 1024
     write = sum(w) / len(w) * sw * 1024
+
+    # the launch configuration of the two counter runs (their bench lines)
+    def launch_of(log):
+        with open(os.path.join(d, log)) as fh:
+            lines = [ln for ln in fh if ln.startswith("{")]
+        return json.loads(lines[-1]).get("launch") if lines else None
+
+    launch = launch_of("pmc_fetch.log")
+    if launch != launch_of("pmc_write.log"):
+        raise SystemExit("the two counter runs used different launch configurations")
     here = os.path.dirname(os.path.abspath(__file__))
     with open(os.path.join(here, "paper_1905_08717_amd", "csrc", "kernels.hip"), "rb") as fh:
         digest = hashlib.sha256(fh.read()).hexdigest()
     rec = {"kernel": kern, "batch": args.batch, "steps": args.steps, "warmup": args.warmup,
            "launches_averaged": len(f), "fetch_scale": round(sf, 4), "write_scale": round(sw, 4),
            "fetch_bytes_per_launch": round(fetch), "write_bytes_per_launch": round(write),
-           "hbm_bytes_per_launch": round(fetch + write), "kernels_hip_sha256": digest}
+           "hbm_bytes_per_launch": round(fetch + write), "kernels_hip_sha256": digest, "launch": launch}
     with open(os.path.join(here, "profiles", "stage_bulk_traffic.json"), "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec), flush=True)
@@ -295,6 +308,9 @@ def main():
     ap.add_argument("--flame-ball-level", type=int, default=7, help="flames mode: 3D flame ball L (0: skip)")
     ap.add_argument("--pmc-dir", default="gpurun_out", help="traffic mode: folder of the four counter runs")
     ap.add_argument("--no-single", action="store_true", help="skip the single-solve reference run")
+    ap.add_argument("--tune", action="store_true", help="search the launch configuration before timing")
+    ap.add_argument("--no-tune", action="store_true", help="library default launch configuration")
+    ap.add_argument("--launch", default="", help="list,iface,comp grid caps")
     ap.add_argument("--requests", type=int, default=0)
     ap.add_argument("--solo-sample", type=int, default=32)
     ap.add_argument("--rate", type=float, default=200.0)
@@ -330,8 +346,28 @@ def main():
     B = args.batch
     dt = W.nagumo_dt(cfg)
     q0 = np.stack([W.nagumo_front(cfg["L"], W.SEED + i) for i in range(B)])
+    q0d = torch.from_numpy(q0).to("cuda")
     s = mrlt.Solver(cfg, n_inst=B)
-    s.load_finest(torch.from_numpy(q0).to("cuda"))
+    # launch configuration (results do not depend on it): given, searched
+    # now (untimed), the stored measured setting of this workload, or the
+    # library default
+    from paper_1905_08717_amd import autotune
+    tuned, source = None, "library default"
+    stored = autotune.lookup(autotune.nagumo_key(cfg["L"], B))
+    if args.launch:
+        lg, ig, cg = (int(v) for v in args.launch.split(","))
+        s.set_launch(list_grid=lg, iface_grid=ig, comp_grid=cg)
+        source = "--launch"
+    elif args.tune:
+        r = autotune.tune(s, q0d, dt, passes=1)
+        tuned = {"launch": r["best"], "ms_per_step_default": round(1e3 * r["default"], 2),
+                 "ms_per_step_tuned": round(1e3 * r["seconds_per_step"], 2), "trials": len(r["trials"])}
+        source = "tuned in this run"
+        print(f"[bench] launch {tuned}", file=sys.stderr, flush=True)
+    elif stored and not args.no_tune:
+        s.set_launch(**stored)
+        source = "paper_1905_08717_amd/tuned_launch.json"
+    s.load_finest(q0d)
     for _ in range(args.warmup):
         s.lt_step(dt)
 
@@ -361,7 +397,7 @@ def main():
     alg_bytes = int(items[0]) * 16 * m + int(items[1]) * 24 * m + int(items[2]) * 24 * m
     achieved = alg_bytes / (ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": 8000.0, "unit": "GB/s",
-                "frac": round(achieved / 8000.0, 5), "traffic": stage_traffic(B),
+                "frac": round(achieved / 8000.0, 5), "traffic": stage_traffic(B, s.get_launch()["list_grid"]),
                 "kernel": "k_stage<2, 2, false> (bulk RK stage kernel, all levels of a stage)",
                 "launches": launches, "avg_launch_us": round(ms * 1e3 / max(launches, 1), 3),
                 "alg_bytes_per_launch": round(alg_bytes / max(launches, 1), 1),
@@ -392,6 +428,9 @@ def main():
                    "dim": 2, "L": 9, "l0": 2, "eps": 1e-3, "batch": B, "dt_L": dt,
                    "leaves_per_level_total": [int(x) for x in leaves[:10]]},
         "roofline": roofline,
+        "launch": s.get_launch(),
+        "launch_source": source,
+        "autotune": tuned,
         "single_solve_leaf_updates_per_s": single,
         "solves_macro_steps_per_s": round(B * args.steps / el, 2),
     }

@@ -170,6 +170,19 @@ mr_status mr_reconstruct(mr_ctx* c, double* q_out);
  * out: host array of n_inst values.                                        */
 mr_status mr_max_wavespeed(mr_ctx* c, double* out);
 
+/* Launch configuration of a context: the most workgroups given to the
+ * list-driven kernels (stage, ghost values, projections, end of step;
+ * default 2048), to the interface-leaf stage launches (512) and to the
+ * list compaction (8192); the kernels loop over the rest.  A tuning knob
+ * only: results are identical for every setting.  A value of 0 keeps the
+ * current one; values outside 0..65535 give MR_EINVAL.  Setting it drops
+ * the captured macro-step graph (recaptured by the next mr_lt_step).     */
+typedef struct {
+  int32_t list_grid, iface_grid, comp_grid;
+} mr_launch;
+mr_status mr_set_launch(mr_ctx* c, const mr_launch* l);
+mr_status mr_get_launch(mr_ctx* c, mr_launch* l);   /* l: host struct, filled */
+
 /* Flame velocity of Sec. 5, v_f = integral of the reaction rate omega over
  * the domain, per unit cross-section normal to axis 0: per instance the sum
  * over its current leaves of omega(cell average) times the cell volume, in a

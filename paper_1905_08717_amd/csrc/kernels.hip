@@ -22,6 +22,15 @@ int blocks_for(int64_t n) {
   if (b > 2048) b = 2048;  // 8 waves per CU on 256 CUs; loops stride over the rest
   return (int)b;
 }
+// grid of the list-driven kernels (stage, ghost, projection, finalize): at
+// most g.list_grid workgroups, the loops stride over the rest (a launch knob
+// of the context, tuned by measurement; results do not depend on it)
+int list_blocks(const Geo& g, int64_t n) {
+  int64_t b = (n + TPB - 1) / TPB;
+  if (b < 1) b = 1;
+  if (b > g.list_grid) b = g.list_grid;
+  return (int)b;
+}
 
 // ---------------------------------------------------------------------------
 // Morton keys and boundary maps
@@ -650,7 +659,7 @@ __global__ __launch_bounds__(TPB) void k_project(Geo g, Dev p, int lev, int mode
 
 void launch_project(const Geo& g, const Dev& p, int lev, int mode, hipStream_t s) {
   const int64_t n = g.B * g.n[lev];
-  k_project<<<blocks_for(n), TPB, 0, s>>>(g, p, lev, mode);
+  k_project<<<list_blocks(g, n), TPB, 0, s>>>(g, p, lev, mode);
 }
 
 // ---------------------------------------------------------------------------
@@ -698,9 +707,10 @@ void launch_ghost(const Geo& g, const Dev& p, int lo, int hi, int cb_lev, int st
   // first-order theta=1/2, theta=1/4
   const int srcA = !g.lt ? dst : (stage == 1 ? SL_Q0 : (stage == 2 ? SL_H1 : SL_N14));
   const int64_t n = g.B * g.n[hi];
-  if (g.d == 1) k_ghost<1><<<blocks_for(n), TPB, 0, s>>>(g, p, lo, hi, cb_lev, srcA, srcB, dst);
-  else if (g.d == 2) k_ghost<2><<<blocks_for(n), TPB, 0, s>>>(g, p, lo, hi, cb_lev, srcA, srcB, dst);
-  else k_ghost<3><<<blocks_for(n), TPB, 0, s>>>(g, p, lo, hi, cb_lev, srcA, srcB, dst);
+  const int nb = list_blocks(g, n);
+  if (g.d == 1) k_ghost<1><<<nb, TPB, 0, s>>>(g, p, lo, hi, cb_lev, srcA, srcB, dst);
+  else if (g.d == 2) k_ghost<2><<<nb, TPB, 0, s>>>(g, p, lo, hi, cb_lev, srcA, srcB, dst);
+  else k_ghost<3><<<nb, TPB, 0, s>>>(g, p, lo, hi, cb_lev, srcA, srcB, dst);
 }
 
 // ---------------------------------------------------------------------------
@@ -1052,14 +1062,14 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
 template <int D, int PDE>
 static void stage_dp(const Geo& g, const Dev& p, int lo, int hi, int stage, int part, hipStream_t s) {
   if (part == 0) {
-    k_stage<D, PDE, false><<<blocks_for(g.B * g.n[hi]), TPB, 0, s>>>(g, p, lo, hi, stage);
+    k_stage<D, PDE, false><<<list_blocks(g, g.B * g.n[hi]), TPB, 0, s>>>(g, p, lo, hi, stage);
     return;
   }
   const int hif = hi < g.L ? hi : g.L - 1;
   if (lo > hif) return;
   // interface leaves lie along refinement boundaries: a small fraction
   int nb = blocks_for(g.B * g.n[hif]);
-  if (nb > 512) nb = 512;
+  if (nb > g.iface_grid) nb = g.iface_grid;
   k_stage<D, PDE, true><<<nb, TPB, 0, s>>>(g, p, lo, hif, stage);
 }
 
@@ -1139,9 +1149,10 @@ __global__ __launch_bounds__(TPB) void k_finalize(Geo g, Dev p, int lo, int hi) 
 void launch_finalize(const Geo& g, const Dev& p, int lo, int hi, hipStream_t s) {
   if (lo > hi) return;
   const int64_t n = g.B * g.n[hi];
-  if (g.d == 1) k_finalize<1><<<blocks_for(n), TPB, 0, s>>>(g, p, lo, hi);
-  else if (g.d == 2) k_finalize<2><<<blocks_for(n), TPB, 0, s>>>(g, p, lo, hi);
-  else k_finalize<3><<<blocks_for(n), TPB, 0, s>>>(g, p, lo, hi);
+  const int nb = list_blocks(g, n);
+  if (g.d == 1) k_finalize<1><<<nb, TPB, 0, s>>>(g, p, lo, hi);
+  else if (g.d == 2) k_finalize<2><<<nb, TPB, 0, s>>>(g, p, lo, hi);
+  else k_finalize<3><<<nb, TPB, 0, s>>>(g, p, lo, hi);
 }
 
 __global__ void k_zero(double* a, int64_t n) { GSL(t, n) a[t] = 0.0; }
@@ -2128,7 +2139,7 @@ __global__ __launch_bounds__(TPB) void k_nerk_tiles(Geo g, Dev p, int lo) {
 
 void launch_compact(const Geo& g, const Dev& p, int lo, bool full, hipStream_t s) {
   int64_t nb = g.comp_first[g.L + 1] - g.comp_first[lo];
-  if (nb > 8192) nb = 8192;
+  if (nb > g.comp_grid) nb = g.comp_grid;
   const int f = full ? 1 : 0;
   if (g.d == 1) k_comp_count<1><<<(unsigned)nb, TPB, 0, s>>>(g, p, lo, f);
   else if (g.d == 2) k_comp_count<2><<<(unsigned)nb, TPB, 0, s>>>(g, p, lo, f);

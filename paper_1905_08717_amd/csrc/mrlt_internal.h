@@ -70,6 +70,9 @@ struct Geo {
   // instances [i0, i1) that the remesh sweeps may change (all of them inside a
   // macro step; one instance when it is loaded or adapted on its own)
   int i0, i1;
+  // launch knobs (no effect on results): grid caps of the list-driven
+  // kernels, of the interface-leaf stage launches and of the compaction
+  int list_grid, iface_grid, comp_grid;
 };
 
 // per-level lists of cell indices (within-level index t = inst * n[l] + key):

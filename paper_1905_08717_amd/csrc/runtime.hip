@@ -402,6 +402,9 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
         return MR_EINVAL;
       }
   }
+  g.list_grid = 2048;
+  g.iface_grid = 512;
+  g.comp_grid = 8192;
   g.nu = s->nu;
   g.k_react = s->k_react;
   g.a_react = s->a_react;
@@ -643,6 +646,30 @@ mr_status mr_reconstruct(mr_ctx* c, double* q_out) {
   mr_status st = check_launch(c, "reconstruct");
   if (st != MR_OK) return st;
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  return MR_OK;
+}
+
+mr_status mr_set_launch(mr_ctx* c, const mr_launch* l) {
+  if (!c || !l) return MR_EINVAL;
+  const int32_t v[3] = {l->list_grid, l->iface_grid, l->comp_grid};
+  for (int j = 0; j < 3; j++)
+    if (v[j] < 0 || v[j] > 65535) return set_err(c, MR_EINVAL, "launch grid outside 0..65535");
+  if (l->list_grid) c->g.list_grid = l->list_grid;
+  if (l->iface_grid) c->g.iface_grid = l->iface_grid;
+  if (l->comp_grid) c->g.comp_grid = l->comp_grid;
+  // the captured macro step holds the old grids
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->graph_exec = nullptr;
+  c->graph = nullptr;
+  return MR_OK;
+}
+
+mr_status mr_get_launch(mr_ctx* c, mr_launch* l) {
+  if (!c || !l) return MR_EINVAL;
+  l->list_grid = c->g.list_grid;
+  l->iface_grid = c->g.iface_grid;
+  l->comp_grid = c->g.comp_grid;
   return MR_OK;
 }
 

@@ -27,7 +27,7 @@ EXPORTS = [
     "mr_get_leaves_inst", "mr_set_leaves", "mr_set_leaves_inst", "mr_stats", "mr_stats_inst",
     "mr_synchronize", "mr_last_error", "mr_destroy", "mr_level_updates", "mr_timing_start",
     "mr_timing_stop", "mr_load_finest_inst", "mr_clear_instance", "mr_instance_flags", "mr_set_eps",
-    "mr_stage_items", "mr_flame_speed",
+    "mr_stage_items", "mr_flame_speed", "mr_set_launch", "mr_get_launch",
 ]
 KC = {"stage_finest": 1, "stage": 2, "project": 3, "ghost": 4, "remesh": 5, "finalize": 6, "stage_bulk": 7}
 
@@ -45,6 +45,10 @@ class MrScheme(ctypes.Structure):
         ("ze", ctypes.c_double), ("tau", ctypes.c_double), ("lewis", ctypes.c_double),
         ("kappa", ctypes.c_double), ("flame_speed", ctypes.c_int32),
     ]
+
+
+class MrLaunch(ctypes.Structure):
+    _fields_ = [("list_grid", ctypes.c_int32), ("iface_grid", ctypes.c_int32), ("comp_grid", ctypes.c_int32)]
 
 
 class MrStats(ctypes.Structure):
@@ -91,6 +95,8 @@ def load_library():
     L.mr_reconstruct.argtypes = [vp, vp]
     L.mr_max_wavespeed.argtypes = [vp, dp]
     L.mr_flame_speed.argtypes = [vp, dp]
+    L.mr_set_launch.argtypes = [vp, ctypes.POINTER(MrLaunch)]
+    L.mr_get_launch.argtypes = [vp, ctypes.POINTER(MrLaunch)]
     L.mr_get_leaves.argtypes = [vp, u64p, dp, i64, ctypes.POINTER(i64)]
     L.mr_get_leaves_inst.argtypes = [vp, i32, u64p, dp, i64, ctypes.POINTER(i64)]
     L.mr_set_leaves.argtypes = [vp, u64p, dp, i64, dbl]
@@ -270,6 +276,18 @@ class Solver:
         arr = (ctypes.c_double * self.n_inst)()
         self._check(load_library().mr_max_wavespeed(self._h, arr), "mr_max_wavespeed")
         return np.array(arr[:])
+
+    def set_launch(self, list_grid: int = 0, iface_grid: int = 0, comp_grid: int = 0):
+        """Grid caps of the list-driven kernels, the interface-leaf stage
+        launches and the compaction (0 keeps a value); results do not
+        depend on them."""
+        lc = MrLaunch(int(list_grid), int(iface_grid), int(comp_grid))
+        self._check(load_library().mr_set_launch(self._h, ctypes.byref(lc)), "mr_set_launch")
+
+    def get_launch(self) -> dict:
+        lc = MrLaunch()
+        self._check(load_library().mr_get_launch(self._h, ctypes.byref(lc)), "mr_get_launch")
+        return {"list_grid": lc.list_grid, "iface_grid": lc.iface_grid, "comp_grid": lc.comp_grid}
 
     def flame_speed(self):
         """v_f of every instance from its current leaves (flame problems)."""

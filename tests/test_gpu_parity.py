@@ -566,3 +566,31 @@ def test_flame_batch_of_thresholds(mods):
             o.lt_step(dt)
             assert compare_state(o, s, inst=i, what=f"instance {i}, macro step {j}")
             _check_flame_speed(o, s, inst=i)
+
+
+def test_launch_knobs_do_not_change_results(mods):
+    # grid caps far below the work (every kernel loops many times) and far
+    # above it give the same leaves and values bit for bit
+    mro, mrlt = mods
+    cfg = W.nagumo_2d(L=8)
+    B = 8
+    q = np.stack([W.nagumo_front(8, W.SEED + 300 + i) for i in range(B)])
+    dt = W.nagumo_dt(cfg)
+    runs = []
+    for knobs in ({}, {"list_grid": 3, "iface_grid": 1, "comp_grid": 5}, {"list_grid": 60000, "comp_grid": 60000}):
+        s = mrlt.Solver(cfg, n_inst=B)
+        s.set_launch(**knobs)
+        assert all(s.get_launch()[k] == v for k, v in knobs.items())
+        s.load_finest(q)
+        for _ in range(2):
+            s.lt_step(dt)
+        runs.append([s.get_leaves(i) for i in (0, B - 1)])
+        s.close()
+    for other in runs[1:]:
+        for (k0, v0), (k1, v1) in zip(runs[0], other):
+            assert np.array_equal(k0, k1) and np.array_equal(v0, v1)
+    s = mrlt.Solver(cfg, n_inst=1)
+    with pytest.raises(mrlt.MrError):
+        s.set_launch(list_grid=-1)
+    with pytest.raises(mrlt.MrError):
+        s.set_launch(comp_grid=70000)
