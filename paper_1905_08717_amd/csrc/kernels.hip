@@ -9,6 +9,7 @@
 // and the appendix algorithms; readings where the paper is silent are noted
 // where they are used.
 #include "mrlt_internal.h"
+#include "group_codes.h"
 
 #define GSL(t, N) \
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (N); \
@@ -1707,128 +1708,41 @@ __device__ __forceinline__ uint32_t cell_code(const Geo& g, const Dev& p, int le
   return hit ? CODE_GHOST : 0u;
 }
 
-// 16-cell Morton groups: extent per axis and local coordinates of cell j
+// codes of the 16 cells of the Morton group at t0 (one byte per cell in
+// out[4]) and their packed list counts: the group, its parents and its 2d
+// face-adjacent groups are loaded together (one memory round trip), then
+// classified bit-parallel (group_codes.h)
 template <int D>
-__device__ __forceinline__ constexpr int gw(int a) {
-  return D == 1 ? 16 : (D == 2 ? 4 : (a == 0 ? 4 : 2));
-}
-template <int D>
-__device__ __forceinline__ constexpr int lco(int j, int a) {
-  return D == 1 ? j
-         : D == 2 ? (a == 0 ? ((j & 1) | (((j >> 2) & 1) << 1)) : (((j >> 1) & 1) | (((j >> 3) & 1) << 1)))
-                  : (a == 0 ? ((j & 1) | (((j >> 3) & 1) << 1)) : (a == 1 ? ((j >> 1) & 1) : ((j >> 2) & 1)));
-}
-template <int D>
-__device__ __forceinline__ constexpr int lidx(int lx, int ly, int lz) {
-  return D == 1 ? lx
-         : D == 2 ? ((lx & 1) | ((ly & 1) << 1) | (((lx >> 1) & 1) << 2) | (((ly >> 1) & 1) << 3))
-                  : ((lx & 1) | ((ly & 1) << 1) | ((lz & 1) << 2) | (((lx >> 1) & 1) << 3));
-}
-
-struct GroupNbhd {
-  uint4 c, m[3], p[3];   // the group, its lower and upper neighbours per axis
-  bool vm[3], vp[3];     // neighbour group inside the domain
-};
-
-// status of the cell at offset o along axis a from cell j (3: outside)
-template <int D>
-__device__ __forceinline__ uint8_t nb_status(const GroupNbhd& h, int j, int a, int o) {
-  int l[3] = {lco<D>(j, 0), D > 1 ? lco<D>(j, 1) : 0, D > 2 ? lco<D>(j, 2) : 0};
-  const int w = gw<D>(a);
-  const int v = l[a] + o;
-  if (v >= 0 && v < w) {
-    l[a] = v;
-    return byte_of(h.c, lidx<D>(l[0], l[1], l[2]));
-  }
-  if (v < 0) {
-    if (!h.vm[a]) return 3;
-    l[a] = v + w;
-    return byte_of(h.m[a], lidx<D>(l[0], l[1], l[2]));
-  }
-  if (!h.vp[a]) return 3;
-  l[a] = v - w;
-  return byte_of(h.p[a], lidx<D>(l[0], l[1], l[2]));
-}
-
-// codes of the 16 cells of the group at t0 (4 bits each)
-template <int D>
-__device__ __forceinline__ uint64_t group_codes(const Geo& g, const Dev& p, int lev, int64_t t0) {
+__device__ __forceinline__ uint64_t group_codes(const Geo& g, const Dev& p, int lev, int64_t t0, uint32_t* out) {
+  constexpr int W[3] = {gcodes::width<D>(0), gcodes::width<D>(1), gcodes::width<D>(2)};
   const int64_t nl = g.n[lev];
   const uint8_t* stl = p.st + g.off[lev];
-  GroupNbhd h;
-  // the group, its parents and its 2d face-adjacent groups are loaded
-  // together (one memory round trip), whether or not they are needed
-  h.c = *reinterpret_cast<const uint4*>(stl + t0);
+  const uint4 c = *reinterpret_cast<const uint4*>(stl + t0);
   const uint64_t par = lev > g.l0 ? ld_parents<D>(p.st + g.off[lev - 1], t0, g.B * nl) : 0ull;
   const int n = 1 << lev;
   const int64_t ib = g.off[lev] + (t0 >> (D * lev)) * nl;
   int x0[3];
   mdec<D>((uint64_t)(t0 & (nl - 1)), x0);
+  uint32_t m[3][4], q[3][4];
 #pragma unroll
   for (int a = 0; a < 3; a++) {
-    h.vm[a] = h.vp[a] = false;
-    h.m[a] = h.p[a] = make_uint4(0u, 0u, 0u, 0u);
-    if (a >= D) continue;
 #pragma unroll
     for (int s = 0; s < 2; s++) {
-      const int u = map_nb(x0[a] + (s ? gw<D>(a) : -gw<D>(a)), n, g.periodic[a]);
-      if (u < 0) continue;
-      int y[3] = {x0[0], x0[1], x0[2]};
-      y[a] = u;
-      const uint4 v = *reinterpret_cast<const uint4*>(p.st + ib + (int64_t)menc<D>(y));
-      if (s) { h.p[a] = v; h.vp[a] = true; } else { h.m[a] = v; h.vm[a] = true; }
-    }
-  }
-  bool par_leaf = false;
-#pragma unroll
-  for (int k = 0; k < (16 >> D); k++) par_leaf = par_leaf || ((par >> (8 * k)) & 0xff) == ST_LEAF;
-  const bool any_leaf = any16(h.c, 0x01010101u);
-  uint64_t codes = 0ull;
-  if (!any_leaf && !par_leaf) {
-#pragma unroll
-    for (int j = 0; j < 16; j++)
-      if (byte_of(h.c, j) == ST_INTERNAL) codes |= (uint64_t)CODE_INT << (4 * j);
-    return codes;
-  }
-  // virtual cells need a leaf of the level within two cells, interface
-  // leaves an internal face neighbour: both read the loaded neighbourhood
-  uint4 u = h.c;
-#pragma unroll
-  for (int a = 0; a < D; a++) {
-    u.x |= h.m[a].x | h.p[a].x; u.y |= h.m[a].y | h.p[a].y;
-    u.z |= h.m[a].z | h.p[a].z; u.w |= h.m[a].w | h.p[a].w;
-  }
-  const bool nb_leaf = any16(u, 0x01010101u), nb_int = lev < g.L && any16(u, 0x02020202u);
-  const int reach = stencil_reach(g);
-#pragma unroll
-  for (int j = 0; j < 16; j++) {
-    const uint8_t st = byte_of(h.c, j);
-    uint32_t c = 0u;
-    if (st == ST_INTERNAL) {
-      c = CODE_INT;
-    } else if (st == ST_LEAF) {
-      bool ref = false;
-      if (nb_int) {
-#pragma unroll
-        for (int a = 0; a < D; a++) {
-          ref = ref || nb_status<D>(h, j, a, -1) == ST_INTERNAL || nb_status<D>(h, j, a, 1) == ST_INTERNAL;
-          if (reach == 2)
-            ref = ref || nb_status<D>(h, j, a, -2) == ST_INTERNAL || nb_status<D>(h, j, a, 2) == ST_INTERNAL;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);  // outside the domain: no status
+      if (a < D) {
+        const int u = map_nb(x0[a] + (s ? W[a] : -W[a]), n, g.periodic[a]);
+        if (u >= 0) {
+          int y[3] = {x0[0], x0[1], x0[2]};
+          y[a] = u;
+          v = *reinterpret_cast<const uint4*>(p.st + ib + (int64_t)menc<D>(y));
         }
       }
-      c = ref ? (CODE_LEAF | CODE_IFACE) : CODE_LEAF;
-    } else if (nb_leaf && ((par >> (8 * (j >> D))) & 0xff) == ST_LEAF) {
-      bool rd = false;
-#pragma unroll
-      for (int a = 0; a < D; a++)
-#pragma unroll
-        for (int o = -2; o <= 2; o++)
-          if (o != 0) rd = rd || nb_status<D>(h, j, a, o) == ST_LEAF;
-      c = rd ? CODE_GHOST : 0u;
+      uint32_t* w = s ? q[a] : m[a];
+      w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
     }
-    codes |= (uint64_t)c << (4 * j);
   }
-  return codes;
+  const uint32_t cw[4] = {c.x, c.y, c.z, c.w};
+  return gcodes::codes16<D>(cw, m, q, par, stencil_reach(g), out);
 }
 
 // per-lane cell range of block b: [t0, t0 + cpt)
@@ -1878,21 +1792,16 @@ __device__ __forceinline__ bool comp_skip(const Geo& g, const Dev& p, const Comp
   return !leaf;
 }
 
-// packed counts of the lane's cells; *codes gets 4 bits per cell
+// packed counts of the lane's cells; out[] gets their code bytes (16 for a
+// group, else the one cell's in out[0])
 template <int D>
-__device__ __forceinline__ uint64_t lane_counts(const Geo& g, const Dev& p, const CompRange& r, bool skip,
-                                                uint64_t* codes) {
-  uint64_t c = 0ull, cd = 0ull;
-  if (r.act && !skip) {
-    if (r.cpt == GRP) {
-      cd = group_codes<D>(g, p, r.lev, r.t0);
-    } else {
-      for (int j = 0; j < r.cpt; j++) cd |= (uint64_t)cell_code<D>(g, p, r.lev, r.t0 + j) << (4 * j);
-    }
-    for (int j = 0; j < r.cpt; j++) c += code_count((uint32_t)(cd >> (4 * j)) & 15u);
-  }
-  *codes = cd;
-  return c;
+__device__ __forceinline__ uint64_t lane_counts(const Geo& g, const Dev& p, const CompRange& r, uint32_t* out) {
+  out[0] = out[1] = out[2] = out[3] = 0u;
+  if (!r.act) return 0ull;
+  if (r.cpt == GRP) return group_codes<D>(g, p, r.lev, r.t0, out);
+  const uint32_t cd = cell_code<D>(g, p, r.lev, r.t0);
+  out[0] = cd;
+  return code_count(cd);
 }
 
 // a level with no cell after this remesh's apply pass lists nothing (not in
@@ -1915,22 +1824,14 @@ __global__ __launch_bounds__(TPB) void k_comp_count(Geo g, Dev p, int lo, int fu
       if (threadIdx.x < NCL) p.bcnt[clist(threadIdx.x) * nbt + b] = 0;
       continue;
     }
-    uint64_t codes, tot;
-    block_exscan<uint64_t>(lane_counts<D>(g, p, r, false, &codes), sh, &tot);
+    uint32_t cb[4];
+    uint64_t tot;
+    block_exscan<uint64_t>(lane_counts<D>(g, p, r, cb), sh, &tot);
     // the codes, one byte per cell, for the write pass
     if (r.act) {
       uint8_t* cc = p.ccode + g.off[r.lev] + r.t0;
-      if (r.cpt == GRP) {
-        uint32_t w[4];
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-          const uint32_t h = (uint32_t)(codes >> (16 * q));
-          w[q] = (h & 15u) | (((h >> 4) & 15u) << 8) | (((h >> 8) & 15u) << 16) | (((h >> 12) & 15u) << 24);
-        }
-        *reinterpret_cast<uint4*>(cc) = make_uint4(w[0], w[1], w[2], w[3]);
-      } else {
-        for (int j = 0; j < r.cpt; j++) cc[j] = (uint8_t)((codes >> (4 * j)) & 15u);
-      }
+      if (r.cpt == GRP) *reinterpret_cast<uint4*>(cc) = make_uint4(cb[0], cb[1], cb[2], cb[3]);
+      else cc[0] = (uint8_t)cb[0];
     }
     if (threadIdx.x == 0) {
       const int64_t nsbt = g.sb_first[g.L + 1];

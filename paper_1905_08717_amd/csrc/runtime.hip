@@ -657,7 +657,9 @@ mr_status mr_set_launch(mr_ctx* c, const mr_launch* l) {
   if (l->list_grid) c->g.list_grid = l->list_grid;
   if (l->iface_grid) c->g.iface_grid = l->iface_grid;
   if (l->comp_grid) c->g.comp_grid = l->comp_grid;
-  // the captured macro step holds the old grids
+  // the captured macro step holds the old grids (destroyed once no replay
+  // of it is in flight)
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   c->graph_exec = nullptr;
