@@ -812,9 +812,14 @@ __device__ __forceinline__ void refined_flux(const Geo& g, const Dev& p, int lev
 // refined face neighbour, evaluated on the finer level, or an internal cell
 // at distance 2 read through its projected value); they run level by level
 // inside the stage sweeps.  The two sets are disjoint and every leaf writes
-// only its own values and flux-register entries.
+// only its own values and flux-register entries.  At the last stage, bulk
+// leaves of levels >= lq0 (levels whose step both runs and ends in this
+// fine iteration: the finest level under local time stepping, every level
+// with one global step) also store their end value as q^n of the next
+// step: no kernel reads a leaf's q^n after its last stage, and a bulk leaf
+// has no refined face to correct.
 template <int D, int PDE, bool IFACE>
-__global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int stage) {
+__global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int stage, int lq0) {
   constexpr int M = NC<D, PDE>::M;
   constexpr double C_1_6 = 1.0 / 6.0, C_2_3 = 2.0 / 3.0, C_1_3 = 1.0 / 3.0;
   constexpr int LS = IFACE ? LS_IFACE : LS_LEAF;
@@ -1028,6 +1033,7 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
             const double q1 = qsv[k];
             const double qe = ((0.5 * q0) + (0.5 * q1)) + ((0.5 * h) * r);
             p.q[SL_QE][I] = qe;
+            if (!IFACE && lev >= lq0) p.q[SL_Q0][I] = qe;
             p.q[SL_X2][I] = q1 + (h * r);
             if (nerk) p.q[SL_QH][I] = p.q[SL_QH][I] + ((0.125 * h) * r);
             if (!isfinite(qe)) atomicOr(&p.cnt[inst * CNT_PER_INST + CNT_NONFINITE], 1ull);
@@ -1053,6 +1059,7 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
           const double qh = qsv[k];
           const double qe = ((C_1_3 * q0) + (C_2_3 * qh)) + ((C_2_3 * h) * r);
           p.q[SL_QE][I] = qe;
+          if (!IFACE && lev >= lq0) p.q[SL_Q0][I] = qe;
           if (!isfinite(qe)) atomicOr(&p.cnt[inst * CNT_PER_INST + CNT_NONFINITE], 1ull);
         }
       }
@@ -1061,9 +1068,9 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
 }
 
 template <int D, int PDE>
-static void stage_dp(const Geo& g, const Dev& p, int lo, int hi, int stage, int part, hipStream_t s) {
+static void stage_dp(const Geo& g, const Dev& p, int lo, int hi, int stage, int part, int lq0, hipStream_t s) {
   if (part == 0) {
-    k_stage<D, PDE, false><<<list_blocks(g, g.B * g.n[hi]), TPB, 0, s>>>(g, p, lo, hi, stage);
+    k_stage<D, PDE, false><<<list_blocks(g, g.B * g.n[hi]), TPB, 0, s>>>(g, p, lo, hi, stage, lq0);
     return;
   }
   const int hif = hi < g.L ? hi : g.L - 1;
@@ -1071,46 +1078,50 @@ static void stage_dp(const Geo& g, const Dev& p, int lo, int hi, int stage, int 
   // interface leaves lie along refinement boundaries: a small fraction
   int nb = blocks_for(g.B * g.n[hif]);
   if (nb > g.iface_grid) nb = g.iface_grid;
-  k_stage<D, PDE, true><<<nb, TPB, 0, s>>>(g, p, lo, hif, stage);
+  k_stage<D, PDE, true><<<nb, TPB, 0, s>>>(g, p, lo, hif, stage, MRD_MAXLEV + 1);
 }
 
 template <int D>
-static void stage_d(const Geo& g, const Dev& p, int lo, int hi, int stage, int part, hipStream_t s) {
+static void stage_d(const Geo& g, const Dev& p, int lo, int hi, int stage, int part, int lq0, hipStream_t s) {
   switch (g.pde) {
-    case PDE_ADVECTION: stage_dp<D, PDE_ADVECTION>(g, p, lo, hi, stage, part, s); break;
-    case PDE_BURGERS: stage_dp<D, PDE_BURGERS>(g, p, lo, hi, stage, part, s); break;
-    case PDE_NAGUMO: stage_dp<D, PDE_NAGUMO>(g, p, lo, hi, stage, part, s); break;
-    case PDE_EULER: stage_dp<D, PDE_EULER>(g, p, lo, hi, stage, part, s); break;
-    case PDE_FLAME: stage_dp<D, PDE_FLAME>(g, p, lo, hi, stage, part, s); break;
-    case PDE_FLAMEBALL: stage_dp<D, PDE_FLAMEBALL>(g, p, lo, hi, stage, part, s); break;
-    default: stage_dp<D, PDE_LINEAR>(g, p, lo, hi, stage, part, s); break;
+    case PDE_ADVECTION: stage_dp<D, PDE_ADVECTION>(g, p, lo, hi, stage, part, lq0, s); break;
+    case PDE_BURGERS: stage_dp<D, PDE_BURGERS>(g, p, lo, hi, stage, part, lq0, s); break;
+    case PDE_NAGUMO: stage_dp<D, PDE_NAGUMO>(g, p, lo, hi, stage, part, lq0, s); break;
+    case PDE_EULER: stage_dp<D, PDE_EULER>(g, p, lo, hi, stage, part, lq0, s); break;
+    case PDE_FLAME: stage_dp<D, PDE_FLAME>(g, p, lo, hi, stage, part, lq0, s); break;
+    case PDE_FLAMEBALL: stage_dp<D, PDE_FLAMEBALL>(g, p, lo, hi, stage, part, lq0, s); break;
+    default: stage_dp<D, PDE_LINEAR>(g, p, lo, hi, stage, part, lq0, s); break;
   }
 }
 
-void launch_stage(const Geo& g, const Dev& p, int lo, int hi, int stage, int part, hipStream_t s) {
+void launch_stage(const Geo& g, const Dev& p, int lo, int hi, int stage, int part, hipStream_t s, int lq0) {
   if (lo > hi) return;
-  if (g.d == 1) stage_d<1>(g, p, lo, hi, stage, part, s);
-  else if (g.d == 2) stage_d<2>(g, p, lo, hi, stage, part, s);
-  else stage_d<3>(g, p, lo, hi, stage, part, s);
+  if (g.d == 1) stage_d<1>(g, p, lo, hi, stage, part, lq0, s);
+  else if (g.d == 2) stage_d<2>(g, p, lo, hi, stage, part, lq0, s);
+  else stage_d<3>(g, p, lo, hi, stage, part, lq0, s);
 }
 
 // ---------------------------------------------------------------------------
 // end of the steps of a level: q^n <- stage-3 value, then on every refined
 // face the conservative correction sigma (A_c - A_f) / dx (faces x-, x+,
-// y-, y+, z-, z+), registers cleared after use
+// y-, y+, z-, z+), registers cleared after use.  Levels lo..min(hi, L-1):
+// the finest level's leaves stored q^n in their last stage (they have no
+// refined face); list: LS_LEAF, or LS_IFACE when every bulk leaf of these
+// levels did so too (one global step: only interface leaves have refined
+// faces).
 
 template <int D>
-__global__ __launch_bounds__(TPB) void k_finalize(Geo g, Dev p, int lo, int hi) {
+__global__ __launch_bounds__(TPB) void k_finalize(Geo g, Dev p, int lo, int hi, int list) {
   const double sc = D == 1 ? 1.0 : (D == 2 ? 0.5 : 0.25);
   __shared__ int s_cnt[MRD_MAXLEV + 1];
-  const int64_t ntot = flat_setup(p, LS_LEAF, lo, hi, s_cnt);
+  const int64_t ntot = flat_setup(p, list, lo, hi, s_cnt);
   GSL(i, ntot) {
     {
       int64_t kk = i;
       const int lev = flat_level(s_cnt, lo, kk);
       const int64_t nl = g.n[lev];
       const int n = 1 << lev;
-      const int64_t t = p.lst[LS_LEAF][g.off[lev] + kk];
+      const int64_t t = p.lst[list][g.off[lev] + kk];
       const int64_t G = g.off[lev] + t;
       double q[5];
       for (int k = 0; k < g.m; k++) q[k] = p.q[SL_QE][(int64_t)k * g.Ntot + G];
@@ -1147,13 +1158,15 @@ __global__ __launch_bounds__(TPB) void k_finalize(Geo g, Dev p, int lo, int hi) 
   }
 }
 
-void launch_finalize(const Geo& g, const Dev& p, int lo, int hi, hipStream_t s) {
+void launch_finalize(const Geo& g, const Dev& p, int lo, int hi, bool iface_only, hipStream_t s) {
+  if (hi > g.L - 1) hi = g.L - 1;  // the finest level is done
   if (lo > hi) return;
+  const int list = iface_only ? LS_IFACE : LS_LEAF;
   const int64_t n = g.B * g.n[hi];
   const int nb = list_blocks(g, n);
-  if (g.d == 1) k_finalize<1><<<nb, TPB, 0, s>>>(g, p, lo, hi);
-  else if (g.d == 2) k_finalize<2><<<nb, TPB, 0, s>>>(g, p, lo, hi);
-  else k_finalize<3><<<nb, TPB, 0, s>>>(g, p, lo, hi);
+  if (g.d == 1) k_finalize<1><<<nb, TPB, 0, s>>>(g, p, lo, hi, list);
+  else if (g.d == 2) k_finalize<2><<<nb, TPB, 0, s>>>(g, p, lo, hi, list);
+  else k_finalize<3><<<nb, TPB, 0, s>>>(g, p, lo, hi, list);
 }
 
 __global__ void k_zero(double* a, int64_t n) { GSL(t, n) a[t] = 0.0; }

@@ -118,8 +118,13 @@ void launch_ghost(const Geo& g, const Dev& p, int lo, int hi, int cb_lev, int st
 // stage kernel over the leaves of levels lo..hi: part 0 the leaves whose
 // stencil reaches no internal cell (stage 1 also adds the leaf-updates of
 // these levels to the counters), part 1 the interface leaves
-void launch_stage(const Geo& g, const Dev& p, int lo, int hi, int stage, int part, hipStream_t s);
-void launch_finalize(const Geo& g, const Dev& p, int lo, int hi, hipStream_t s);
+// part 0: bulk leaves of levels lo..hi (levels >= lq0 also store q^n at
+// the last stage); part 1: interface leaves
+void launch_stage(const Geo& g, const Dev& p, int lo, int hi, int stage, int part, hipStream_t s,
+                  int lq0 = MRD_MAXLEV + 1);
+// end of step of the leaves of levels lo..min(hi, L-1) (all leaves, or the
+// interface leaves only)
+void launch_finalize(const Geo& g, const Dev& p, int lo, int hi, bool iface_only, hipStream_t s);
 // remesh byte table cleared on levels lo..hi
 void launch_remesh_clear(const Geo& g, const Dev& p, int lo, int hi, hipStream_t s);
 // level flags before the apply passes of a remesh at la

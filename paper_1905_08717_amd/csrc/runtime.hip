@@ -141,13 +141,14 @@ void ghost_fill(mr_ctx* c, int lmin, int stage) {
 // one step of the MR scheme with a global time step (the paper's
 // comparison method): every level advances by dt at the same stage times
 // RK stage st on the leaves of levels lo..hi: the bulk launch (timed under
-// MR_KC_STAGE_BULK too) and, unless bulk_only, the interface launch
-void stage_launch(mr_ctx* c, int lo, int hi, int st, bool bulk, bool iface) {
+// MR_KC_STAGE_BULK too; at the last stage its leaves of levels >= lq0 also
+// store q^n of their next step) and the interface launch
+void stage_launch(mr_ctx* c, int lo, int hi, int st, bool bulk, bool iface, int lq0 = MRD_MAXLEV + 1) {
   const Geo& g = c->g;
   hipStream_t s = c->stream;
   const int cls = lo == g.L ? MR_KC_STAGE_FINEST : MR_KC_STAGE;
   if (bulk)
-    timed(c, cls, [&] { timed(c, MR_KC_STAGE_BULK, [&] { launch_stage(g, c->p, lo, hi, st, 0, s); }); });
+    timed(c, cls, [&] { timed(c, MR_KC_STAGE_BULK, [&] { launch_stage(g, c->p, lo, hi, st, 0, s, lq0); }); });
   if (iface && lo <= g.L - 1)
     timed(c, cls, [&] { launch_stage(g, c->p, lo, hi < g.L ? hi : g.L - 1, st, 1, s); });
 }
@@ -156,7 +157,7 @@ void mr_iteration(mr_ctx* c) {
   const Geo& g = c->g;
   const int L = g.L;
   hipStream_t s = c->stream;
-  auto stage = [&](int st) { stage_launch(c, g.l0, L, st, true, true); };
+  auto stage = [&](int st) { stage_launch(c, g.l0, L, st, true, true, st == g.rk ? g.l0 : MRD_MAXLEV + 1); };
   project_range(c, L - 1, g.l0, PJ_Q0);
   if (c->s.remesh && g.l0 <= L - 1) {
     remesh(c, g.l0);
@@ -172,7 +173,7 @@ void mr_iteration(mr_ctx* c) {
     ghost_fill(c, g.l0, 3);
     stage(3);
   }
-  timed(c, MR_KC_FINALIZE, [&] { launch_finalize(g, c->p, g.l0, L, s); });
+  timed(c, MR_KC_FINALIZE, [&] { launch_finalize(g, c->p, g.l0, L, true, s); });
 }
 
 // one iteration of Alg. alg-LTS
@@ -184,6 +185,9 @@ void lt_iteration(mr_ctx* c, int64_t n, int64_t N) {
     return;
   }
   const int lmin = lmin_of(g, n);
+  // the steps of levels >= lnext end with this iteration (the next one
+  // starts there); of those, only the finest level's step also ran in it
+  const int lnext = (n + 1 == N) ? g.l0 : lmin_of(g, n + 1);
   project_range(c, L - 1, lmin, PJ_Q0);
   if (c->s.remesh && lmin <= L - 1) {
     remesh(c, lmin);
@@ -198,26 +202,24 @@ void lt_iteration(mr_ctx* c, int64_t n, int64_t N) {
   // stage-2 sweep L -> lmin: the bulk leaves of every level read only their
   // own level, so they go first in one launch; the interface leaves of a
   // level need the finer level's stage-2 values and its projection
-  stage_launch(c, lmin, L, 2, true, false);
+  stage_launch(c, lmin, L, 2, true, false, g.rk == 2 ? L : MRD_MAXLEV + 1);
   for (int lev = L - 1; lev >= lmin; lev--) {
     project_range(c, lev, lev, PJ_RK2);
     stage_launch(c, lev, lev, 2, false, true);
   }
   if (g.rk == 2) {
     // RK2: the step ends after the second stage
-    const int lnext2 = (n + 1 == N) ? g.l0 : lmin_of(g, n + 1);
-    timed(c, MR_KC_FINALIZE, [&] { launch_finalize(g, c->p, lnext2, L, s); });
+    timed(c, MR_KC_FINALIZE, [&] { launch_finalize(g, c->p, lnext, L, false, s); });
     return;
   }
   project_range(c, L - 1, lmin, PJ_REF3);
   ghost_fill(c, lmin, 3);
-  stage_launch(c, lmin, L, 3, true, false);
+  stage_launch(c, lmin, L, 3, true, false, L);
   for (int lev = L - 1; lev >= lmin; lev--) {
     project_range(c, lev, lev, PJ_RK3);
     stage_launch(c, lev, lev, 3, false, true);
   }
-  const int lnext = (n + 1 == N) ? g.l0 : lmin_of(g, n + 1);
-  timed(c, MR_KC_FINALIZE, [&] { launch_finalize(g, c->p, lnext, L, s); });
+  timed(c, MR_KC_FINALIZE, [&] { launch_finalize(g, c->p, lnext, L, false, s); });
 }
 
 mr_status read_counters(mr_ctx* c) {
