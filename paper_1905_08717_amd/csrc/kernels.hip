@@ -1579,6 +1579,43 @@ __global__ __launch_bounds__(TPB) void k_apply(Geo g, Dev p, int lev, int la) {
       if (any16(so, 0xffffffffu) || par_int) {
         const uint4 wv = lev <= g.L - 1 ? ldg<G>(p.rf + g.off[lev], t0, N) : make_uint4(0u, 0u, 0u, 0u);
         uint64_t nlo = 0ull, nhi = 0ull;  // new statuses of cells 0-7, 8-15
+        if (G == 16 && t0 + 16 <= N) {
+          // four cells per 32-bit word (statuses 0, 1, 2 and the W bit add
+          // without carries): existing / created cells are 1, plus 1 where W
+          const bool keep = inst_of_window_skip(g, t0, D * lev);  // the group is one instance
+          const uint32_t ow[4] = {so.x, so.y, so.z, so.w}, ww[4] = {wv.x, wv.y, wv.z, wv.w};
+          uint32_t nv[4], clr = 0u;
+#pragma unroll
+          for (int q = 0; q < 4; q++) {
+            const uint32_t o = ow[q], onz = (o | (o >> 1)) & 0x01010101u;
+            uint32_t base;
+            if (lev == la) {
+              base = onz;
+            } else {
+              // children 4q..4q+3 of parents (4q) >> D .. (4q + 3) >> D
+              const uint32_t pa = (uint32_t)(par >> (8 * ((4 * q) >> D))) & 0xffu;
+              if (D == 1) {
+                const uint32_t pb = (uint32_t)(par >> (8 * (2 * q + 1))) & 0xffu;
+                base = (pa == ST_INTERNAL ? 0x00000101u : 0u) | (pb == ST_INTERNAL ? 0x01010000u : 0u);
+              } else {
+                base = pa == ST_INTERNAL ? 0x01010101u : 0u;
+              }
+            }
+            const uint32_t nw = keep ? o : base + (base & (ww[q] >> 1) & 0x01010101u);
+            nv[q] = nw;
+            const uint32_t nnz = (nw | (nw >> 1)) & 0x01010101u;
+            if (lev > la) mask |= gcodes::word_bits<1>(nnz & ~onz) << (4 * q);
+            clr |= gcodes::word_bits<1>((nw >> 1) & ~(o >> 1) & 0x01010101u) << (4 * q);
+          }
+          // a node that turns internal has no significance of its own yet
+          while (clr) {
+            const int j = __builtin_ctz(clr);
+            clr &= clr - 1u;
+            p.sigt[g.off[lev] + t0 + j] = 0;
+          }
+          nlo = (uint64_t)nv[0] | ((uint64_t)nv[1] << 32);
+          nhi = (uint64_t)nv[2] | ((uint64_t)nv[3] << 32);
+        } else {
 #pragma unroll
         for (int j = 0; j < G; j++) {
           const int64_t t = t0 + j;
@@ -1598,6 +1635,7 @@ __global__ __launch_bounds__(TPB) void k_apply(Geo g, Dev p, int lev, int la) {
           }
           if (j < 8) nlo |= (uint64_t)nw << (8 * j);
           else nhi |= (uint64_t)nw << (8 * (j - 8));
+        }
         }
         if (G == 1) {
           stl[t0] = (uint8_t)nlo;
@@ -1941,6 +1979,7 @@ template <int D>
 __global__ __launch_bounds__(TPB) void k_comp_write(Geo g, Dev p, int lo, int full) {
   __shared__ uint64_t sh[TPB / 64];
   __shared__ int4 s_pre;
+  __shared__ int s_ent[TPB * GRP];  // one list's entries of the block, in order
   const int64_t nbt = g.comp_first[g.L + 1];
   for (int64_t b = g.comp_first[lo] + blockIdx.x; b < nbt; b += gridDim.x) {
     const CompRange r = comp_range(g, lo, b);
@@ -1953,21 +1992,25 @@ __global__ __launch_bounds__(TPB) void k_comp_write(Geo g, Dev p, int lo, int fu
       if (threadIdx.x == 0 && wide_level(g, r.lev)) p.bsum[g.bs_off[r.lev] + (r.tb >> BS_SHIFT)] = 0;
       continue;
     }
-    uint64_t codes = 0ull, c = 0ull, tot;
+    // the lane's cells of each list as a mask (bit j: cell t0 + j)
+    uint32_t mk[NCL] = {0u, 0u, 0u, 0u};
     if (r.act) {
       const uint8_t* cc = p.ccode + g.off[r.lev] + r.t0;
       if (r.cpt == GRP) {
         const uint4 v = *reinterpret_cast<const uint4*>(cc);
         const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-        for (int q = 0; q < 4; q++)
+        for (int k = 0; k < NCL; k++)
 #pragma unroll
-          for (int i = 0; i < 4; i++) codes |= (uint64_t)((w[q] >> (8 * i)) & 15u) << (4 * (4 * q + i));
+          for (int q = 0; q < 4; q++) mk[k] |= gcodes::word_bits<1>((w[q] >> k) & 0x01010101u) << (4 * q);
       } else {
-        for (int j = 0; j < r.cpt; j++) codes |= (uint64_t)(cc[j] & 15u) << (4 * j);
+#pragma unroll
+        for (int k = 0; k < NCL; k++) mk[k] = ((uint32_t)cc[0] >> k) & 1u;
       }
-      for (int j = 0; j < r.cpt; j++) c += code_count((uint32_t)(codes >> (4 * j)) & 15u);
     }
+    uint64_t c = 0ull, tot;
+#pragma unroll
+    for (int k = 0; k < NCL; k++) c |= (uint64_t)__popc(mk[k]) << (16 * k);
     const uint64_t ex = block_exscan<uint64_t>(c, sh, &tot);
     // list offsets of the block: its superblock's plus the counts of the
     // preceding blocks of the superblock (fewer than 64: wave 0 sums them)
@@ -2006,16 +2049,26 @@ __global__ __launch_bounds__(TPB) void k_comp_write(Geo g, Dev p, int lo, int fu
       if ((tot >> 16) & 0xffffull) bits |= BS_EXIST | BS_INT;
       p.bsum[g.bs_off[r.lev] + (r.tb >> BS_SHIFT)] = (uint8_t)bits;
     }
-    if (c == 0ull) continue;  // no barrier follows in this step
-    int base[NCL] = {pre.x, pre.y, pre.z, pre.w};
-#pragma unroll
-    for (int k = 0; k < NCL; k++) base[k] += (int)((ex >> (16 * k)) & 0xffffull);
+    // each list's entries of the block are one contiguous range of the
+    // list: staged in order in shared memory, then stored with consecutive
+    // lanes on consecutive entries
+    const int base[NCL] = {pre.x, pre.y, pre.z, pre.w};
     const int64_t o = g.off[r.lev];
-    for (int j = 0; j < r.cpt; j++) {
-      const uint32_t e = (uint32_t)(codes >> (4 * j)) & 15u;
 #pragma unroll
-      for (int k = 0; k < NCL; k++)
-        if ((e >> k) & 1u) p.lst[clist(k)][o + base[k]++] = (int)(r.t0 + j);
+    for (int k = 0; k < NCL; k++) {
+      const int tk = (int)((tot >> (16 * k)) & 0xffffull);
+      if (tk == 0) continue;  // the same in every lane
+      int pos = (int)((ex >> (16 * k)) & 0xffffull);
+      uint32_t m = mk[k];
+      while (m) {
+        const int j = __builtin_ctz(m);
+        m &= m - 1u;
+        s_ent[pos++] = (int)(r.t0 + j);
+      }
+      __syncthreads();
+      int* dst = p.lst[clist(k)] + o + base[k];
+      for (int i = threadIdx.x; i < tk; i += TPB) dst[i] = s_ent[i];
+      __syncthreads();
     }
   }
 }
