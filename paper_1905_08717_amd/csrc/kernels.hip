@@ -603,18 +603,27 @@ __device__ __forceinline__ int flat_level(const int* s_cnt, int lo, int64_t& k) 
   return lo + j;
 }
 
-__global__ __launch_bounds__(TPB) void k_project(Geo g, Dev p, int lev, int mode) {
+// the mode is a template argument, so each mode loads only what it uses;
+// the next list entry is fetched while a node is processed
+template <int mode>
+__global__ __launch_bounds__(TPB) void k_project(Geo g, Dev p, int lev) {
   const int nch = 1 << g.d;
   const double sc = g.d == 1 ? 0.5 : (g.d == 2 ? 0.25 : 0.125);
   const int64_t NT = g.Ntot;
   const int n = list_len(p, LS_INTERNAL, lev);
   const int* lst = p.lst[LS_INTERNAL] + g.off[lev];
-  GSL(i, n) {
-    const int64_t t = lst[i];
+  constexpr bool NEED_ST = mode == PJ_REF2 || mode == PJ_RK2;
+  const int step = (int)(gridDim.x * blockDim.x);
+  int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  int t_next = i < n ? lst[i] : 0;
+  for (; i < n; i += step) {
+    const int64_t t = t_next;
+    if (i + step < n) t_next = lst[i + step];
     const int64_t G = g.off[lev] + t;
     const int64_t C0 = g.off[lev + 1] + (t << g.d);
     uint8_t cs[8];
-    for (int cb = 0; cb < nch; cb++) cs[cb] = p.st[C0 + cb];
+    if (NEED_ST)
+      for (int cb = 0; cb < nch; cb++) cs[cb] = p.st[C0 + cb];
     for (int k = 0; k < g.m; k++) {
       const int64_t kk = (int64_t)k * NT;
       double s = 0.0;
@@ -660,7 +669,17 @@ __global__ __launch_bounds__(TPB) void k_project(Geo g, Dev p, int lev, int mode
 
 void launch_project(const Geo& g, const Dev& p, int lev, int mode, hipStream_t s) {
   const int64_t n = g.B * g.n[lev];
-  k_project<<<list_blocks(g, n), TPB, 0, s>>>(g, p, lev, mode);
+  const int nb = list_blocks(g, n);
+  switch (mode) {
+    case PJ_Q0: k_project<PJ_Q0><<<nb, TPB, 0, s>>>(g, p, lev); break;
+    case PJ_CASEB: k_project<PJ_CASEB><<<nb, TPB, 0, s>>>(g, p, lev); break;
+    case PJ_REF2: k_project<PJ_REF2><<<nb, TPB, 0, s>>>(g, p, lev); break;
+    case PJ_RK2: k_project<PJ_RK2><<<nb, TPB, 0, s>>>(g, p, lev); break;
+    case PJ_REF3: k_project<PJ_REF3><<<nb, TPB, 0, s>>>(g, p, lev); break;
+    case PJ_RK3: k_project<PJ_RK3><<<nb, TPB, 0, s>>>(g, p, lev); break;
+    case PJ_ST2: k_project<PJ_ST2><<<nb, TPB, 0, s>>>(g, p, lev); break;
+    default: k_project<PJ_ST3><<<nb, TPB, 0, s>>>(g, p, lev); break;
+  }
 }
 
 // ---------------------------------------------------------------------------
