@@ -1125,12 +1125,13 @@ void launch_stage(const Geo& g, const Dev& p, int lo, int hi, int stage, int par
 // face the conservative correction sigma (A_c - A_f) / dx (faces x-, x+,
 // y-, y+, z-, z+), registers cleared after use.  Levels lo..min(hi, L-1):
 // the finest level's leaves stored q^n in their last stage (they have no
-// refined face); list: LS_LEAF, or LS_IFACE when every bulk leaf of these
-// levels did so too (one global step: only interface leaves have refined
-// faces).
+// refined face).  Only interface leaves have refined faces: a plain copy
+// over all leaves (list LS_LEAF, reflux 0), then the corrected values of
+// the interface leaves (LS_IFACE, reflux 1) over it; with one global step
+// every bulk leaf stored q^n itself and only the second pass runs.
 
 template <int D>
-__global__ __launch_bounds__(TPB) void k_finalize(Geo g, Dev p, int lo, int hi, int list) {
+__global__ __launch_bounds__(TPB) void k_finalize(Geo g, Dev p, int lo, int hi, int list, int reflux) {
   const double sc = D == 1 ? 1.0 : (D == 2 ? 0.5 : 0.25);
   __shared__ int s_cnt[MRD_MAXLEV + 1];
   const int64_t ntot = flat_setup(p, list, lo, hi, s_cnt);
@@ -1144,7 +1145,7 @@ __global__ __launch_bounds__(TPB) void k_finalize(Geo g, Dev p, int lo, int hi, 
       const int64_t G = g.off[lev] + t;
       double q[5];
       for (int k = 0; k < g.m; k++) q[k] = p.q[SL_QE][(int64_t)k * g.Ntot + G];
-      if (g.reflux && lev < g.L) {
+      if (reflux && g.reflux && lev < g.L) {
         const int64_t inst = t >> (D * lev);
         const int64_t ib = g.off[lev] + inst * nl;
         int x[3];
@@ -1180,12 +1181,15 @@ __global__ __launch_bounds__(TPB) void k_finalize(Geo g, Dev p, int lo, int hi, 
 void launch_finalize(const Geo& g, const Dev& p, int lo, int hi, bool iface_only, hipStream_t s) {
   if (hi > g.L - 1) hi = g.L - 1;  // the finest level is done
   if (lo > hi) return;
-  const int list = iface_only ? LS_IFACE : LS_LEAF;
   const int64_t n = g.B * g.n[hi];
   const int nb = list_blocks(g, n);
-  if (g.d == 1) k_finalize<1><<<nb, TPB, 0, s>>>(g, p, lo, hi, list);
-  else if (g.d == 2) k_finalize<2><<<nb, TPB, 0, s>>>(g, p, lo, hi, list);
-  else k_finalize<3><<<nb, TPB, 0, s>>>(g, p, lo, hi, list);
+  for (int pass = iface_only ? 1 : 0; pass < 2; pass++) {
+    const int list = pass ? LS_IFACE : LS_LEAF;
+    const int nbp = pass ? (nb < g.iface_grid ? nb : g.iface_grid) : nb;
+    if (g.d == 1) k_finalize<1><<<nbp, TPB, 0, s>>>(g, p, lo, hi, list, pass);
+    else if (g.d == 2) k_finalize<2><<<nbp, TPB, 0, s>>>(g, p, lo, hi, list, pass);
+    else k_finalize<3><<<nbp, TPB, 0, s>>>(g, p, lo, hi, list, pass);
+  }
 }
 
 __global__ void k_zero(double* a, int64_t n) { GSL(t, n) a[t] = 0.0; }
