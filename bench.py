@@ -113,7 +113,7 @@ def traffic_record(args):
     cw = col(os.path.join(d, "pmc_cwrite", "cwrite_counter_collection.csv"), "copyBuffer")
     gib_kib = float(1 << 20)
     sf, sw = gib_kib / max(cf), gib_kib / max(cw)
-    kern = "k_stage<2, 2, false>"
+    kern = "k_stage<2, 2, false, "  # the three stage instantiations
     from paper_1905_08717_amd import workloads as W
     n = 3 * W.macro_iters(W.nagumo_2d()) * args.steps  # one bulk launch per stage and iteration
     f = col(os.path.join(d, "pmc_fetch", "fetch_counter_collection.csv"), kern)[-n:]
@@ -398,7 +398,7 @@ def main():
     achieved = alg_bytes / (ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": 8000.0, "unit": "GB/s",
                 "frac": round(achieved / 8000.0, 5), "traffic": stage_traffic(B, s.get_launch()["list_grid"]),
-                "kernel": "k_stage<2, 2, false> (bulk RK stage kernel, all levels of a stage)",
+                "kernel": "k_stage<2, 2, false, 1|2|3> (bulk RK stage kernel, all levels of a stage)",
                 "launches": launches, "avg_launch_us": round(ms * 1e3 / max(launches, 1), 3),
                 "alg_bytes_per_launch": round(alg_bytes / max(launches, 1), 1),
                 "leaf_stage_updates": [int(x) for x in items],

@@ -837,8 +837,8 @@ __device__ __forceinline__ void refined_flux(const Geo& g, const Dev& p, int lev
 // with one global step) also store their end value as q^n of the next
 // step: no kernel reads a leaf's q^n after its last stage, and a bulk leaf
 // has no refined face to correct.
-template <int D, int PDE, bool IFACE>
-__global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int stage, int lq0) {
+template <int D, int PDE, bool IFACE, int stage>
+__global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int lq0) {
   constexpr int M = NC<D, PDE>::M;
   constexpr double C_1_6 = 1.0 / 6.0, C_2_3 = 2.0 / 3.0, C_1_3 = 1.0 / 3.0;
   constexpr int LS = IFACE ? LS_IFACE : LS_LEAF;
@@ -1086,10 +1086,19 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
   }
 }
 
+// the stage is a template argument: the stage arrays a leaf reads and
+// writes are known at compile time (its own value is loaded once)
+template <int D, int PDE, bool IFACE>
+static void stage_launch_st(int stage, int nb, const Geo& g, const Dev& p, int lo, int hi, int lq0, hipStream_t s) {
+  if (stage == 1) k_stage<D, PDE, IFACE, 1><<<nb, TPB, 0, s>>>(g, p, lo, hi, lq0);
+  else if (stage == 2) k_stage<D, PDE, IFACE, 2><<<nb, TPB, 0, s>>>(g, p, lo, hi, lq0);
+  else k_stage<D, PDE, IFACE, 3><<<nb, TPB, 0, s>>>(g, p, lo, hi, lq0);
+}
+
 template <int D, int PDE>
 static void stage_dp(const Geo& g, const Dev& p, int lo, int hi, int stage, int part, int lq0, hipStream_t s) {
   if (part == 0) {
-    k_stage<D, PDE, false><<<list_blocks(g, g.B * g.n[hi]), TPB, 0, s>>>(g, p, lo, hi, stage, lq0);
+    stage_launch_st<D, PDE, false>(stage, list_blocks(g, g.B * g.n[hi]), g, p, lo, hi, lq0, s);
     return;
   }
   const int hif = hi < g.L ? hi : g.L - 1;
@@ -1097,7 +1106,7 @@ static void stage_dp(const Geo& g, const Dev& p, int lo, int hi, int stage, int 
   // interface leaves lie along refinement boundaries: a small fraction
   int nb = blocks_for(g.B * g.n[hif]);
   if (nb > g.iface_grid) nb = g.iface_grid;
-  k_stage<D, PDE, true><<<nb, TPB, 0, s>>>(g, p, lo, hif, stage, MRD_MAXLEV + 1);
+  stage_launch_st<D, PDE, true>(stage, nb, g, p, lo, hif, MRD_MAXLEV + 1, s);
 }
 
 template <int D>
