@@ -17,7 +17,8 @@
  *  - The context owns all of its device memory; input buffers are borrowed
  *    (copied in), output buffers are allocated by the caller.
  *  - Work is queued on the stream given to mr_set_stream / mr_load_finest
- *    (default: the null stream).  mr_lt_step, mr_reconstruct,
+ *    (default: a non-blocking stream the context creates; mr_init returns
+ *    with its zero fills and uploads complete).  mr_lt_step, mr_reconstruct,
  *    mr_max_wavespeed, mr_get_leaves, mr_stats synchronise that stream
  *    before returning.
  *  - One host thread per context at a time.
@@ -26,6 +27,12 @@
  *    The single-solve calls act on a batch of one.
  *  - Errors are sticky: after MR_ENONFINITE or MR_ESTATE the context refuses
  *    mr_lt_step until mr_load_finest or mr_set_leaves resets it.
+ *  - Environment, read by mr_init / mr_init_batch: MRLT_CHECK (set: the
+ *    kernels also verify the tree invariants the grading guarantees --
+ *    stencil cells exist, the coarse side of a refined face is a leaf --
+ *    and report a violation as MR_ESTATE; results are the same);
+ *    MRLT_NO_GRAPH (set: launch every kernel of a macro step eagerly
+ *    instead of replaying the captured graph).
  */
 #ifndef MRLT_H
 #define MRLT_H

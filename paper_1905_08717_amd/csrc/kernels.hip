@@ -231,7 +231,7 @@ __device__ __forceinline__ bool gather27(const Geo& g, const Dev& p, const doubl
         if (D > 1) fl = fl != st_flip(x[1] + oy, n, g.dirichlet[1]);
         if (D > 2) fl = fl != st_flip(x[2] + oz, n, g.dirichlet[2]);
         const int64_t G = ibase + (int64_t)menc<D>(y);
-        ok = ok && (p.st[G] != ST_ABSENT);
+        if (g.check) ok = ok && (p.st[G] != ST_ABSENT);  // grading: the stencil exists
         const double v = src[(int64_t)k * g.Ntot + G];
         S[(ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)] = fl ? -v : v;
       }
@@ -1007,7 +1007,7 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
               int y[3] = {x[0] >> 1, x[1] >> 1, x[2] >> 1};
               y[dir] = nbs[dir][side] >> 1;
               const int64_t tX = inst * g.n[lev - 1] + (int64_t)menc<D>(y);
-              if (p.st[g.off[lev - 1] + tX] != ST_LEAF) flag_bad(p, inst, 8);
+              if (g.check && p.st[g.off[lev - 1] + tX] != ST_LEAF) flag_bad(p, inst, 8);
               int t0, t1;
               transverse<D>(dir, t0, t1);
               int b = 0;

@@ -407,6 +407,7 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
   g.list_grid = 2048;
   g.iface_grid = 512;
   g.comp_grid = 8192;
+  g.check = getenv("MRLT_CHECK") != nullptr ? 1 : 0;
   g.nu = s->nu;
   g.k_react = s->k_react;
   g.a_react = s->a_react;

@@ -594,3 +594,34 @@ def test_launch_knobs_do_not_change_results(mods):
         s.set_launch(list_grid=-1)
     with pytest.raises(mrlt.MrError):
         s.set_launch(comp_grid=70000)
+
+
+@pytest.mark.parametrize("case", ["nagumo2d", "euler3d"])
+def test_invariant_checks_change_nothing(mods, monkeypatch, case):
+    # with MRLT_CHECK the kernels also verify the graded-tree invariants
+    # while they read stencils; no violation is reported and the results are
+    # bit-identical to the unchecked run
+    _, mrlt = mods
+    if case == "nagumo2d":
+        cfg, B = W.nagumo_2d(L=8), 4
+        q = np.stack([W.nagumo_front(8, W.SEED + 40 + i) for i in range(B)])
+        dt = W.nagumo_dt(cfg)
+    else:
+        cfg, B = W.euler_3d(L=5), 2
+        q = np.stack([W.euler_sphere(5)] * B)
+        dt = None
+    runs = []
+    for check in (False, True):
+        if check:
+            monkeypatch.setenv("MRLT_CHECK", "1")
+        else:
+            monkeypatch.delenv("MRLT_CHECK", raising=False)
+        s = mrlt.Solver(cfg, n_inst=B)
+        s.load_finest(q)
+        step = dt if dt is not None else W.euler_dt(cfg, s.max_wavespeed()[0], 0.0)
+        for _ in range(2):
+            assert s.lt_step_rc(step) == 0
+        runs.append([s.get_leaves(i) for i in range(B)])
+        s.close()
+    for (k0, v0), (k1, v1) in zip(*runs):
+        assert np.array_equal(k0, k1) and np.array_equal(v0, v1)
