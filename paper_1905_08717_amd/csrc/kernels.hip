@@ -795,8 +795,10 @@ __device__ __forceinline__ void refined_flux(const Geo& g, const Dev& p, int lev
       int y[3] = {fy[0], fy[1], fy[2]};
       y[dir] = 2 * nbx + e;
       const int64_t Gf = ibf + (int64_t)menc<D>(y);
-      const uint8_t sf = p.st[Gf];
-      if (sf == ST_ABSENT) flag_bad(p, inst, 4);
+      // the finer cell's status selects its stage-2 value under local time
+      // stepping; otherwise it is read only to verify that the cell exists
+      const uint8_t sf = (g.check || (g.lt && stage == 2)) ? p.st[Gf] : (uint8_t)ST_LEAF;
+      if (g.check && sf == ST_ABSENT) flag_bad(p, inst, 4);
 #pragma unroll
       for (int k = 0; k < M; k++) {
         const int64_t I = (int64_t)k * g.Ntot + Gf;
