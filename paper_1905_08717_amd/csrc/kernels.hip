@@ -690,32 +690,72 @@ void launch_project(const Geo& g, const Dev& p, int lev, int mode, hipStream_t s
 //   case B (parent level l_min - 1 at mid-step): S1 q** / theta=1/2
 //     projection, S2 end value, S3 theta=3/4 value (Alg. refRK22, Sec. 4.3)
 
+template <class T>
+__device__ __forceinline__ T block_exscan(T v, T* sh, T* tot);  // block-wide exclusive scan (below)
+
 template <int D>
 __global__ __launch_bounds__(TPB) void k_ghost(Geo g, Dev p, int lo, int hi, int cb_lev, int srcA, int srcB,
                                               int dst) {
+  // siblings are adjacent in a level's list (Morton order), and all of them
+  // are predicted from the same parent stencil: a block takes 1024 list
+  // entries (four per lane), gathers the first listed sibling of each
+  // parent into shared memory, and each lane then predicts one parent's
+  // listed children from one gather of its stencil
+  constexpr int PER = 4, CH = TPB * PER, NS = 1 << D;
   __shared__ int s_cnt[MRD_MAXLEV + 1];
+  __shared__ int s_lead[CH];
+  __shared__ int sh[TPB / 64];
   const int64_t ntot = flat_setup(p, LS_GHOST, lo, hi, s_cnt);
-  GSL(i, ntot) {
-    {
+  for (int64_t base = (int64_t)blockIdx.x * CH; base < ntot; base += (int64_t)gridDim.x * CH) {
+    uint32_t lead = 0u;  // bit e: entry base + PER * threadIdx.x + e leads its sibling group
+#pragma unroll
+    for (int e = 0; e < PER; e++) {
+      const int64_t i = base + PER * (int64_t)threadIdx.x + e;
+      if (i >= ntot) break;
       int64_t kk = i;
+      const int lev = flat_level(s_cnt, lo, kk);
+      const int* lst = p.lst[LS_GHOST] + g.off[lev];
+      const int t = lst[kk];
+      if (kk == 0 || (lst[kk - 1] >> D) != (t >> D)) lead |= 1u << e;
+    }
+    int tot;
+    int pos = block_exscan<int>(__popc(lead), sh, &tot);
+    while (lead) {
+      const int e = __builtin_ctz(lead);
+      lead &= lead - 1u;
+      s_lead[pos++] = PER * (int)threadIdx.x + e;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < tot; q += TPB) {
+      int64_t kk = base + s_lead[q];
       const int lev = flat_level(s_cnt, lo, kk);
       const int64_t nl = g.n[lev];
       const double* src = p.q[lev == cb_lev ? srcB : srcA];
-      const int64_t t = p.lst[LS_GHOST][g.off[lev] + kk];
-      const int64_t G = g.off[lev] + t;
-      const int64_t inst = t >> (D * lev);
+      const int* lst = p.lst[LS_GHOST] + g.off[lev];
+      const int len = s_cnt[lev - lo];
+      const int t = lst[kk];
+      uint32_t cbits = 1u << (t & (NS - 1));
+      for (int e = 1; e < NS && kk + e < len; e++) {
+        const int u = lst[kk + e];
+        if ((u >> D) != (t >> D)) break;
+        cbits |= 1u << (u & (NS - 1));
+      }
+      const int64_t G0 = g.off[lev] + (int64_t)(t & ~(NS - 1));  // child 0 of the parent
+      const int64_t inst = (int64_t)t >> (D * lev);
       int x[3];
-      mdec<D>((uint64_t)(t & (nl - 1)), x);
+      mdec<D>((uint64_t)((int64_t)t & (nl - 1)), x);
       const int px[3] = {x[0] >> 1, x[1] >> 1, x[2] >> 1};
       const int64_t ibp = g.off[lev - 1] + inst * g.n[lev - 1];
-      const int cb = (x[0] & 1) | ((x[1] & 1) << 1) | ((x[2] & 1) << 2);
       for (int k = 0; k < g.m; k++) {
         double S[27], T[8];
         if (!gather27<D>(g, p, src, lev - 1, ibp, px, k, S)) flag_bad(p, inst, 1);
         pred_terms<D>(S, T);
-        p.q[dst][(int64_t)k * g.Ntot + G] = pred_child<D>(T, cb);
+#pragma unroll
+        for (int cb = 0; cb < NS; cb++)
+          if ((cbits >> cb) & 1u) p.q[dst][(int64_t)k * g.Ntot + G0 + cb] = pred_child<D>(T, cb);
       }
     }
+    __syncthreads();  // s_lead is reused
   }
 }
 
