@@ -1389,6 +1389,45 @@ __device__ __forceinline__ int block_items(uint32_t mask, int* items, int* sh) {
   return tot;
 }
 
+// block-wide gather of sibling groups: with 16-cell lane groups, one work
+// item per sibling group (2^d cells with one parent) that has a cell in
+// `mask`, the group's first cell in bits 0-15 and the child mask in bits
+// 16-23; with one cell per lane (G = 1), one item per cell as block_items.
+// Returns their number.
+template <int D, int G>
+__device__ __forceinline__ int block_sib_items(uint32_t mask, int* items, int* sh) {
+  if (G == 1) {
+    const int cnt = block_items<G>(mask, items, sh);
+    return cnt;
+  }
+  constexpr uint32_t CM = (1u << (1 << D)) - 1u;
+  uint32_t gmask = 0u;
+#pragma unroll
+  for (int gi = 0; gi < (16 >> D); gi++)
+    if ((mask >> (gi << D)) & CM) gmask |= 1u << gi;
+  if (!__syncthreads_or(gmask != 0u)) return 0;
+  int tot;
+  int k = block_exscan<int>(__popc(gmask), sh, &tot);
+  while (gmask) {
+    const int gi = __builtin_ctz(gmask);
+    gmask &= gmask - 1u;
+    items[k++] = ((int)threadIdx.x * 16 + (gi << D)) | (int)(((mask >> (gi << D)) & CM) << 16);
+  }
+  __syncthreads();
+  return tot;
+}
+// an item of block_sib_items: first cell (within-level index) and child mask
+template <int D, int G>
+__device__ __forceinline__ int64_t sib_item(int it, int64_t tb, uint32_t* cbits) {
+  if (G == 1) {
+    const int64_t t = tb + it;
+    *cbits = 1u << (int)(t & ((1 << D) - 1));
+    return t & ~(int64_t)((1 << D) - 1);
+  }
+  *cbits = (uint32_t)it >> 16;
+  return tb + (it & 0xffff);
+}
+
 // remesh table and W flags cleared on levels lo..hi: one workgroup per
 // 4096-cell block, only blocks flagged in wsum hold marks
 __global__ __launch_bounds__(TPB) void k_clear_w(Geo g, Dev p, int lo, int hi) {
@@ -1537,9 +1576,11 @@ __global__ __launch_bounds__(TPB) void k_close(Geo g, Dev p, int lev) {
     if (p.wsum[g.bs_off[lf] + (tb >> BS_SHIFT)] == 0) continue;  // no W in the block
     const int64_t t0 = tb + (int64_t)threadIdx.x * G;
     const uint32_t mask = t0 < N ? w_mask<G>(g, ldg<G>(rff, t0, N), t0, D * lf) : 0u;
-    const int cnt = block_items<G>(mask, items, sh);
+    // the marks depend only on the parent: one item per sibling group
+    const int cnt = block_sib_items<D, G>(mask, items, sh);
     for (int i = threadIdx.x; i < cnt; i += TPB) {
-      const int64_t t = tb + items[i];
+      uint32_t cbits;
+      const int64_t t = sib_item<D, G>(items[i], tb, &cbits);
       const int64_t inst = t >> (D * lf);
       const int64_t ibc = inst * g.n[lev];
       int y[3];
@@ -1582,9 +1623,11 @@ __global__ __launch_bounds__(TPB) void k_prune(Geo g, Dev p, int lev, int la) {
     if (p.wsum[g.bs_off[lev] + (tb >> BS_SHIFT)] == 0) continue;  // no W in the block
     const int64_t t0 = tb + (int64_t)threadIdx.x * G;
     const uint32_t mask = t0 < N ? w_mask<G>(g, ldg<G>(rfl, t0, N), t0, D * lev) : 0u;
-    const int cnt = block_items<G>(mask, items, sh);
+    // the test depends only on the parent: one item per sibling group
+    const int cnt = block_sib_items<D, G>(mask, items, sh);
     for (int i = threadIdx.x; i < cnt; i += TPB) {
-      const int64_t t = tb + items[i];
+      uint32_t cbits;
+      const int64_t t = sib_item<D, G>(items[i], tb, &cbits);
       const int64_t inst = t >> (D * lev);
       int x[3];
       mdec<D>((uint64_t)(t & (nl - 1)), x);
@@ -1605,7 +1648,11 @@ __global__ __launch_bounds__(TPB) void k_prune(Geo g, Dev p, int lev, int la) {
             const bool in = (lev - 1 >= la) ? ((p.rf[Gp] & RF_W) != 0) : (p.st[Gp] == ST_INTERNAL);
             ok = ok && in;
           }
-      if (!ok) rfl[t] = 0;  // the byte holds only the W bit
+      if (!ok) {
+#pragma unroll
+        for (int cb = 0; cb < (1 << D); cb++)
+          if ((cbits >> cb) & 1u) rfl[t + cb] = 0;  // the byte holds only the W bit
+      }
     }
     __syncthreads();
   }
