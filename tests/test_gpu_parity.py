@@ -308,18 +308,23 @@ def test_full_size_nagumo_one_macro_step(mods):
 
 
 def test_large_batch_thresholds_take_effect(mods):
-    # A batch of 256 full-size Nagumo fronts: the context's allocations are
+    # The benchmark's configuration: a batch of 512 full-size Nagumo fronts
+    # with the stored launch setting.  The context's allocations are
     # zero-filled on its stream (several GB here), and the per-instance
     # thresholds uploaded after them must survive those fills.  Sampled
     # instances against the oracle after the load and one macro step.
     mro, mrlt = mods
+    from paper_1905_08717_amd import autotune
     cfg = W.nagumo_2d()            # L=9, 512^2
-    B = 256
+    B = 512
     q = np.stack([W.nagumo_front(9, W.SEED + i) for i in range(B)])
     s = mrlt.Solver(cfg, n_inst=B)
+    stored = autotune.lookup(autotune.nagumo_key(9, B))
+    if stored:
+        s.set_launch(**stored)
     s.load_finest(q)
     dt = W.nagumo_dt(cfg)
-    sample = (0, 131, B - 1)
+    sample = (0, 131, 300, B - 1)
     oracles = []
     for i in sample:
         o = mro.Oracle(cfg)
