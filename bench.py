@@ -104,6 +104,8 @@ def traffic_record(args):
     what the counters read for the 1 GiB copy."""
     import csv
     d = args.pmc_dir
+    if not d:
+        raise SystemExit("--mode traffic needs --pmc-dir (the folder holding the four counter runs)")
 
     def col(path, kern):
         with open(path) as f:
@@ -306,7 +308,7 @@ def main():
     ap.add_argument("--levels", default="8,9,10", help="paper mode: finest levels")
     ap.add_argument("--flame-levels", default="11,12", help="flames mode: finest levels of the 1D flame")
     ap.add_argument("--flame-ball-level", type=int, default=7, help="flames mode: 3D flame ball L (0: skip)")
-    ap.add_argument("--pmc-dir", default="gpurun_out", help="traffic mode: folder of the four counter runs")
+    ap.add_argument("--pmc-dir", default="", help="traffic mode: folder of the four counter runs (required)")
     ap.add_argument("--no-single", action="store_true", help="skip the single-solve reference run")
     ap.add_argument("--tune", action="store_true", help="search the launch configuration before timing")
     ap.add_argument("--no-tune", action="store_true", help="library default launch configuration")
