@@ -36,48 +36,48 @@ int list_blocks(const Geo& g, int64_t n) {
 // ---------------------------------------------------------------------------
 // Morton keys and boundary maps
 
-__device__ __forceinline__ uint64_t part1by1(uint64_t x) {
-  x &= 0xffffffffull;
-  x = (x | (x << 16)) & 0x0000ffff0000ffffull;
-  x = (x | (x << 8)) & 0x00ff00ff00ff00ffull;
-  x = (x | (x << 4)) & 0x0f0f0f0f0f0f0f0full;
-  x = (x | (x << 2)) & 0x3333333333333333ull;
-  x = (x | (x << 1)) & 0x5555555555555555ull;
+// Within-instance Morton keys have at most 30 bits (a level holds fewer
+// than 2^30 cells per instance), so the bit interleaving works on 32-bit
+// words: spread / compact by binary magic numbers (the shift-or-mask
+// construction for interleaved codes), one instruction per step.
+__device__ __forceinline__ uint32_t part1by1(uint32_t x) {  // x < 2^15
+  x &= 0x0000ffffu;
+  x = (x | (x << 8)) & 0x00ff00ffu;
+  x = (x | (x << 4)) & 0x0f0f0f0fu;
+  x = (x | (x << 2)) & 0x33333333u;
+  x = (x | (x << 1)) & 0x55555555u;
   return x;
 }
-__device__ __forceinline__ uint64_t compact1by1(uint64_t x) {
-  x &= 0x5555555555555555ull;
-  x = (x | (x >> 1)) & 0x3333333333333333ull;
-  x = (x | (x >> 2)) & 0x0f0f0f0f0f0f0f0full;
-  x = (x | (x >> 4)) & 0x00ff00ff00ff00ffull;
-  x = (x | (x >> 8)) & 0x0000ffff0000ffffull;
-  x = (x | (x >> 16)) & 0x00000000ffffffffull;
+__device__ __forceinline__ uint32_t compact1by1(uint32_t x) {
+  x &= 0x55555555u;
+  x = (x | (x >> 1)) & 0x33333333u;
+  x = (x | (x >> 2)) & 0x0f0f0f0fu;
+  x = (x | (x >> 4)) & 0x00ff00ffu;
+  x = (x | (x >> 8)) & 0x0000ffffu;
   return x;
 }
-__device__ __forceinline__ uint64_t part1by2(uint64_t x) {
-  x &= 0x1fffffull;
-  x = (x | (x << 32)) & 0x1f00000000ffffull;
-  x = (x | (x << 16)) & 0x1f0000ff0000ffull;
-  x = (x | (x << 8)) & 0x100f00f00f00f00full;
-  x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
-  x = (x | (x << 2)) & 0x1249249249249249ull;
+__device__ __forceinline__ uint32_t part1by2(uint32_t x) {  // x < 2^10
+  x &= 0x3ffu;
+  x = (x | (x << 16)) & 0x030000ffu;
+  x = (x | (x << 8)) & 0x0300f00fu;
+  x = (x | (x << 4)) & 0x030c30c3u;
+  x = (x | (x << 2)) & 0x09249249u;
   return x;
 }
-__device__ __forceinline__ uint64_t compact1by2(uint64_t x) {
-  x &= 0x1249249249249249ull;
-  x = (x | (x >> 2)) & 0x10c30c30c30c30c3ull;
-  x = (x | (x >> 4)) & 0x100f00f00f00f00full;
-  x = (x | (x >> 8)) & 0x1f0000ff0000ffull;
-  x = (x | (x >> 16)) & 0x1f00000000ffffull;
-  x = (x | (x >> 32)) & 0x1fffffull;
+__device__ __forceinline__ uint32_t compact1by2(uint32_t x) {
+  x &= 0x09249249u;
+  x = (x | (x >> 2)) & 0x030c30c3u;
+  x = (x | (x >> 4)) & 0x0300f00fu;
+  x = (x | (x >> 8)) & 0x030000ffu;
+  x = (x | (x >> 16)) & 0x000003ffu;
   return x;
 }
 
 template <int D>
 __device__ __forceinline__ uint64_t menc(const int* x) {
   if (D == 1) return (uint64_t)x[0];
-  if (D == 2) return part1by1((uint64_t)x[0]) | (part1by1((uint64_t)x[1]) << 1);
-  return part1by2((uint64_t)x[0]) | (part1by2((uint64_t)x[1]) << 1) | (part1by2((uint64_t)x[2]) << 2);
+  if (D == 2) return (uint64_t)(part1by1((uint32_t)x[0]) | (part1by1((uint32_t)x[1]) << 1));
+  return (uint64_t)(part1by2((uint32_t)x[0]) | (part1by2((uint32_t)x[1]) << 1) | (part1by2((uint32_t)x[2]) << 2));
 }
 
 template <int D>
@@ -86,21 +86,23 @@ __device__ __forceinline__ void mdec(uint64_t k, int* x) {
   if (D == 1) {
     x[0] = (int)k;
   } else if (D == 2) {
-    x[0] = (int)compact1by1(k);
-    x[1] = (int)compact1by1(k >> 1);
+    const uint32_t k32 = (uint32_t)k;
+    x[0] = (int)compact1by1(k32);
+    x[1] = (int)compact1by1(k32 >> 1);
   } else {
-    x[0] = (int)compact1by2(k);
-    x[1] = (int)compact1by2(k >> 1);
-    x[2] = (int)compact1by2(k >> 2);
+    const uint32_t k32 = (uint32_t)k;
+    x[0] = (int)compact1by2(k32);
+    x[1] = (int)compact1by2(k32 >> 1);
+    x[2] = (int)compact1by2(k32 >> 2);
   }
 }
 
-// Morton bits of axis a (a, a + D, a + 2D, ...)
+// Morton bits of axis a (a, a + D, a + 2D, ...) of a 32-bit key
 template <int D>
-__device__ __forceinline__ constexpr uint64_t axis_mask(int a) {
-  return D == 1 ? ~0ull
-         : D == 2 ? (a == 0 ? 0x5555555555555555ull : 0xaaaaaaaaaaaaaaaaull)
-                  : (a == 0 ? 0x9249249249249249ull : (a == 1 ? 0x2492492492492492ull : 0x4924924924924924ull));
+__device__ __forceinline__ constexpr uint32_t axis_mask(int a) {
+  return D == 1 ? ~0u
+         : D == 2 ? (a == 0 ? 0x55555555u : 0xaaaaaaaau)
+                  : (a == 0 ? 0x49249249u : (a == 1 ? 0x92492492u : 0x24924924u));
 }
 // key of the cell o cells (|o| <= 2) along axis a from key k, the coordinate
 // staying on the level: an add on the dilated coordinate (the other axes'
@@ -109,10 +111,11 @@ __device__ __forceinline__ constexpr uint64_t axis_mask(int a) {
 template <int D>
 __device__ __forceinline__ uint64_t morton_step(uint64_t k, int a, int o) {
   if (D == 1) return o > 0 ? k + (uint64_t)o : k - (uint64_t)(-o);
-  const uint64_t m = axis_mask<D>(a);
-  const uint64_t d = (o == 1 || o == -1) ? (1ull << a) : (1ull << (D + a));
-  if (o > 0) return (((k | ~m) + d) & m) | (k & ~m);
-  return (((k & m) - d) & m) | (k & ~m);
+  const uint32_t k32 = (uint32_t)k;
+  const uint32_t m = axis_mask<D>(a);
+  const uint32_t d = (o == 1 || o == -1) ? (1u << a) : (1u << (D + a));
+  if (o > 0) return (uint64_t)((((k32 | ~m) + d) & m) | (k32 & ~m));
+  return (uint64_t)((((k32 & m) - d) & m) | (k32 & ~m));
 }
 
 // stencil coordinate: periodic wraps, homogeneous Neumann reflects evenly
