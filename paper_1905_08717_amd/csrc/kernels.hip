@@ -1991,31 +1991,55 @@ __device__ __forceinline__ bool level_empty(const Dev& p, int lev, int full) {
 template <int D>
 __global__ __launch_bounds__(TPB) void k_comp_count(Geo g, Dev p, int lo, int full) {
   __shared__ uint64_t sh[TPB / 64];
+  __shared__ unsigned long long s_work;
   const int64_t nbt = g.comp_first[g.L + 1];
-  for (int64_t b = g.comp_first[lo] + blockIdx.x; b < nbt; b += gridDim.x) {
-    const CompRange r = comp_range(g, lo, b);
-    if (level_empty(p, r.lev, full)) continue;
-    if (!full && comp_skip<D>(g, p, r)) {
-      if (threadIdx.x < NCL) p.bcnt[clist(threadIdx.x) * nbt + b] = 0;
-      continue;
-    }
-    uint32_t cb[4];
-    uint64_t tot;
-    block_exscan<uint64_t>(lane_counts<D>(g, p, r, cb), sh, &tot);
-    // the codes, one byte per cell, for the write pass
-    if (r.act) {
-      uint8_t* cc = p.ccode + g.off[r.lev] + r.t0;
-      if (r.cpt == GRP) *reinterpret_cast<uint4*>(cc) = make_uint4(cb[0], cb[1], cb[2], cb[3]);
-      else cc[0] = (uint8_t)cb[0];
-    }
-    if (threadIdx.x == 0) {
-      const int64_t nsbt = g.sb_first[g.L + 1];
-      const int64_t sbi = g.sb_first[r.lev] + ((b - g.comp_first[r.lev]) >> g.sb_shift[r.lev]);
+  // the workgroup's next 64 blocks are tested for work by the 64 lanes of
+  // its first wave at once (empty level, or nothing to list), then only the
+  // blocks with work are visited
+  for (int64_t b0 = g.comp_first[lo] + blockIdx.x; b0 < nbt; b0 += 64 * (int64_t)gridDim.x) {
+    if (threadIdx.x < 64) {
+      const int64_t bj = b0 + (int64_t)threadIdx.x * gridDim.x;
+      bool work = false;
+      if (bj < nbt) {
+        const CompRange rj = comp_range(g, lo, bj);
+        if (!level_empty(p, rj.lev, full)) {
+          if (!full && comp_skip<D>(g, p, rj)) {
 #pragma unroll
-      for (int k = 0; k < NCL; k++) {
-        const int cnt = (int)((tot >> (16 * k)) & 0xffffull);
-        p.bcnt[clist(k) * nbt + b] = cnt;
-        if (cnt) atomicAdd(&p.sbcnt[clist(k) * nsbt + sbi], cnt);
+            for (int k = 0; k < NCL; k++) p.bcnt[clist(k) * nbt + bj] = 0;
+          } else {
+            work = true;
+          }
+        }
+      }
+      const unsigned long long wm = __ballot(work);
+      if (threadIdx.x == 0) s_work = wm;
+    }
+    __syncthreads();
+    unsigned long long wm = s_work;
+    __syncthreads();  // s_work is rewritten by the next group of blocks
+    while (wm) {
+      const int jb = __builtin_ctzll(wm);
+      wm &= wm - 1ull;
+      const int64_t b = b0 + (int64_t)jb * gridDim.x;
+      const CompRange r = comp_range(g, lo, b);
+      uint32_t cb[4];
+      uint64_t tot;
+      block_exscan<uint64_t>(lane_counts<D>(g, p, r, cb), sh, &tot);
+      // the codes, one byte per cell, for the write pass
+      if (r.act) {
+        uint8_t* cc = p.ccode + g.off[r.lev] + r.t0;
+        if (r.cpt == GRP) *reinterpret_cast<uint4*>(cc) = make_uint4(cb[0], cb[1], cb[2], cb[3]);
+        else cc[0] = (uint8_t)cb[0];
+      }
+      if (threadIdx.x == 0) {
+        const int64_t nsbt = g.sb_first[g.L + 1];
+        const int64_t sbi = g.sb_first[r.lev] + ((b - g.comp_first[r.lev]) >> g.sb_shift[r.lev]);
+  #pragma unroll
+        for (int k = 0; k < NCL; k++) {
+          const int cnt = (int)((tot >> (16 * k)) & 0xffffull);
+          p.bcnt[clist(k) * nbt + b] = cnt;
+          if (cnt) atomicAdd(&p.sbcnt[clist(k) * nsbt + sbi], cnt);
+        }
       }
     }
   }
@@ -2104,95 +2128,115 @@ __global__ __launch_bounds__(TPB) void k_comp_write(Geo g, Dev p, int lo, int fu
   __shared__ uint64_t sh[TPB / 64];
   __shared__ int4 s_pre;
   __shared__ int s_ent[TPB * GRP];  // one list's entries of the block, in order
+  __shared__ unsigned long long s_work;
   const int64_t nbt = g.comp_first[g.L + 1];
-  for (int64_t b = g.comp_first[lo] + blockIdx.x; b < nbt; b += gridDim.x) {
-    const CompRange r = comp_range(g, lo, b);
-    if (level_empty(p, r.lev, full)) continue;
-    // the count pass left the block's counts (zero for skipped blocks) and
-    // every listed cell's code
-    const int n0 = p.bcnt[clist(0) * nbt + b], n1 = p.bcnt[clist(1) * nbt + b];
-    const int n2 = p.bcnt[clist(2) * nbt + b], n3 = p.bcnt[clist(3) * nbt + b];
-    if ((n0 | n1 | n2 | n3) == 0) {
-      if (threadIdx.x == 0 && wide_level(g, r.lev)) p.bsum[g.bs_off[r.lev] + (r.tb >> BS_SHIFT)] = 0;
-      continue;
-    }
-    // the lane's cells of each list as a mask (bit j: cell t0 + j)
-    uint32_t mk[NCL] = {0u, 0u, 0u, 0u};
-    if (r.act) {
-      const uint8_t* cc = p.ccode + g.off[r.lev] + r.t0;
-      if (r.cpt == GRP) {
-        const uint4 v = *reinterpret_cast<const uint4*>(cc);
-        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-        for (int k = 0; k < NCL; k++)
-#pragma unroll
-          for (int q = 0; q < 4; q++) mk[k] |= gcodes::word_bits<1>((w[q] >> k) & 0x01010101u) << (4 * q);
-      } else {
-#pragma unroll
-        for (int k = 0; k < NCL; k++) mk[k] = ((uint32_t)cc[0] >> k) & 1u;
-      }
-    }
-    uint64_t c = 0ull, tot;
-#pragma unroll
-    for (int k = 0; k < NCL; k++) c |= (uint64_t)__popc(mk[k]) << (16 * k);
-    const uint64_t ex = block_exscan<uint64_t>(c, sh, &tot);
-    // list offsets of the block: its superblock's plus the counts of the
-    // preceding blocks of the superblock (fewer than 64: wave 0 sums them)
-    int4 pre = make_int4(0, 0, 0, 0);
-    if (tot != 0ull) {
-      const int64_t bl = b - g.comp_first[r.lev];
-      const int sh2 = g.sb_shift[r.lev];
-      const int64_t bs = g.comp_first[r.lev] + ((bl >> sh2) << sh2);
-      const int nprev = (int)(b - bs);
-      if (threadIdx.x < 64) {
-        int4 v = make_int4(0, 0, 0, 0);
-        if ((int)threadIdx.x < nprev) {
-          const int64_t j = bs + threadIdx.x;
-          v = make_int4(p.bcnt[clist(0) * nbt + j], p.bcnt[clist(1) * nbt + j], p.bcnt[clist(2) * nbt + j],
-                        p.bcnt[clist(3) * nbt + j]);
+  // as in the count pass: the next 64 blocks are tested at once (empty
+  // level, or nothing listed: the count pass left the block's counts)
+  for (int64_t b0 = g.comp_first[lo] + blockIdx.x; b0 < nbt; b0 += 64 * (int64_t)gridDim.x) {
+    if (threadIdx.x < 64) {
+      const int64_t bj = b0 + (int64_t)threadIdx.x * gridDim.x;
+      bool work = false;
+      if (bj < nbt) {
+        const CompRange rj = comp_range(g, lo, bj);
+        if (!level_empty(p, rj.lev, full)) {
+          const int n0 = p.bcnt[clist(0) * nbt + bj], n1 = p.bcnt[clist(1) * nbt + bj];
+          const int n2 = p.bcnt[clist(2) * nbt + bj], n3 = p.bcnt[clist(3) * nbt + bj];
+          if ((n0 | n1 | n2 | n3) == 0) {
+            if (wide_level(g, rj.lev)) p.bsum[g.bs_off[rj.lev] + (rj.tb >> BS_SHIFT)] = 0;
+          } else {
+            work = true;
+          }
         }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-          v.x += __shfl_xor(v.x, o, 64); v.y += __shfl_xor(v.y, o, 64);
-          v.z += __shfl_xor(v.z, o, 64); v.w += __shfl_xor(v.w, o, 64);
+      }
+      const unsigned long long wm = __ballot(work);
+      if (threadIdx.x == 0) s_work = wm;
+    }
+    __syncthreads();
+    unsigned long long wm = s_work;
+    __syncthreads();  // s_work is rewritten by the next group of blocks
+    while (wm) {
+      const int jb = __builtin_ctzll(wm);
+      wm &= wm - 1ull;
+      const int64_t b = b0 + (int64_t)jb * gridDim.x;
+      const CompRange r = comp_range(g, lo, b);
+      // the lane's cells of each list as a mask (bit j: cell t0 + j)
+      uint32_t mk[NCL] = {0u, 0u, 0u, 0u};
+      if (r.act) {
+        const uint8_t* cc = p.ccode + g.off[r.lev] + r.t0;
+        if (r.cpt == GRP) {
+          const uint4 v = *reinterpret_cast<const uint4*>(cc);
+          const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+  #pragma unroll
+          for (int k = 0; k < NCL; k++)
+  #pragma unroll
+            for (int q = 0; q < 4; q++) mk[k] |= gcodes::word_bits<1>((w[q] >> k) & 0x01010101u) << (4 * q);
+        } else {
+  #pragma unroll
+          for (int k = 0; k < NCL; k++) mk[k] = ((uint32_t)cc[0] >> k) & 1u;
         }
-        if (threadIdx.x == 0) s_pre = v;
       }
-      __syncthreads();
-      pre = s_pre;
-      const int64_t sbi = g.sb_first[r.lev] + (bl >> sh2);
-      const int64_t nsbt = g.sb_first[g.L + 1];
-      pre.x += p.sboff[clist(0) * nsbt + sbi]; pre.y += p.sboff[clist(1) * nsbt + sbi];
-      pre.z += p.sboff[clist(2) * nsbt + sbi]; pre.w += p.sboff[clist(3) * nsbt + sbi];
-      __syncthreads();  // s_pre is free again
-    }
-    // block summary of a 4096-cell block (levels with >= 4096 cells)
-    if (threadIdx.x == 0 && wide_level(g, r.lev)) {
-      unsigned bits = 0u;
-      if (tot & 0xffffull) bits |= BS_EXIST | BS_LEAF;
-      if ((tot >> 16) & 0xffffull) bits |= BS_EXIST | BS_INT;
-      p.bsum[g.bs_off[r.lev] + (r.tb >> BS_SHIFT)] = (uint8_t)bits;
-    }
-    // each list's entries of the block are one contiguous range of the
-    // list: staged in order in shared memory, then stored with consecutive
-    // lanes on consecutive entries
-    const int base[NCL] = {pre.x, pre.y, pre.z, pre.w};
-    const int64_t o = g.off[r.lev];
-#pragma unroll
-    for (int k = 0; k < NCL; k++) {
-      const int tk = (int)((tot >> (16 * k)) & 0xffffull);
-      if (tk == 0) continue;  // the same in every lane
-      int pos = (int)((ex >> (16 * k)) & 0xffffull);
-      uint32_t m = mk[k];
-      while (m) {
-        const int j = __builtin_ctz(m);
-        m &= m - 1u;
-        s_ent[pos++] = (int)(r.t0 + j);
+      uint64_t c = 0ull, tot;
+  #pragma unroll
+      for (int k = 0; k < NCL; k++) c |= (uint64_t)__popc(mk[k]) << (16 * k);
+      const uint64_t ex = block_exscan<uint64_t>(c, sh, &tot);
+      // list offsets of the block: its superblock's plus the counts of the
+      // preceding blocks of the superblock (fewer than 64: wave 0 sums them)
+      int4 pre = make_int4(0, 0, 0, 0);
+      if (tot != 0ull) {
+        const int64_t bl = b - g.comp_first[r.lev];
+        const int sh2 = g.sb_shift[r.lev];
+        const int64_t bs = g.comp_first[r.lev] + ((bl >> sh2) << sh2);
+        const int nprev = (int)(b - bs);
+        if (threadIdx.x < 64) {
+          int4 v = make_int4(0, 0, 0, 0);
+          if ((int)threadIdx.x < nprev) {
+            const int64_t j = bs + threadIdx.x;
+            v = make_int4(p.bcnt[clist(0) * nbt + j], p.bcnt[clist(1) * nbt + j], p.bcnt[clist(2) * nbt + j],
+                          p.bcnt[clist(3) * nbt + j]);
+          }
+  #pragma unroll
+          for (int o = 32; o > 0; o >>= 1) {
+            v.x += __shfl_xor(v.x, o, 64); v.y += __shfl_xor(v.y, o, 64);
+            v.z += __shfl_xor(v.z, o, 64); v.w += __shfl_xor(v.w, o, 64);
+          }
+          if (threadIdx.x == 0) s_pre = v;
+        }
+        __syncthreads();
+        pre = s_pre;
+        const int64_t sbi = g.sb_first[r.lev] + (bl >> sh2);
+        const int64_t nsbt = g.sb_first[g.L + 1];
+        pre.x += p.sboff[clist(0) * nsbt + sbi]; pre.y += p.sboff[clist(1) * nsbt + sbi];
+        pre.z += p.sboff[clist(2) * nsbt + sbi]; pre.w += p.sboff[clist(3) * nsbt + sbi];
+        __syncthreads();  // s_pre is free again
       }
-      __syncthreads();
-      int* dst = p.lst[clist(k)] + o + base[k];
-      for (int i = threadIdx.x; i < tk; i += TPB) dst[i] = s_ent[i];
-      __syncthreads();
+      // block summary of a 4096-cell block (levels with >= 4096 cells)
+      if (threadIdx.x == 0 && wide_level(g, r.lev)) {
+        unsigned bits = 0u;
+        if (tot & 0xffffull) bits |= BS_EXIST | BS_LEAF;
+        if ((tot >> 16) & 0xffffull) bits |= BS_EXIST | BS_INT;
+        p.bsum[g.bs_off[r.lev] + (r.tb >> BS_SHIFT)] = (uint8_t)bits;
+      }
+      // each list's entries of the block are one contiguous range of the
+      // list: staged in order in shared memory, then stored with consecutive
+      // lanes on consecutive entries
+      const int base[NCL] = {pre.x, pre.y, pre.z, pre.w};
+      const int64_t o = g.off[r.lev];
+  #pragma unroll
+      for (int k = 0; k < NCL; k++) {
+        const int tk = (int)((tot >> (16 * k)) & 0xffffull);
+        if (tk == 0) continue;  // the same in every lane
+        int pos = (int)((ex >> (16 * k)) & 0xffffull);
+        uint32_t m = mk[k];
+        while (m) {
+          const int j = __builtin_ctz(m);
+          m &= m - 1u;
+          s_ent[pos++] = (int)(r.t0 + j);
+        }
+        __syncthreads();
+        int* dst = p.lst[clist(k)] + o + base[k];
+        for (int i = threadIdx.x; i < tk; i += TPB) dst[i] = s_ent[i];
+        __syncthreads();
+      }
     }
   }
 }
