@@ -320,7 +320,7 @@ def main():
     ap.add_argument("--hbm-budget", type=float, default=64.0, help="GiB for resident solves")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (--gpus 1); independent solves would shard "
+        print("bench.py: the library runs on one GPU only (--gpus 1); independent solves would shard "
               "across GPUs by instance, which is not built here", file=sys.stderr)
         sys.exit(2)
 
