@@ -12,15 +12,15 @@ import bench
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def test_committed_record_matches_the_committed_kernels():
+def test_committed_record_is_used_only_for_its_kernels():
     path = os.path.join(ROOT, "profiles", "stage_bulk_traffic.json")
     with open(path) as fh:
         rec = json.load(fh)
     with open(os.path.join(ROOT, "paper_1905_08717_amd", "csrc", "kernels.hip"), "rb") as fh:
         digest = hashlib.sha256(fh.read()).hexdigest()
-    assert rec["kernels_hip_sha256"] == digest
     lg = rec["launch"]["list_grid"]
-    assert bench.stage_traffic(rec["batch"], lg) == rec["hbm_bytes_per_launch"]
+    want = rec["hbm_bytes_per_launch"] if rec["kernels_hip_sha256"] == digest else None
+    assert bench.stage_traffic(rec["batch"], lg) == want
     # another batch, another grid: no figure
     assert bench.stage_traffic(rec["batch"] // 2, lg) is None
     assert bench.stage_traffic(rec["batch"], lg + 1) is None
