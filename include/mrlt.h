@@ -214,6 +214,19 @@ mr_status mr_set_leaves_inst(mr_ctx* c, int inst, const uint64_t* keys, const do
 mr_status mr_stats(mr_ctx* c, mr_stats_t* out);
 mr_status mr_stats_inst(mr_ctx* c, int inst, mr_stats_t* out);
 
+/* Near-threshold decisions of instance `inst` (Alg. waveletThres: a node
+ * is kept when its detail exceeds the level's threshold; a decision with
+ * |detail - eps_l| <= 1e-12 eps_l is near the threshold, where rounding
+ * could decide it): one entry per decision since the instance's last load
+ * or set_leaves, sorted by (iteration, level, key).  iter[j] = fine
+ * iterations completed before the remesh that took it (0 for the remesh of
+ * the load), level[j] = the node's level, key[j] = its Morton key (host
+ * arrays of cap entries).  With iter == NULL only *n is set.  MR_ECAPACITY
+ * if cap is too small, or if the context recorded more than 65536
+ * decisions since mr_load_finest (the list is then incomplete).           */
+mr_status mr_near_threshold(mr_ctx* c, int inst, int64_t* iter, int32_t* level, uint64_t* key, int64_t cap,
+                            int64_t* n);
+
 /* Measurement support.  Cumulative leaf-updates of instance `inst` per
  * level (host array of MR_MAXLEV + 1 entries; one update = one leaf
  * advanced by one full RK step at that level).                           */

@@ -67,6 +67,12 @@ struct mro_ctx {
   int64_t leaf_updates, near_thr, iters;
   int nonfinite, bad;
   char err[256];
+  /* near-threshold decisions |D - eps_l| <= 1e-12 eps_l: fine iterations
+   * completed before the remesh, level and Morton key of the node */
+  int64_t* near_iter;
+  int32_t* near_lev;
+  uint64_t* near_key;
+  int64_t near_n, near_cap;
 };
 
 /* RK coefficients of the compact forms (Sec. 3) and the NERK partials.  */
@@ -968,6 +974,29 @@ static double level_eps(const mro_ctx* c, int lam) {
   return c->eps;
 }
 
+static uint64_t morton(int d, const int* x);
+
+/* append one near-threshold decision (node i of level lev) */
+static void near_record(mro_ctx* c, int lev, int64_t i) {
+  int x[3];
+  ccoord(c, lev, i, x);
+  if (c->near_n == c->near_cap) {
+    int64_t cap = c->near_cap ? 2 * c->near_cap : 64;
+    int64_t* it = (int64_t*)realloc(c->near_iter, sizeof(int64_t) * (size_t)cap);
+    if (it) c->near_iter = it;
+    int32_t* lv = (int32_t*)realloc(c->near_lev, sizeof(int32_t) * (size_t)cap);
+    if (lv) c->near_lev = lv;
+    uint64_t* ky = (uint64_t*)realloc(c->near_key, sizeof(uint64_t) * (size_t)cap);
+    if (ky) c->near_key = ky;
+    if (!it || !lv || !ky) return;
+    c->near_cap = cap;
+  }
+  c->near_iter[c->near_n] = c->iters;
+  c->near_lev[c->near_n] = lev;
+  c->near_key[c->near_n] = morton(c->d, x);
+  c->near_n++;
+}
+
 /* max over children and components of |q_c - q~_c| / scale_k */
 static double detail_norm(mro_ctx* c, int lev, int64_t i) {
   int x[3];
@@ -1082,7 +1111,11 @@ static void remesh(mro_ctx* c, int la) {
       }
       double D = detail_norm(c, lev, i);
       LV->sig[i] = D > e;
-      if (fabs(D - e) <= 1e-12 * e) near++;
+      if (fabs(D - e) <= 1e-12 * e) {
+        near++;
+#pragma omp critical(near_list)
+        near_record(c, lev, i);
+      }
     }
     c->near_thr += near;
   }
@@ -1354,7 +1387,41 @@ int mro_init(int dim, int L, double eps, const mro_scheme* s, mro_ctx** out) {
 void mro_destroy(mro_ctx* c) {
   if (!c) return;
   free_levels(c);
+  free(c->near_iter);
+  free(c->near_lev);
+  free(c->near_key);
   free(c);
+}
+
+typedef struct { int64_t it; int32_t lev; uint64_t key; } near_t;
+static int near_cmp(const void* a, const void* b) {
+  const near_t* x = (const near_t*)a;
+  const near_t* y = (const near_t*)b;
+  if (x->it != y->it) return x->it < y->it ? -1 : 1;
+  if (x->lev != y->lev) return x->lev < y->lev ? -1 : 1;
+  return x->key < y->key ? -1 : (x->key > y->key ? 1 : 0);
+}
+
+int mro_near_threshold(mro_ctx* c, int64_t* iter, int32_t* level, uint64_t* key, int64_t cap, int64_t* n) {
+  if (!c || !n) return MRO_EINVAL;
+  *n = c->near_n;
+  if (!iter || !level || !key) return MRO_OK;
+  if (cap < c->near_n) return MRO_EINVAL;
+  near_t* v = (near_t*)malloc(sizeof(near_t) * (size_t)(c->near_n + 1));
+  if (!v) return MRO_ENOMEM;
+  for (int64_t j = 0; j < c->near_n; j++) {
+    v[j].it = c->near_iter[j];
+    v[j].lev = c->near_lev[j];
+    v[j].key = c->near_key[j];
+  }
+  qsort(v, (size_t)c->near_n, sizeof(near_t), near_cmp);
+  for (int64_t j = 0; j < c->near_n; j++) {
+    iter[j] = v[j].it;
+    level[j] = v[j].lev;
+    key[j] = v[j].key;
+  }
+  free(v);
+  return MRO_OK;
 }
 
 int mro_ncomp(const mro_ctx* c) { return c ? c->m : 0; }
@@ -1396,6 +1463,11 @@ int mro_load_finest(mro_ctx* c, const double* q0) {
   }
   memcpy(c->lv[L].slot[S_Q0], q0, sizeof(double) * (size_t)c->m * (size_t)c->lv[L].ncell);
   c->t = 0.0;
+  /* counters and the near-threshold list start again with the new state */
+  c->near_n = 0;
+  c->iters = 0;
+  c->leaf_updates = 0;
+  c->near_thr = 0;
   c->nonfinite = 0;
   c->bad = 0;
   c->err[0] = 0;
@@ -1593,6 +1665,10 @@ int mro_set_leaves(mro_ctx* c, const uint64_t* keys, const double* q, int64_t n,
     }
   project_q0(c, L - 1, c->l0);
   c->t = t;
+  c->near_n = 0;
+  c->iters = 0;
+  c->leaf_updates = 0;
+  c->near_thr = 0;
   c->nonfinite = 0;
   c->bad = 0;
   c->err[0] = 0;

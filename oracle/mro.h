@@ -87,6 +87,10 @@ int  mro_predict(int dim, int m, const double* stencil, double* children);
 int  mro_project(int dim, int m, const double* children, double* parent);
 int  mro_face_flux(mro_ctx* c, int level, int dir, const double* cells, double* F);
 int  mro_details(mro_ctx* c, int level, double* D);  /* detail norm per internal node, -1 else */
+/* near-threshold decisions since the last load / set_leaves, sorted by
+ * (iteration, level, key): iteration = fine iterations completed before the
+ * remesh that took the decision; with iter == NULL only *n is set */
+int  mro_near_threshold(mro_ctx* c, int64_t* iter, int32_t* level, uint64_t* key, int64_t cap, int64_t* n);
 
 #ifdef __cplusplus
 }

@@ -97,6 +97,8 @@ def lib():
         L.mro_project.argtypes = [i32, i32, dp, dp]
         L.mro_face_flux.argtypes = [vp, i32, i32, dp, dp]
         L.mro_details.argtypes = [vp, i32, dp]
+        L.mro_near_threshold.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_int32), u64p, i64,
+                                         ctypes.POINTER(i64)]
         _lib = L
     return _lib
 
@@ -234,6 +236,21 @@ class Oracle:
             "iterations": st.iterations,
             "mass": [st.mass[k] for k in range(self.m)],
         }
+
+    def near_threshold(self):
+        """Near-threshold decisions since the last load / set_leaves as a
+        sorted list of (iteration, level, Morton key)."""
+        n = ctypes.c_int64()
+        self._check(lib().mro_near_threshold(self._h, None, None, None, 0, ctypes.byref(n)), "mro_near_threshold")
+        it = np.zeros(n.value, dtype=np.int64)
+        lv = np.zeros(n.value, dtype=np.int32)
+        ky = np.zeros(n.value, dtype=np.uint64)
+        if n.value:
+            self._check(lib().mro_near_threshold(
+                self._h, it.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                lv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                ky.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), n.value, ctypes.byref(n)), "mro_near_threshold")
+        return [(int(a), int(b), int(c)) for a, b, c in zip(it, lv, ky)]
 
     def level(self, lev: int):
         n = 1 << (self.dim * lev)

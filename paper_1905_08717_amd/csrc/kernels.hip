@@ -1464,7 +1464,7 @@ __global__ __launch_bounds__(TPB) void k_level_w(Geo g, Dev p, int la) {
 // safety (Sec. 4: apart from which scales may split or merge, the LT remesh
 // is the multiresolution remesh).
 template <int D>
-__global__ __launch_bounds__(TPB) void k_detail_seed(Geo g, Dev p, int lo, int hi, int la) {
+__global__ __launch_bounds__(TPB) void k_detail_seed(Geo g, Dev p, int lo, int hi, int la, int n_it) {
   __shared__ int s_cnt[MRD_MAXLEV + 1];
   const int64_t ntot = flat_setup(p, LS_INTERNAL, lo, hi, s_cnt);
   GSL(i, ntot) {
@@ -1508,7 +1508,15 @@ __global__ __launch_bounds__(TPB) void k_detail_seed(Geo g, Dev p, int lo, int h
           }
         }
         sig = Dm > e;
-        if (fabs(Dm - e) <= 1e-12 * e) atomicAdd(&p.cnt[inst * CNT_PER_INST + CNT_NEAR], 1ull);
+        if (fabs(Dm - e) <= 1e-12 * e) {
+          atomicAdd(&p.cnt[inst * CNT_PER_INST + CNT_NEAR], 1ull);
+          const unsigned long long j = atomicAdd(p.near_n, 1ull);
+          if (j < NEAR_CAP) {
+            p.near[2 * j] = (unsigned long long)(*p.iterb + n_it);
+            p.near[2 * j + 1] = ((unsigned long long)inst << 45) | ((unsigned long long)lev << 40) |
+                                (unsigned long long)(t & (nl - 1));
+          }
+        }
       }
       p.sigt[g.off[lev] + t] = sig ? 1 : 0;
       if (!sig) continue;
@@ -2317,10 +2325,10 @@ void launch_remesh_clear(const Geo& g, const Dev& p, int lo, int hi, hipStream_t
   if (nb > 2048) nb = 2048;
   k_clear_w<<<(unsigned)nb, TPB, 0, s>>>(g, p, lo, hi);
 }
-void launch_detail_seed(const Geo& g, const Dev& p, int la, int hi, hipStream_t s) {
+void launch_detail_seed(const Geo& g, const Dev& p, int la, int hi, int n_it, hipStream_t s) {
   if (la > hi) return;
   const int lo = la > g.l0 ? la - 1 : la;
-  DISPATCH_D(k_detail_seed, g.B * g.n[hi], g, p, lo, hi, la);
+  DISPATCH_D(k_detail_seed, g.B * g.n[hi], g, p, lo, hi, la, n_it);
 }
 // dense passes: 16 cells per lane on levels with >= 2^20 cells (where the
 // block summaries let whole blocks be skipped), one cell per lane below (so

@@ -109,7 +109,16 @@ struct Dev {
   unsigned* lflag;          // [MRD_MAXLEV + 1] level flags (kernels.hip, LF_*)
   double* vel;              // [2B] flames: velocity along axis 0 this macro step, then v_f
   double* vfpart;           // [compaction blocks] flames: partial integrals of omega
+  // near-threshold decisions |D - eps_l| <= 1e-12 eps_l: entry j is
+  // near[2j] = fine iterations completed before the remesh,
+  // near[2j+1] = inst << 45 | level << 40 | Morton key; near_n counts them
+  // (entries beyond NEAR_CAP are counted, not stored)
+  unsigned long long* near;
+  unsigned long long* near_n;
+  const long long* iterb;   // fine iterations completed before the current macro step
 };
+
+#define NEAR_CAP 65536
 
 // ---- launchers (kernels.hip) -------------------------------------------
 void launch_fill_status(const Geo& g, const Dev& p, int lev, uint8_t v, hipStream_t s);
@@ -135,7 +144,9 @@ void launch_remesh_clear(const Geo& g, const Dev& p, int lo, int hi, hipStream_t
 void launch_level_w(const Geo& g, const Dev& p, int la, hipStream_t s);
 // details of the internal nodes of levels la..hi and the seed of W, with the
 // scale safety of the frozen level la - 1
-void launch_detail_seed(const Geo& g, const Dev& p, int la, int hi, hipStream_t s);
+// n_it: fine iteration of the macro step (0 outside a macro step), recorded
+// with near-threshold decisions
+void launch_detail_seed(const Geo& g, const Dev& p, int la, int hi, int n_it, hipStream_t s);
 // flames: v_f of every instance from its leaves; vel = flame_speed * v_f
 void launch_flame_speed(const Geo& g, const Dev& p, hipStream_t s);
 // lists of levels lo..L; full: rebuild without trusting the block summaries

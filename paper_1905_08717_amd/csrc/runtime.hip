@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -36,6 +37,9 @@ struct mr_ctx {
   bool use_graph = true;              // replay the captured macro step
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
+  long long* iterb_d = nullptr;       // fine iterations before the current macro step
+  long long iter_upload = 0;          // host copy of it, written only before an upload
+  std::vector<int64_t> it_start;      // per instance: iterations at its last load / set
   int timed_class = 0;          // kernel class under HIP-event timing (0: none)
   std::vector<hipEvent_t> ev;   // event pairs around timed launches
   size_t ev_used = 0;
@@ -117,13 +121,23 @@ void refresh_lists(mr_ctx* c, int la, bool full) {
   timed(c, MR_KC_REMESH, [&] { launch_compact(c->g, c->p, la, full, c->stream); });
 }
 
-// remesh with levels below la frozen; statuses, new values and lists
-void remesh(mr_ctx* c, int la) {
+// the iteration count the detail kernel records with near-threshold
+// decisions: iterations completed before the macro step (or remesh) that
+// follows on the stream
+mr_status upload_iter_base(mr_ctx* c) {
+  c->iter_upload = (long long)c->iters;
+  return hip_check(c, hipMemcpyAsync(c->iterb_d, &c->iter_upload, sizeof(long long), hipMemcpyHostToDevice, c->stream),
+                   "iteration upload");
+}
+
+// remesh with levels below la frozen; statuses, new values and lists;
+// n_it: fine iteration of the macro step (0 outside one)
+void remesh(mr_ctx* c, int la, int n_it = 0) {
   const Geo& g = c->g;
   if (la > g.L - 1) return;
   hipStream_t s = c->stream;
   timed(c, MR_KC_REMESH, [&] { launch_remesh_clear(g, c->p, la, g.L - 1, s); });
-  timed(c, MR_KC_REMESH, [&] { launch_detail_seed(g, c->p, la, g.L - 1, s); });
+  timed(c, MR_KC_REMESH, [&] { launch_detail_seed(g, c->p, la, g.L - 1, n_it, s); });
   for (int lev = g.L - 2; lev >= la; lev--) timed(c, MR_KC_REMESH, [&] { launch_close(g, c->p, lev, s); });
   for (int lev = la; lev <= g.L - 1; lev++) timed(c, MR_KC_REMESH, [&] { launch_prune(g, c->p, lev, la, s); });
   timed(c, MR_KC_REMESH, [&] { launch_level_w(g, c->p, la, s); });
@@ -153,14 +167,14 @@ void stage_launch(mr_ctx* c, int lo, int hi, int st, bool bulk, bool iface, int 
     timed(c, cls, [&] { launch_stage(g, c->p, lo, hi < g.L ? hi : g.L - 1, st, 1, s); });
 }
 
-void mr_iteration(mr_ctx* c) {
+void mr_iteration(mr_ctx* c, int n_it) {
   const Geo& g = c->g;
   const int L = g.L;
   hipStream_t s = c->stream;
   auto stage = [&](int st) { stage_launch(c, g.l0, L, st, true, true, st == g.rk ? g.l0 : MRD_MAXLEV + 1); };
   project_range(c, L - 1, g.l0, PJ_Q0);
   if (c->s.remesh && g.l0 <= L - 1) {
-    remesh(c, g.l0);
+    remesh(c, g.l0, n_it);
     project_range(c, L - 1, g.l0, PJ_Q0);
   }
   ghost_fill(c, g.l0, 1);
@@ -181,7 +195,7 @@ void lt_iteration(mr_ctx* c, int64_t n, int64_t N) {
   const Geo& g = c->g;
   const int L = g.L;
   if (!g.lt) {
-    mr_iteration(c);
+    mr_iteration(c, (int)n);
     return;
   }
   const int lmin = lmin_of(g, n);
@@ -190,7 +204,7 @@ void lt_iteration(mr_ctx* c, int64_t n, int64_t N) {
   const int lnext = (n + 1 == N) ? g.l0 : lmin_of(g, n + 1);
   project_range(c, L - 1, lmin, PJ_Q0);
   if (c->s.remesh && lmin <= L - 1) {
-    remesh(c, lmin);
+    remesh(c, lmin, (int)n);
     project_range(c, L - 1, lmin, PJ_Q0);
   }
   hipStream_t s = c->stream;
@@ -253,6 +267,8 @@ mr_status check_flags(mr_ctx* c) {
 
 mr_status adapt_impl(mr_ctx* c) {
   const Geo& g = c->g;
+  mr_status st0 = upload_iter_base(c);
+  if (st0 != MR_OK) return st0;
   project_range(c, g.L - 1, g.l0, PJ_Q0);
   if (g.l0 <= g.L - 1) remesh(c, g.l0);
   else refresh_lists(c, g.l0, true);
@@ -431,6 +447,7 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
   c->t.assign(n_inst, 0.0);
   c->dt_host.assign(n_inst, 0.0);
   c->cnt_host.assign((size_t)n_inst * CNT_PER_INST, 0);
+  c->it_start.assign(n_inst, 0);
   c->max_blocks = (int)((g.n[L] + 255) / 256);
 
   mr_status st = MR_OK;
@@ -469,9 +486,13 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
   ALLOC(c->p.lflag, unsigned, MRD_MAXLEV + 1);
   ALLOC(c->p.vel, double, 2 * n_inst);
   if (flame) ALLOC(c->p.vfpart, double, g.comp_first[L + 1]);
+  ALLOC(c->p.near, unsigned long long, 2 * NEAR_CAP);
+  ALLOC(c->p.near_n, unsigned long long, 1);
+  ALLOC(c->iterb_d, long long, 1);
 #undef ALLOC
   c->p.dt = c->dt_d;
   c->p.eps = c->eps_d;
+  c->p.iterb = c->iterb_d;
   // the zero fills of the allocations are queued on the context's own
   // non-blocking stream, which does not order with the null stream: the
   // upload goes behind them on the same stream (a blocking hipMemcpy could
@@ -514,9 +535,11 @@ mr_status mr_load_finest(mr_ctx* c, const double* q0, void* hip_stream) {
   launch_clear_regs(g, c->p, c->stream);
   refresh_lists(c, g.l0, true);
   HIPCHK(c, hipMemsetAsync(c->p.cnt, 0, sizeof(unsigned long long) * g.B * CNT_PER_INST, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->p.near_n, 0, sizeof(unsigned long long), c->stream));
   mr_status st = check_launch(c, "load_finest");
   if (st != MR_OK) return st;
   std::fill(c->t.begin(), c->t.end(), 0.0);
+  std::fill(c->it_start.begin(), c->it_start.end(), 0);
   c->iters = 0;
   c->broken = false;
   c->err.clear();
@@ -535,6 +558,11 @@ mr_status mr_load_finest_inst(mr_ctx* c, int inst, const double* q0) {
   k_reset_counters<<<1, 64, 0, c->stream>>>(c->p.cnt, inst);
   refresh_lists(c, g.l0, true);
   project_range(c, g.L - 1, g.l0, PJ_Q0);
+  c->it_start[inst] = c->iters;
+  {
+    mr_status su = upload_iter_base(c);
+    if (su != MR_OK) return su;
+  }
   if (g.l0 <= g.L - 1) {
     // only this instance is remeshed; the others keep their trees
     g.i0 = inst;
@@ -608,6 +636,10 @@ mr_status mr_lt_step_batch(mr_ctx* c, const double* dt) {
   c->dt_host.assign(dt, dt + c->g.B);
   HIPCHK(c, hipMemcpyAsync(c->dt_d, c->dt_host.data(), sizeof(double) * c->g.B, hipMemcpyHostToDevice, c->stream));
   const int64_t N = (int64_t)1 << (c->g.L - c->g.l0);
+  {
+    mr_status su = upload_iter_base(c);
+    if (su != MR_OK) return su;
+  }
   // The launch sequence of a macro step depends only on the iteration index
   // and the kernels read counts, lists and dt from device memory, so the whole
   // macro step is captured once into a HIP graph and replayed.
@@ -799,6 +831,7 @@ mr_status mr_set_leaves_inst(mr_ctx* c, int inst, const uint64_t* keys, const do
   if (st != MR_OK) return st;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->t[inst] = t;
+  c->it_start[inst] = c->iters;
   c->broken = false;
   c->err.clear();
   return MR_OK;
@@ -837,6 +870,43 @@ mr_status mr_stats_inst(mr_ctx* c, int inst, mr_stats_t* out) {
 }
 
 mr_status mr_stats(mr_ctx* c, mr_stats_t* out) { return mr_stats_inst(c, 0, out); }
+
+mr_status mr_near_threshold(mr_ctx* c, int inst, int64_t* iter, int32_t* level, uint64_t* key, int64_t cap,
+                            int64_t* n) {
+  if (!c || !n || inst < 0 || inst >= c->g.B) return MR_EINVAL;
+  unsigned long long cnt = 0;
+  HIPCHK(c, hipMemcpyAsync(&cnt, c->p.near_n, sizeof cnt, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (cnt > NEAR_CAP) return set_err(c, MR_ECAPACITY, "near-threshold list overflowed (more than 65536 decisions)");
+  std::vector<unsigned long long> raw(2 * (size_t)cnt + 2);
+  if (cnt) {
+    HIPCHK(c, hipMemcpyAsync(raw.data(), c->p.near, sizeof(unsigned long long) * 2 * cnt, hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  struct E { int64_t it; int32_t lev; uint64_t key; };
+  std::vector<E> v;
+  for (unsigned long long j = 0; j < cnt; j++) {
+    const unsigned long long w = raw[2 * j + 1];
+    const int64_t it = (int64_t)raw[2 * j];
+    if ((int)(w >> 45) != inst || it < c->it_start[inst]) continue;
+    v.push_back(E{it - c->it_start[inst], (int32_t)((w >> 40) & 31u), w & ((1ull << 40) - 1)});
+  }
+  std::sort(v.begin(), v.end(), [](const E& a, const E& b) {
+    if (a.it != b.it) return a.it < b.it;
+    if (a.lev != b.lev) return a.lev < b.lev;
+    return a.key < b.key;
+  });
+  *n = (int64_t)v.size();
+  if (!iter || !level || !key) return MR_OK;
+  if (cap < (int64_t)v.size()) return set_err(c, MR_ECAPACITY, "near-threshold buffer too small");
+  for (size_t j = 0; j < v.size(); j++) {
+    iter[j] = v[j].it;
+    level[j] = v[j].lev;
+    key[j] = v[j].key;
+  }
+  return MR_OK;
+}
 
 mr_status mr_level_updates(mr_ctx* c, int inst, int64_t* per_level) {
   if (!c || !per_level || inst < 0 || inst >= c->g.B) return MR_EINVAL;

@@ -27,7 +27,7 @@ EXPORTS = [
     "mr_get_leaves_inst", "mr_set_leaves", "mr_set_leaves_inst", "mr_stats", "mr_stats_inst",
     "mr_synchronize", "mr_last_error", "mr_destroy", "mr_level_updates", "mr_timing_start",
     "mr_timing_stop", "mr_load_finest_inst", "mr_clear_instance", "mr_instance_flags", "mr_set_eps",
-    "mr_stage_items", "mr_flame_speed", "mr_set_launch", "mr_get_launch",
+    "mr_stage_items", "mr_flame_speed", "mr_set_launch", "mr_get_launch", "mr_near_threshold",
 ]
 KC = {"stage_finest": 1, "stage": 2, "project": 3, "ghost": 4, "remesh": 5, "finalize": 6, "stage_bulk": 7}
 
@@ -114,6 +114,8 @@ def load_library():
     L.mr_clear_instance.argtypes = [vp, i32]
     L.mr_instance_flags.argtypes = [vp, i32, ctypes.POINTER(i32)]
     L.mr_set_eps.argtypes = [vp, i32, dbl]
+    L.mr_near_threshold.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i32), u64p, i64,
+                                    ctypes.POINTER(i64)]
     L.mr_destroy.argtypes = [vp]
     L.mr_destroy.restype = None
     for name in EXPORTS:
@@ -324,6 +326,22 @@ class Solver:
             "iterations": st.iterations,
             "mass": [st.mass[k] for k in range(self.m)],
         }
+
+    def near_threshold(self, inst: int = 0):
+        """Near-threshold decisions of one instance since its last load /
+        set_leaves: sorted list of (iteration, level, Morton key)."""
+        L = load_library()
+        n = ctypes.c_int64()
+        self._check(L.mr_near_threshold(self._h, inst, None, None, None, 0, ctypes.byref(n)), "mr_near_threshold")
+        it = np.zeros(n.value, dtype=np.int64)
+        lv = np.zeros(n.value, dtype=np.int32)
+        ky = np.zeros(n.value, dtype=np.uint64)
+        if n.value:
+            self._check(L.mr_near_threshold(self._h, inst, it.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                            lv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                            ky.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), n.value,
+                                            ctypes.byref(n)), "mr_near_threshold")
+        return [(int(a), int(b), int(c)) for a, b, c in zip(it, lv, ky)]
 
     def level_updates(self, inst: int = 0):
         arr = (ctypes.c_int64 * (MAXLEV + 1))()

@@ -1,10 +1,19 @@
 """HIP path (through the C ABI) against the CPU oracle, macro step by macro step.
 
-Bar: identical leaf sets (keys, integers, bit-exact) unless a near-threshold
-decision (|detail - eps_l| <= 1e-12 eps_l) was counted; cell averages within
-1e-12 relative L1 per macro step per component (both sides evaluate the same
-expression trees without FP contraction, so the observed difference is
-normally zero).
+Bar, checked after every macro step:
+* PDEs whose fluxes and sources use only +, -, *, / and comparisons (every
+  PDE but the flames): both sides evaluate the same expression trees in
+  IEEE FP64 without contraction, so the leaf sets (keys) and the cell
+  averages must be identical bit for bit, and so must the lists of
+  near-threshold decisions (iteration, level, key).
+* Flames (exp from two different math libraries): every cell average within
+  1e-12 relative (plus 1e-15 of the field's maximum, for values near 0).
+  The leaf sets must be identical unless a near-threshold decision
+  (|detail - eps_l| <= 1e-12 eps_l) was taken in the macro step on either
+  side, and every leaf in only one of the sets lies within 4 cells (at the
+  coarser of the two levels) of a node listed in it; then both sides are
+  set to the oracle's state and the comparison goes on.
+The relative L1 difference per component is reported as well.
 """
 import math
 
@@ -16,6 +25,8 @@ from paper_1905_08717_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 REL_L1 = 1e-12
+REL_ELEM = 1e-12
+INEXACT_PDES = ("flame", "flameball")
 
 
 def _gpu_ok():
@@ -42,17 +53,91 @@ def rel_l1(a, b):
     return num / np.maximum(den, 1e-300)
 
 
+def _decode(dim, key):
+    key = int(key)
+    lev = key >> 56
+    m = key & ((1 << 56) - 1)
+    x = [0, 0, 0]
+    for b in range(20):
+        for a in range(dim):
+            x[a] |= ((m >> (dim * b + a)) & 1) << b
+    return lev, x[:dim]
+
+
+def _bc_periodic(cfg, a):
+    bc = cfg.get("bc", "periodic")
+    side = bc[a] if isinstance(bc, (list, tuple)) else bc
+    side = side[0] if isinstance(side, (list, tuple)) else side
+    return side == "periodic"
+
+
+def near_excuses(cfg, diff_keys, near):
+    """True when every leaf key in diff_keys lies within 4 cells, at the
+    coarser of the two levels, of a node in the near-threshold list."""
+    dim = cfg["dim"]
+    nodes = [(lev, _decode(dim, key)[1]) for _, lev, key in near]
+    for k in diff_keys:
+        lam, x = _decode(dim, k)
+        ok = False
+        for lev, p in nodes:
+            mu = min(lam, lev)
+            a = [xi >> (lam - mu) for xi in x]
+            b = [pi >> (lev - mu) for pi in p]
+            n = 1 << mu
+            dist = 0
+            for ax in range(dim):
+                d = abs(a[ax] - b[ax])
+                if _bc_periodic(cfg, ax):
+                    d = min(d, n - d)
+                dist = max(dist, d)
+            if dist <= 4:
+                ok = True
+                break
+        if not ok:
+            return False
+    return True
+
+
 def compare_state(o, s, inst=0, what=""):
+    """Assert the bar above for one instance; False after a leaf-set
+    difference that near-threshold decisions excuse (the caller re-syncs)."""
+    cfg = o.cfg
     ko, vo = o.get_leaves()
     kg, vg = s.get_leaves(inst)
+    no, ng = o.near_threshold(), s.near_threshold(inst)
     so, sg = o.stats(), s.stats(inst)
-    if not np.array_equal(ko, kg):
-        assert so["near_threshold"] + sg["near_threshold"] > 0, f"{what}: leaf sets differ"
-        return False
+    if cfg["pde"] not in INEXACT_PDES:
+        assert ng == no, f"{what}: near-threshold lists differ: {ng[:5]} vs {no[:5]}"
+        assert np.array_equal(ko, kg), f"{what}: leaf sets differ"
+        bad = np.nonzero(vg != vo)
+        assert bad[0].size == 0, (f"{what}: {bad[0].size} cell averages differ, first at leaf "
+                                  f"{bad[1][0]}: {vg[bad][0]!r} vs {vo[bad][0]!r}")
+    else:
+        if not np.array_equal(ko, kg):
+            diff = np.setxor1d(ko, kg)
+            assert no or ng, f"{what}: leaf sets differ ({diff.size} keys) with no near-threshold decision"
+            assert near_excuses(cfg, diff, no + ng), f"{what}: leaf sets differ away from near-threshold nodes"
+            return False
+        tol = REL_ELEM * np.abs(vo) + 1e-15 * np.abs(vo).max(axis=1, keepdims=True)
+        worst = np.abs(vg - vo) - tol
+        assert np.all(worst <= 0.0), f"{what}: max elementwise excess {worst.max()}"
     err = rel_l1(vg, vo)
-    assert np.all(err <= REL_L1), f"{what}: rel L1 {err}, max abs {np.abs(vg - vo).max()}"
+    assert np.all(err <= REL_L1), f"{what}: rel L1 {err}"
     assert sg["leaf_updates"] == so["leaf_updates"], what
     return True
+
+
+def resync(o, s, inst=0):
+    """Both sides continue from the oracle's state (synchronised leaves)."""
+    ko, vo = o.get_leaves()
+    t = o.stats()["t"]
+    o.set_leaves(ko, vo, t)
+    s.set_leaves(ko, vo, t, inst=inst)
+
+
+def check(o, s, inst=0, what=""):
+    if not compare_state(o, s, inst, what):
+        resync(o, s, inst)
 
 
 def run_pair(mods, cfg, q0, dts, inst_eps=None):
@@ -63,16 +148,36 @@ def run_pair(mods, cfg, q0, dts, inst_eps=None):
     s.load_finest(q0[None])
     print(f"[parity] {cfg.get('name', cfg['pde'])} dim={cfg['dim']} L={cfg['L']} leaves={sum(o.stats()['leaves'])}",
           flush=True)
-    assert compare_state(o, s, what="after load")
+    check(o, s, what="after load")
     for j, dt in enumerate(dts):
         dt = dt(o) if callable(dt) else dt
         o.lt_step(dt)
         s.lt_step(dt)
-        compare_state(o, s, what=f"macro step {j}")
+        check(o, s, what=f"macro step {j}")
     rg = s.reconstruct().cpu().numpy()[0]
     ro = o.reconstruct()
-    assert np.all(rel_l1(rg, ro) <= REL_L1)
+    if cfg["pde"] in INEXACT_PDES:
+        assert np.all(rel_l1(rg, ro) <= REL_L1)
+    else:
+        assert np.array_equal(rg, ro)
     return o, s
+
+
+def test_designed_near_threshold_decision(mods):
+    # a threshold equal to a detail the oracle computed: both sides list the
+    # decision (iteration 0, level 4, the node's key) and keep the same tree
+    mro, _ = mods
+    from tests.trees import morton_encode
+    cfg = W.nagumo_2d(L=6, eps=0.0)
+    q0 = W.nagumo_front(6)
+    o = mro.Oracle(cfg)
+    o.load_finest(q0)
+    D = o.details(4)
+    i = int(np.argsort(D)[-40])
+    eps = D[i] * 4.0                       # eps_5 = 2^{2 (5 - 6)} eps = D exactly
+    cfg = dict(cfg, eps=eps)
+    o2, s = run_pair(mods, cfg, q0, [W.nagumo_dt(cfg)] * 2)
+    assert (0, 4, morton_encode(2, (i % 16, i // 16))) in s.near_threshold()
 
 
 def test_burgers_1d_full_config_to_t_final(mods):
@@ -179,7 +284,7 @@ def test_advection_centered_frozen_two_level_tree(mods):
     for _ in range(20):
         o.lt_step(1.6e-4)
         s.lt_step(1.6e-4)
-    assert compare_state(o, s)
+    check(o, s)
 
 
 @pytest.mark.parametrize("dim", [1, 2])
@@ -198,7 +303,7 @@ def test_linear_diffusion_designed_tree(mods, dim):
     for _ in range(2):
         o.lt_step(dt)
         s.lt_step(dt)
-        assert compare_state(o, s)
+        check(o, s)
 
 
 def test_batch_instances_equal_solo_runs(mods):
@@ -218,7 +323,7 @@ def test_batch_instances_equal_solo_runs(mods):
         s.lt_step(dt)
         for i in range(4):
             orc[i].lt_step(dt)
-            assert compare_state(orc[i], s, inst=i, what=f"instance {i}")
+            check(orc[i], s, inst=i, what=f"instance {i}")
 
 
 @pytest.mark.parametrize("case", ["nagumo2d", "euler3d", "burgers2d_dirichlet", "burgers2d_periodic"])
@@ -257,7 +362,7 @@ def test_wide_batch_against_oracle(mods, case):
         s.lt_step(dt)
         for i in sample:
             orc[i].lt_step(dt)
-            assert compare_state(orc[i], s, inst=i, what=f"instance {i}, macro step {j}")
+            check(orc[i], s, inst=i, what=f"instance {i}, macro step {j}")
 
 
 def test_checkpoint_resume_bit_identical(mods):
@@ -330,12 +435,12 @@ def test_large_batch_thresholds_take_effect(mods):
         o = mro.Oracle(cfg)
         o.load_finest(q[i])
         assert o.stats()["leaves"][9] < (1 << 18) // 4       # an adapted tree
-        assert compare_state(o, s, inst=i, what=f"instance {i} after load")
+        check(o, s, inst=i, what=f"instance {i} after load")
         oracles.append(o)
     s.lt_step(dt)
     for i, o in zip(sample, oracles):
         o.lt_step(dt)
-        compare_state(o, s, inst=i, what=f"instance {i} after one macro step")
+        check(o, s, inst=i, what=f"instance {i} after one macro step")
     s.close()
 
 
@@ -409,12 +514,12 @@ def test_admission_into_running_batch_keeps_others_identical(mods):
         s.lt_step(dt)
         for i in range(3):
             solo[i].lt_step(dt)
-            assert compare_state(solo[i], s, inst=i, what=f"instance {i}")
+            check(solo[i], s, inst=i, what=f"instance {i}")
     s.clear_instance(0)
     s.lt_step(dt)
     for i in (1, 2):
         solo[i].lt_step(dt)
-        assert compare_state(solo[i], s, inst=i, what=f"after clearing 0, instance {i}")
+        check(solo[i], s, inst=i, what=f"after clearing 0, instance {i}")
 
 
 def test_batched_and_served_results_equal_solo(mods):
@@ -519,7 +624,7 @@ def test_flame_ball_wide_batch(mods):
         s.lt_step(dt)
         for i in sample:
             orc[i].lt_step(dt)
-            assert compare_state(orc[i], s, inst=i, what=f"instance {i}, macro step {j}")
+            check(orc[i], s, inst=i, what=f"instance {i}, macro step {j}")
             _check_flame_speed(orc[i], s, inst=i)
 
 
@@ -569,7 +674,7 @@ def test_flame_batch_of_thresholds(mods):
         s.lt_step(dt)
         for i, o in enumerate(orc):
             o.lt_step(dt)
-            assert compare_state(o, s, inst=i, what=f"instance {i}, macro step {j}")
+            check(o, s, inst=i, what=f"instance {i}, macro step {j}")
             _check_flame_speed(o, s, inst=i)
 
 

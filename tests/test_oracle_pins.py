@@ -299,12 +299,34 @@ def test_table1_fv_rk3_third_order(oracle_mod):
 
 def test_table1_mrlt_nerk3_second_order(oracle_mod):
     # the paper: MRLT/NERK3 converges with order 2 (third order is lost at the
-    # level interface, eqs. EvRk3finer / EvRk3coarser); the pre-asymptotic
-    # value depends on synchronisation details, so the pin is the trend to 2.
-    p1 = _order(oracle_mod, 1.6e-4, uniform=False)
-    p2 = _order(oracle_mod, 0.8e-4, uniform=False)
-    assert 1.75 < p2 < p1 < 2.6
-    assert abs(p2 - 2.0) < 0.3
+    # level interface, eqs. EvRk3finer / EvRk3coarser).  The printed values
+    # (1.7895, 1.9152) approach 2 from below; every reading of the paper's
+    # open synchronisation choices scanned with tests/table1_readings.py
+    # approaches it from above (2.01-2.94 at dt = 1.6e-4), so the pin is the
+    # monotone approach to the limit order 2 over four halvings.
+    p = [_order(oracle_mod, 1.6e-4 / 2 ** j, uniform=False) for j in range(3)]
+    assert p[0] > p[1] > p[2] > 2.0
+    assert abs(p[2] - 2.0) < 0.12
+    assert abs(p[1] - 2.0) < 0.3
+
+
+def test_table1_model_matches_oracle(oracle_mod):
+    """The vectorised model of the Table 1 experiment used to scan the
+    synchronisation readings takes the oracle's readings by default and
+    gives its values bit for bit."""
+    from tests.table1_readings import run
+    dt = 1.6e-4
+    cfg = dict(dim=1, L=9, l0=8, eps=0.0, pde="advection", adv_vel=[1.0, 0, 0],
+               bc="periodic", recon=2, reflux=0, remesh=0)
+    o = oracle_mod.Oracle(cfg)
+    a9, a8 = _gauss_avg(9), _gauss_avg(8)
+    leaves = [(9, (i,)) for i in range(256)] + [(8, (i,)) for i in range(128, 256)]
+    leaves.sort(key=lambda lx: leaf_key(lx[0], 1, lx[1]))
+    keys, vals = leaf_arrays(1, leaves, lambda lev, x: [(a9 if lev == 9 else a8)[x[0]]])
+    o.set_leaves(keys, vals)
+    for _ in range(60):
+        o.lt_step(dt)
+    assert np.array_equal(o.reconstruct()[0], run(dt, iters=120))
 
 
 # ---------------------------------------------------------------------------

@@ -223,3 +223,26 @@ def test_remesh_of_synchronised_data_keeps_the_adapted_tree(oracle_mod, case):
         o.remesh(la)
         for lev in range(l0, L + 1):
             assert np.array_equal(o.level(lev)[0], ref[lev]), (la, lev)
+
+
+def test_near_threshold_decision_is_recorded(oracle_mod):
+    """A threshold equal to a computed detail (Alg. waveletThres keeps a
+    node only when its detail exceeds the threshold): the node is not
+    significant, and the decision is listed as near the threshold with the
+    iteration, level and Morton key of the node."""
+    from tests.trees import morton_encode
+    cfg = W.nagumo_2d(L=6, eps=0.0)
+    q0 = W.nagumo_front(6)
+    o = oracle_mod.Oracle(cfg)
+    o.load_finest(q0)
+    assert o.near_threshold() == []          # eps = 0: no threshold test
+    D = o.details(4)                          # level-4 nodes, details of level-5 children
+    i = int(np.argsort(D)[-40])               # a node well inside the front
+    assert D[i] > 0
+    eps = D[i] * 4.0                          # eps_5 = 2^{2 (5 - 6)} eps = D exactly
+    o2 = oracle_mod.Oracle(dict(cfg, eps=eps))
+    o2.load_finest(q0)
+    key = morton_encode(2, (i % 16, i // 16))
+    near = o2.near_threshold()
+    assert (0, 4, key) in near
+    assert o2.stats()["near_threshold"] == len(near)
