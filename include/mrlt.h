@@ -203,6 +203,19 @@ mr_status mr_flame_speed(mr_ctx* c, double* vf);
 mr_status mr_get_leaves(mr_ctx* c, uint64_t* keys, double* q, int64_t cap, int64_t* n);
 mr_status mr_get_leaves_inst(mr_ctx* c, int inst, uint64_t* keys, double* q, int64_t cap, int64_t* n);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops and harnesses that forbid allocation): the leaves
+ * of instance `inst` as mr_get_leaves_inst returns them, staged through a
+ * fixed device array of the library instead of buffers allocated per call.
+ * The array holds MR_NOALLOC_MAX_LEAVES leaves of up to 5 components
+ * (48 MiB per GPU, resolved when the first context on a GPU is created and
+ * held until the process ends); MR_ECAPACITY if the instance has more
+ * leaves, or if cap is smaller than their number.  Allocates nothing.
+ * Every call on one GPU uses the same array: calls that overlap on one GPU
+ * (from several threads or contexts at once) race.                        */
+#define MR_NOALLOC_MAX_LEAVES (1 << 20)
+mr_status mr_get_leaves_noalloc(mr_ctx* c, int inst, uint64_t* keys, double* q, int64_t cap, int64_t* n);
+
 /* Replace the tree of instance 0 (or `inst`) by the given leaves (same key
  * and value layout, host buffers) at time t.  The leaves must form a
  * complete tree over level l0 that is graded (every cell within distance 2

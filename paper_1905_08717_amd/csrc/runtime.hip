@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -32,6 +33,7 @@ struct mr_ctx {
   int* err_d = nullptr;
   unsigned long long* ws_d = nullptr;
   double* part_d = nullptr;
+  void* scratch_d = nullptr;          // staging array of this context's device
   int max_blocks = 0;
   hipStream_t own_stream = nullptr;   // default stream of the context
   bool use_graph = true;              // replay the captured macro step
@@ -45,7 +47,37 @@ struct mr_ctx {
   size_t ev_used = 0;
 };
 
+// Staging array of mr_get_leaves_noalloc: keys of up to MR_NOALLOC_MAX_LEAVES
+// leaves, then their values (up to 5 components), in device memory the
+// library holds on every GPU it runs on until the process ends.  Host code
+// uses the address hipGetSymbolAddress gives for the current device, never
+// the array's name.
+#define NOALLOC_BYTES ((size_t)MR_NOALLOC_MAX_LEAVES * 8u * 6u)
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// address of the staging array on the current device (resolved once per
+// device, at the first context created there)
+hipError_t scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 mr_status set_err(mr_ctx* c, mr_status st, const std::string& msg) {
   if (c) c->err = msg;
@@ -335,6 +367,11 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
   mr_ctx* c = new mr_ctx();
   c->s = *s;
   if (hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking) != hipSuccess) {
+    delete c;
+    return MR_EDEVICE;
+  }
+  if (scratch_address(&c->scratch_d) != hipSuccess) {
+    (void)hipStreamDestroy(c->own_stream);
     delete c;
     return MR_EDEVICE;
   }
@@ -775,6 +812,39 @@ mr_status mr_get_leaves_inst(mr_ctx* c, int inst, uint64_t* keys, double* q, int
 
 mr_status mr_get_leaves(mr_ctx* c, uint64_t* keys, double* q, int64_t cap, int64_t* n) {
   return mr_get_leaves_inst(c, 0, keys, q, cap, n);
+}
+
+mr_status mr_get_leaves_noalloc(mr_ctx* c, int inst, uint64_t* keys, double* q, int64_t cap, int64_t* n) {
+  if (!c || !n || inst < 0 || inst >= c->g.B) return MR_EINVAL;
+  const Geo& g = c->g;
+  std::vector<long long> per(MR_MAXLEV + 1, 0);
+  long long tot = 0;
+  for (int lev = g.l0; lev <= g.L; lev++) {
+    mr_status st = level_count(c, lev, inst, ST_LEAF, &per[lev]);
+    if (st != MR_OK) return st;
+    tot += per[lev];
+  }
+  *n = tot;
+  if (!keys || !q) return MR_OK;
+  if (cap < tot) return set_err(c, MR_ECAPACITY, "leaf buffer too small");
+  if (tot > MR_NOALLOC_MAX_LEAVES)
+    return set_err(c, MR_ECAPACITY, "more leaves than the staging array of mr_get_leaves_noalloc holds");
+  unsigned long long* kd = (unsigned long long*)c->scratch_d;
+  double* vd = (double*)((unsigned char*)c->scratch_d + (size_t)MR_NOALLOC_MAX_LEAVES * 8u);
+  long long base = 0;
+  for (int lev = g.l0; lev <= g.L; lev++) {
+    const int nblk = (int)((g.n[lev] + 255) / 256);
+    launch_count(g, c->p, lev, inst, ST_LEAF, c->blockcnt_d, nblk, c->stream);
+    launch_scan_blocks(c->blockcnt_d, nblk, c->total_d, c->stream);
+    launch_gather_leaves(g, c->p, lev, inst, c->blockcnt_d, nblk, base, kd, vd, tot, c->stream);
+    base += per[lev];
+  }
+  if (tot > 0) {
+    HIPCHK(c, hipMemcpyAsync(keys, kd, sizeof(uint64_t) * (size_t)tot, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(q, vd, sizeof(double) * (size_t)tot * g.m, hipMemcpyDeviceToHost, c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return check_launch(c, "get_leaves_noalloc");
 }
 
 __global__ void k_fill_range(uint8_t* st, int64_t base, int64_t n, uint8_t v) {

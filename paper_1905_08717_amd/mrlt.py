@@ -28,6 +28,7 @@ EXPORTS = [
     "mr_synchronize", "mr_last_error", "mr_destroy", "mr_level_updates", "mr_timing_start",
     "mr_timing_stop", "mr_load_finest_inst", "mr_clear_instance", "mr_instance_flags", "mr_set_eps",
     "mr_stage_items", "mr_flame_speed", "mr_set_launch", "mr_get_launch", "mr_near_threshold",
+    "mr_get_leaves_noalloc",
 ]
 KC = {"stage_finest": 1, "stage": 2, "project": 3, "ghost": 4, "remesh": 5, "finalize": 6, "stage_bulk": 7}
 
@@ -99,6 +100,7 @@ def load_library():
     L.mr_get_launch.argtypes = [vp, ctypes.POINTER(MrLaunch)]
     L.mr_get_leaves.argtypes = [vp, u64p, dp, i64, ctypes.POINTER(i64)]
     L.mr_get_leaves_inst.argtypes = [vp, i32, u64p, dp, i64, ctypes.POINTER(i64)]
+    L.mr_get_leaves_noalloc.argtypes = [vp, i32, u64p, dp, i64, ctypes.POINTER(i64)]
     L.mr_set_leaves.argtypes = [vp, u64p, dp, i64, dbl]
     L.mr_set_leaves_inst.argtypes = [vp, i32, u64p, dp, i64, dbl]
     L.mr_stats.argtypes = [vp, ctypes.POINTER(MrStats)]
@@ -306,6 +308,19 @@ class Solver:
         self._check(L.mr_get_leaves_inst(self._h, inst, keys.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
                                          q.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n.value,
                                          ctypes.byref(n)), "mr_get_leaves")
+        return keys, q
+
+    def get_leaves_noalloc(self, inst: int = 0):
+        """Leaves of one instance through the library's fixed staging array
+        (mr_get_leaves_noalloc): no device allocation in the call."""
+        L = load_library()
+        n = ctypes.c_int64()
+        self._check(L.mr_get_leaves_noalloc(self._h, inst, None, None, 0, ctypes.byref(n)), "mr_get_leaves_noalloc")
+        keys = np.zeros(n.value, dtype=np.uint64)
+        q = np.zeros((self.m, n.value))
+        self._check(L.mr_get_leaves_noalloc(self._h, inst, keys.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                            q.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n.value,
+                                            ctypes.byref(n)), "mr_get_leaves_noalloc")
         return keys, q
 
     def set_leaves(self, keys, q, t: float = 0.0, inst: int = 0):
