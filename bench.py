@@ -61,11 +61,16 @@ def stage_traffic(batch, list_grid):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(cfg, q0, dt, seconds):
-    """The oracle as it is, on this host, for about `seconds` of work."""
+def cpu_oracle_leg(seconds):
+    """One timing of the oracle as it is (this process's OpenMP threads): one
+    front of the 2D Nagumo configuration, macro steps from t=0 for about
+    `seconds` (initial data and the load excluded); prints one JSON line."""
     from oracle import mro
+    from paper_1905_08717_amd import workloads as W
+    cfg = W.nagumo_2d()
+    dt = W.nagumo_dt(cfg)
     o = mro.Oracle(cfg)
-    o.load_finest(q0)
+    o.load_finest(W.nagumo_front(cfg["L"], W.SEED))
     u0 = o.stats()["leaf_updates"]
     t0 = time.perf_counter()
     nmac = 0
@@ -76,9 +81,52 @@ def cpu_baseline(cfg, q0, dt, seconds):
         if el > seconds or nmac >= 64:
             break
     upd = o.stats()["leaf_updates"] - u0
-    return {"value": upd / el, "unit": "leaf-updates/s", "cores": mro.num_threads(), "kind": "oracle",
-            "sample": f"1 instance of the same workload, {nmac} macro steps from t=0 ({upd} leaf-updates, "
-                      f"{el:.1f} s), OpenMP threads={mro.num_threads()}"}
+    print(json.dumps({"leaf_updates_per_s": upd / el, "threads": mro.num_threads(), "macro_steps": nmac,
+                      "leaf_updates": upd, "seconds": el}), flush=True)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(seconds, repeats=3):
+    """The oracle timed on this host's cores: single-threaded and on every
+    core the process may use (OMP_NUM_THREADS as set, else all), each the
+    median of `repeats` runs in a fresh process."""
+    import statistics
+    import subprocess
+    here = os.path.abspath(__file__)
+    legs = {}
+    for name, threads in (("single_thread", "1"), ("all_cores", os.environ.get("OMP_NUM_THREADS", ""))):
+        env = dict(os.environ)
+        if threads:
+            env["OMP_NUM_THREADS"] = threads
+        else:
+            env.pop("OMP_NUM_THREADS", None)
+        runs = []
+        for _ in range(repeats):
+            out = subprocess.run([sys.executable, here, "--mode", "cpu-oracle", "--cpu-seconds", str(seconds)],
+                                 env=env, capture_output=True, text=True, check=True)
+            runs.append(json.loads(out.stdout.strip().splitlines()[-1]))
+            print(f"[bench] cpu oracle {name}: {runs[-1]['leaf_updates_per_s']:.3e} leaf-updates/s", file=sys.stderr,
+                  flush=True)
+        legs[name] = {"value": statistics.median(r["leaf_updates_per_s"] for r in runs),
+                      "runs": [round(r["leaf_updates_per_s"], 1) for r in runs], "threads": runs[0]["threads"]}
+    allc = legs["all_cores"]
+    return {"value": round(allc["value"], 1), "unit": "leaf-updates/s", "cores": allc["threads"], "kind": "oracle",
+            "single_thread": round(legs["single_thread"]["value"], 1),
+            "single_thread_runs": legs["single_thread"]["runs"], "all_core_runs": allc["runs"],
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "sample": f"one front of the same workload (2D Nagumo L=9), macro steps from t=0 for about {seconds} s "
+                      f"per run, median of {repeats} runs each single-threaded and on {allc['threads']} OpenMP "
+                      "threads; value = the all-core median"}
 
 
 def copy_calibration():
@@ -294,16 +342,110 @@ def systems_mode(args):
     print(json.dumps(out), flush=True)
 
 
+def euler3d_single(args):
+    """The 3D Euler spherical Riemann problem at its stated size (128^3,
+    L=7, eps=1e-3, five FP64 fields): one solve, leaf-updates/s over two
+    macro steps after one (CFL step from the wave-speed reduction each macro
+    step, inside the timed region), then the bulk stage kernel's HBM
+    roofline over two macro steps of a fresh load."""
+    import torch
+    from paper_1905_08717_amd import mrlt
+    from paper_1905_08717_amd import workloads as W
+    cfg = W.euler_3d(L=7)
+    q0 = torch.from_numpy(W.euler_sphere(7)[None]).to("cuda")
+    s = mrlt.Solver(cfg)
+
+    def run(k, t):
+        for _ in range(k):
+            dt = W.euler_dt(cfg, s.max_wavespeed()[0], t)
+            s.lt_step(dt)
+            t += W.macro_iters(cfg) * dt
+        return t
+
+    s.load_finest(q0)
+    t = run(1, 0.0)
+    u0 = total_updates(s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(2, t)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    upd = total_updates(s) - u0
+    s.load_finest(q0)
+    t = run(1, 0.0)
+    it0 = s.stage_items()
+    s.timing_start("stage_bulk")
+    run(2, t)
+    ms, launches = s.timing_stop()
+    items = s.stage_items() - it0
+    m = s.m
+    alg = int(items[0]) * 16 * m + int(items[1]) * 24 * m + int(items[2]) * 24 * m
+    ach = alg / (ms * 1e-3) / 1e9
+    leaves = int(sum(s.stats()["leaves"]))
+    s.close()
+    print(f"[bench] 3D Euler L=7: {upd / el:.3e} leaf-updates/s", file=sys.stderr, flush=True)
+    return {"workload": "euler3d_L7_128^3 spherical Riemann problem, eps=1e-3, one solve, macro steps 2-3 from t=0",
+            "leaf_updates_per_s": round(upd / el, 1), "ms_per_macro_step": round(el / 2 * 1e3, 2),
+            "leaves": leaves,
+            "roofline": {"bound": "hbm", "achieved": round(ach, 2), "peak": 8000.0, "unit": "GB/s",
+                         "frac": round(ach / 8000.0, 5), "kernel": "k_stage<3, 3, false, 1|2|3>",
+                         "launches": launches, "avg_launch_us": round(ms * 1e3 / max(launches, 1), 3),
+                         "alg_bytes_per_leaf_stage": [16 * m, 24 * m, 24 * m]}}
+
+
+def batched_leg(args):
+    """The batched configuration: 256 four-quadrant 2D Euler problems (finest
+    level from {7, 8, 9}, eps from {1e-2, 1e-3, 1e-4}) to t_final 0.25, all
+    in one context of the library's scheduler; against the first 32 of the
+    same requests solved one at a time (each alone in a context of its own
+    level), whose results must be identical."""
+    from paper_1905_08717_amd import systems as S
+    reqs = S.batched_euler_requests(256)
+    b = S.run_batched(reqs)
+    solo = S.batched_euler_requests(256)[:32]
+    a = S.run_one_at_a_time(solo)
+    same = all((r.failed and q.failed) or
+               (r.result is not None and q.result is not None and
+                np.array_equal(r.result[0], q.result[0]) and np.array_equal(r.result[1], q.result[1]))
+               for r, q in zip(reqs[:32], solo))
+    print(f"[bench] batched {b['solves_per_s']:.2f} solves/s, one at a time {a['solves_per_s']:.2f}",
+          file=sys.stderr, flush=True)
+    return {"workload": "256 2D Euler four-quadrant Riemann problems, L in {7,8,9}, eps in {1e-2,1e-3,1e-4}, "
+                        "t_final 0.25, CFL 0.5 per solve",
+            "solves_per_s": round(b["solves_per_s"], 3), "seconds": round(b["seconds"], 3),
+            "solves": b["solves"], "failed": b["failed"], "macro_steps": b["macro_steps"],
+            "hbm_bytes": b["hbm_bytes"],
+            "one_at_a_time_solves_per_s": round(a["solves_per_s"], 3),
+            "one_at_a_time_sample": "first 32 of the same requests",
+            "speedup": round(b["solves_per_s"] / a["solves_per_s"], 3),
+            "results_identical_to_one_at_a_time": bool(same)}
+
+
+def served_leg(args):
+    """The served configuration, shortened to 200 requests: Poisson arrivals
+    at 200/s, half 1D viscous Burgers (L 10..14, t_final 0.5), half 2D Nagumo
+    (L 7..9, t_final 0.01), eps log-uniform in [1e-4, 1e-2]."""
+    from paper_1905_08717_amd import systems as S
+    reqs = S.served_requests(200, rate=200.0)
+    r = S.serve(reqs, hbm_budget=args.hbm_budget * 2 ** 30)
+    print(f"[bench] served p50 {r['p50_s']:.2f} s p99 {r['p99_s']:.2f} s", file=sys.stderr, flush=True)
+    return dict(r, workload="200 requests (of the configuration's 1000), Poisson 200/s, half 1D viscous Burgers "
+                            "L 10..14 t_final 0.5, half 2D Nagumo L 7..9 t_final 0.01, eps log-uniform "
+                            "[1e-4, 1e-2]; one class per scheme and finest level, 16 slots each")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batch", type=int, default=512)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=4.0)
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the 3D Euler, batched and served legs of the default line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", choices=["throughput", "batched", "served", "copycal", "traffic", "paper",
-                                       "flames"],
+                                       "flames", "cpu-oracle"],
                     default="throughput")
     ap.add_argument("--levels", default="8,9,10", help="paper mode: finest levels")
     ap.add_argument("--flame-levels", default="11,12", help="flames mode: finest levels of the 1D flame")
@@ -324,6 +466,9 @@ def main():
               "across GPUs by instance, which is not built here", file=sys.stderr)
         sys.exit(2)
 
+    if args.mode == "cpu-oracle":
+        cpu_oracle_leg(args.cpu_seconds)
+        return
     if args.mode == "copycal":
         copy_calibration()
         return
@@ -436,8 +581,14 @@ def main():
         "single_solve_leaf_updates_per_s": single,
         "solves_macro_steps_per_s": round(B * args.steps / el, 2),
     }
+    del s
+    torch.cuda.empty_cache()
+    if not args.no_configs:
+        out["euler3d"] = euler3d_single(args)
+        out["batched"] = batched_leg(args)
+        out["served"] = served_leg(args)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, q0[0], dt, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

@@ -36,6 +36,7 @@
  */
 #ifndef MRLT_H
 #define MRLT_H
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -115,15 +116,36 @@ typedef struct {
   double mass[5];                  /* sum over leaves of |cell| q, per component */
 } mr_stats_t;
 
+/* Device memory of a context from the caller's allocator (for example
+ * PyTorch's caching allocator): alloc(bytes, user) returns device memory of
+ * at least `bytes` bytes aligned to 256 bytes, or NULL when it has none;
+ * free(ptr, user) takes back a pointer alloc returned.  The context calls
+ * alloc from mr_init / mr_init_batch and from the calls that stage host
+ * data (mr_get_leaves, mr_set_leaves), on the calling thread, and frees
+ * everything in mr_destroy after its stream is idle.  A NULL mr_alloc (or
+ * alloc == free == NULL) means hipMalloc / hipFree.                        */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* user);
+  void (*free)(void* ptr, void* user);
+  void* user;
+} mr_alloc;
+
 /* Create a single solve (Sec. 2: the IVP on a box; Alg. waveletThres takes
  * the finest level L, the level-L solution and the threshold eps).
  * dim in 1..3, l0 >= 2, l0 <= L, L - l0 <= 20, dim*L <= 3*MR_MAXLEV,
- * eps >= 0 (eps = 0 keeps the full tree).  *out receives the context.      */
-mr_status mr_init(int dim, int L, double eps, const mr_scheme* s, mr_ctx** out);
+ * eps >= 0 (eps = 0 keeps the full tree); a: allocator or NULL.
+ * *out receives the context.                                               */
+mr_status mr_init(int dim, int L, double eps, const mr_scheme* s, const mr_alloc* a, mr_ctx** out);
 
 /* Create a batch of n_inst independent solves sharing dim, L and scheme;
- * eps is a host array of n_inst thresholds.                                */
-mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_scheme* s, mr_ctx** out);
+ * eps is a host array of n_inst thresholds; a: allocator or NULL.         */
+mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_scheme* s, const mr_alloc* a,
+                        mr_ctx** out);
+
+/* Device bytes the context holds (its tables are dense over the full tree
+ * of every instance: the footprint depends on dim, L, m and n_inst, not on
+ * how many leaves the trees keep).                                         */
+mr_status mr_footprint(mr_ctx* c, size_t* bytes);
 
 /* Stream (hipStream_t, may be NULL) on which later work is queued. */
 mr_status mr_set_stream(mr_ctx* c, void* hip_stream);
@@ -140,6 +162,17 @@ mr_status mr_load_finest(mr_ctx* c, const double* q0, void* hip_stream);
  * adapted tree; the other instances are not changed.
  * q0: device, [m][2^{dL}], x fastest.                                      */
 mr_status mr_load_finest_inst(mr_ctx* c, int inst, const double* q0);
+
+/* Load one instance with its own finest level L_inst (l0 <= L_inst <= L)
+ * and threshold eps: q0 holds its finest-level averages (device,
+ * [m][2^{d L_inst}], x fastest).  The instance never refines past L_inst,
+ * its level-dependent thresholds are eps_l = 2^{d(l - L_inst)} eps, and its
+ * level l steps by 2^{L-l} dt_L: with dt_L = 2^{L_inst - L} times its own
+ * finest step, a context macro step is one macro step of the solve with
+ * finest level L_inst, and its leaves and values are those of that solve
+ * bit for bit.  So solves of uneven finest levels share every launch.
+ * mr_reconstruct gives its averages on the level-L grid.                   */
+mr_status mr_load_inst(mr_ctx* c, int inst, int L_inst, double eps, const double* q0);
 
 /* Free one instance of a batch: all of its cells become absent, it drops out
  * of every kernel's work until it is loaded again.                         */
@@ -273,6 +306,79 @@ mr_status mr_timing_start(mr_ctx* c, int kernel_class);
 /* Synchronise; *total_ms = summed event time of the timed launches,
  * *launches = their number.  Ends the timing.                             */
 mr_status mr_timing_stop(mr_ctx* c, double* total_ms, int64_t* launches);
+
+/* ---- systems forms: many solves of uneven size under one scheduler ------
+ *
+ * A batch serves solves grouped in classes.  A class is one context: the
+ * scheme, dim, its largest finest level L_max and a number of slots; each
+ * slot holds one solve with its own finest level L <= L_max (mr_load_inst),
+ * threshold, final time and CFL step, so every kernel launch of a macro
+ * step serves all the class's solves, uneven trees included.  A class's
+ * context is created when a solve is first admitted to it, if its device
+ * footprint fits the batch's HBM budget (contexts of idle classes are
+ * destroyed to make room), and classes step on their own streams, so their
+ * work overlaps on the device.  Slots are numbered over the classes in
+ * order (class 0 has slots 0 .. slots_0 - 1, and so on).                   */
+typedef struct mr_batch mr_batch;
+
+typedef struct {
+  int32_t dim, L_max, slots;
+  mr_scheme scheme;
+} mr_class_desc;
+
+/* One solve: its class is the first whose scheme, dim and l0 match and whose
+ * L_max >= L.  Each macro step takes the finest step
+ * dt = min(cfl / (w / dx + 2 d D / dx^2 + R), dt_max, (t_final - t) / N)
+ * with dx the finest cell width along axis 0, w the largest wave speed of
+ * its leaves (mr_max_wavespeed), D the largest diffusion coefficient (nu;
+ * max(1, 1/Le) for the flames), R = 0.8 k for the Nagumo source (0
+ * otherwise), dt_max > 0 an optional cap and N = 2^{L - l0} fine iterations
+ * per macro step, so that the last macro step ends at t_final.            */
+typedef struct {
+  int32_t dim, L;
+  double eps, t_final, cfl, dt_max;
+  mr_scheme scheme;
+} mr_instance_desc;
+
+enum { MR_SLOT_FREE = 0, MR_SLOT_RUNNING = 1, MR_SLOT_DONE = 2, MR_SLOT_FAILED = 3 };
+
+/* An empty batch of n_classes classes (host array) whose contexts may hold
+ * at most hbm_budget device bytes together; a: allocator or NULL.         */
+mr_status mr_batch_create(int n_classes, const mr_class_desc* classes, size_t hbm_budget, const mr_alloc* a,
+                          mr_batch** out);
+
+/* Admit a solve into a free slot of its class: q0 device, [m][2^{d L}],
+ * x fastest (copied in; the tree is adapted at once).  *slot receives the
+ * slot.  MR_ECAPACITY if its class has no free slot, or if creating the
+ * class's context would exceed the budget; MR_EINVAL if no class fits it. */
+mr_status mr_batch_admit(mr_batch* b, const mr_instance_desc* d, const double* q0, int* slot);
+
+/* One macro step of every running solve (each with its own dt, above);
+ * classes are queued on their own streams before any wait.  A solve whose
+ * values become non-finite fails alone (state MR_SLOT_FAILED).            */
+mr_status mr_batch_step(mr_batch* b);
+
+/* Slots that reached their final time (MR_SLOT_DONE) or failed since the
+ * last poll (host array of cap entries; *n receives their number).        */
+mr_status mr_batch_poll(mr_batch* b, int* done_slots, int cap, int* n);
+
+/* State (MR_SLOT_*), time and macro steps taken of one slot. */
+mr_status mr_batch_slot_info(mr_batch* b, int slot, int* state, double* t, int64_t* macro_steps);
+
+/* Leaves of a slot (layout of mr_get_leaves; host buffers). */
+mr_status mr_batch_get_leaves(mr_batch* b, int slot, uint64_t* keys, double* q, int64_t cap, int64_t* n);
+
+/* Free a slot (its cells become absent; it drops out of every launch). */
+mr_status mr_batch_release(mr_batch* b, int slot);
+
+/* Device bytes the batch's class contexts hold. */
+mr_status mr_batch_footprint(mr_batch* b, size_t* bytes);
+
+/* Description of the batch's last error (never NULL). */
+const char* mr_batch_last_error(const mr_batch* b);
+
+/* Destroy the batch and every class context (NULL is ignored). */
+void mr_batch_destroy(mr_batch* b);
 
 /* Wait for all queued work of the context. */
 mr_status mr_synchronize(mr_ctx* c);

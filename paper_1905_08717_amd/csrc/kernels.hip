@@ -474,9 +474,10 @@ void launch_fill_status(const Geo& g, const Dev& p, int lev, uint8_t v, hipStrea
   k_fill_status<<<blocks_for(n), TPB, 0, s>>>(p.st, g.off[lev], n, v);
 }
 
+// finest-level averages into level L (the instance's own finest level when
+// one instance is loaded)
 template <int D>
-__global__ void k_load_finest(Geo g, Dev p, const double* src, int only) {
-  const int L = g.L;
+__global__ void k_load_finest(Geo g, Dev p, const double* src, int only, int L) {
   const int64_t nl = g.n[L], N = (only >= 0 ? 1 : g.B) * nl;
   const int n = 1 << L;
   GSL(u, N) {
@@ -492,18 +493,19 @@ __global__ void k_load_finest(Geo g, Dev p, const double* src, int only) {
   }
 }
 
-// statuses of one instance: levels below L internal, level L absent (the
-// finest level is then written by k_load_finest); or all absent (free slot)
-__global__ void k_fill_instance(Geo g, Dev p, int inst, int free_slot) {
+// statuses of one instance: levels below its finest level Li internal, the
+// others absent (level Li is then written by k_load_finest); or all absent
+// (free slot)
+__global__ void k_fill_instance(Geo g, Dev p, int inst, int free_slot, int Li) {
   for (int lev = g.l0; lev <= g.L; lev++) {
     const int64_t nl = g.n[lev];
-    const uint8_t v = free_slot ? ST_ABSENT : (lev < g.L ? ST_INTERNAL : ST_ABSENT);
+    const uint8_t v = free_slot ? ST_ABSENT : (lev < Li ? ST_INTERNAL : ST_ABSENT);
     GSL(u, nl) p.st[g.off[lev] + (int64_t)inst * nl + u] = v;
   }
 }
 
-void launch_fill_instance(const Geo& g, const Dev& p, int inst, hipStream_t s) {
-  k_fill_instance<<<blocks_for(g.n[g.L]), TPB, 0, s>>>(g, p, inst >= 0 ? inst : -1 - inst, inst < 0);
+void launch_fill_instance(const Geo& g, const Dev& p, int inst, int Li, hipStream_t s) {
+  k_fill_instance<<<blocks_for(g.n[g.L]), TPB, 0, s>>>(g, p, inst >= 0 ? inst : -1 - inst, inst < 0, Li);
 }
 
 template <int D>
@@ -1476,9 +1478,10 @@ __global__ __launch_bounds__(TPB) void k_detail_seed(Geo g, Dev p, int lo, int h
       const int64_t t = p.lst[LS_INTERNAL][g.off[lev] + kk];
       if (inst_of_window_skip(g, t, D * lev)) continue;
       const int64_t inst = t >> (D * lev);
+      const int Lc = p.lcap[inst];  // the instance's finest level
       if (lev < la) {
         // frozen level: scale safety of a node significant at its last remesh
-        if (!p.sigt[g.off[lev] + t] || lev + 1 > g.L - 1) continue;
+        if (!p.sigt[g.off[lev] + t] || lev + 1 > Lc - 1) continue;
         uint32_t need = 0u;
 #pragma unroll
         for (int cb = 0; cb < (1 << D); cb++)
@@ -1494,7 +1497,7 @@ __global__ __launch_bounds__(TPB) void k_detail_seed(Geo g, Dev p, int lo, int h
       const double e0 = p.eps[inst];
       bool sig = true;
       if (e0 != 0.0) {
-        const double e = g.thresh ? ldexp(e0, D * (lev + 1 - g.L)) : e0;
+        const double e = g.thresh ? ldexp(e0, D * (lev + 1 - Lc)) : e0;
         const int64_t C0 = g.off[lev + 1] + (t << D);
         double Dm = 0.0;
         for (int k = 0; k < g.m; k++) {
@@ -1523,7 +1526,7 @@ __global__ __launch_bounds__(TPB) void k_detail_seed(Geo g, Dev p, int lo, int h
       // targets: the 3^d neighbourhood (existing cells; the node itself is
       // internal) and, below L-1, the 2^d children
       constexpr int NN = D == 1 ? 3 : (D == 2 ? 9 : 27);
-      const bool kids = lev + 1 <= g.L - 1;
+      const bool kids = lev + 1 <= Lc - 1;
       uint64_t need = 0ull;
 #pragma unroll
       for (int o = 0; o < NN; o++) {
@@ -2305,8 +2308,8 @@ void launch_compact(const Geo& g, const Dev& p, int lo, bool full, hipStream_t s
     else kern<3><<<nb_, TPB, 0, s>>>(__VA_ARGS__);                                \
   } while (0)
 
-void launch_load_finest(const Geo& g, const Dev& p, const double* src, int inst, hipStream_t s) {
-  DISPATCH_D(k_load_finest, (inst >= 0 ? 1 : g.B) * g.n[g.L], g, p, src, inst);
+void launch_load_finest(const Geo& g, const Dev& p, const double* src, int inst, int Li, hipStream_t s) {
+  DISPATCH_D(k_load_finest, (inst >= 0 ? 1 : g.B) * g.n[Li], g, p, src, inst, Li);
 }
 void launch_recon_level(const Geo& g, const Dev& p, int lev, double* dense, hipStream_t s) {
   DISPATCH_D(k_recon_level, g.B * g.n[lev], g, p, lev, dense);

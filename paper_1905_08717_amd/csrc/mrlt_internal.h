@@ -116,14 +116,22 @@ struct Dev {
   unsigned long long* near;
   unsigned long long* near_n;
   const long long* iterb;   // fine iterations completed before the current macro step
+  // [B] finest level of each instance (<= L): an instance whose finest level
+  // is below L never refines past it, and its level-dependent thresholds
+  // are those of a solve with that finest level
+  const uint8_t* lcap;
 };
 
 #define NEAR_CAP 65536
 
 // ---- launchers (kernels.hip) -------------------------------------------
 void launch_fill_status(const Geo& g, const Dev& p, int lev, uint8_t v, hipStream_t s);
-void launch_load_finest(const Geo& g, const Dev& p, const double* src, int inst, hipStream_t s);
-void launch_fill_instance(const Geo& g, const Dev& p, int inst, hipStream_t s);
+// finest-level averages of every instance (inst < 0, level L) or of one
+// instance at its own finest level Li
+void launch_load_finest(const Geo& g, const Dev& p, const double* src, int inst, int Li, hipStream_t s);
+// statuses of one instance for a load at finest level Li (inst >= 0), or
+// all absent (inst = -1 - slot)
+void launch_fill_instance(const Geo& g, const Dev& p, int inst, int Li, hipStream_t s);
 void launch_project(const Geo& g, const Dev& p, int lev, int mode, hipStream_t s);
 // virtual cells of levels lo..hi at `stage`; level cb_lev (if in range) is
 // the child of the mid-step level (case B)

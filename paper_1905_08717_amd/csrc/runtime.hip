@@ -26,6 +26,9 @@ struct mr_ctx {
   bool broken = false;
   std::string err;
   std::vector<void*> allocs;
+  mr_alloc alloc{};                   // caller's device allocator (alloc == NULL: hipMalloc)
+  size_t bytes = 0;                   // device bytes the context holds
+  double* ws_host = nullptr;          // pinned [B]: wave speeds read back without blocking
   double* dt_d = nullptr;
   double* eps_d = nullptr;
   int* blockcnt_d = nullptr;
@@ -40,6 +43,8 @@ struct mr_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   long long* iterb_d = nullptr;       // fine iterations before the current macro step
+  uint8_t* lcap_d = nullptr;          // finest level of each instance
+  std::vector<uint8_t> lcap_host;
   long long iter_upload = 0;          // host copy of it, written only before an upload
   std::vector<int64_t> it_start;      // per instance: iterations at its last load / set
   int timed_class = 0;          // kernel class under HIP-event timing (0: none)
@@ -96,15 +101,29 @@ mr_status hip_check(mr_ctx* c, hipError_t e, const char* what) {
     if (st__ != MR_OK) return st__;                      \
   } while (0)
 
+// device memory through the caller's allocator when one was given, else
+// hipMalloc; tmp_free returns it
+void* raw_alloc(mr_ctx* c, size_t bytes) {
+  if (c->alloc.alloc) return c->alloc.alloc(bytes, c->alloc.user);
+  void* ptr = nullptr;
+  if (hipMalloc(&ptr, bytes) != hipSuccess) return nullptr;
+  return ptr;
+}
+
+void raw_free(mr_ctx* c, void* ptr) {
+  if (!ptr) return;
+  if (c->alloc.alloc) c->alloc.free(ptr, c->alloc.user);
+  else (void)hipFree(ptr);
+}
+
 mr_status dalloc(mr_ctx* c, void** ptr, size_t bytes) {
   *ptr = nullptr;
   if (bytes == 0) bytes = 8;
-  hipError_t e = hipMalloc(ptr, bytes);
-  if (e != hipSuccess) {
-    *ptr = nullptr;
-    return hip_check(c, e, "hipMalloc");
-  }
+  bytes = (bytes + 255) & ~(size_t)255;
+  *ptr = raw_alloc(c, bytes);
+  if (!*ptr) return set_err(c, MR_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
   c->allocs.push_back(*ptr);
+  c->bytes += bytes;
   return hip_check(c, hipMemsetAsync(*ptr, 0, bytes, c->stream), "hipMemsetAsync");
 }
 
@@ -310,6 +329,11 @@ mr_status adapt_impl(mr_ctx* c) {
   return check_flags(c);
 }
 
+mr_status upload_lcap(mr_ctx* c) {
+  return hip_check(c, hipMemcpyAsync(c->lcap_d, c->lcap_host.data(), c->g.B, hipMemcpyHostToDevice, c->stream),
+                   "finest level upload");
+}
+
 mr_status level_count(mr_ctx* c, int lev, int inst, uint8_t want, long long* total) {
   const int nblk = (int)((c->g.n[lev] + 255) / 256);
   launch_count(c->g, c->p, lev, inst, want, c->blockcnt_d, nblk, c->stream);
@@ -334,15 +358,18 @@ void mr_destroy(mr_ctx* c) {
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
-  for (void* a : c->allocs) (void)hipFree(a);
+  for (void* a : c->allocs) raw_free(c, a);
+  if (c->ws_host) (void)hipHostFree(c->ws_host);
   if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
   delete c;
 }
 
-mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_scheme* s, mr_ctx** out) {
+mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_scheme* s, const mr_alloc* a,
+                        mr_ctx** out) {
   if (!out) return MR_EINVAL;
   *out = nullptr;
   if (!s || !eps || dim < 1 || dim > 3 || n_inst < 1) return MR_EINVAL;
+  if (a && ((a->alloc == nullptr) != (a->free == nullptr))) return MR_EINVAL;
   if (s->l0 < 2 || L < s->l0 || L > MR_MAXLEV || L - s->l0 > 20 || dim * L > 40) return MR_EINVAL;
   if ((s->rk != 2 && s->rk != 3) || (s->lt != 0 && s->lt != 1) || s->pde < MR_PDE_ADVECTION ||
       s->pde > MR_PDE_FLAMEBALL)
@@ -366,6 +393,7 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
 
   mr_ctx* c = new mr_ctx();
   c->s = *s;
+  if (a) c->alloc = *a;
   if (hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking) != hipSuccess) {
     delete c;
     return MR_EDEVICE;
@@ -485,6 +513,7 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
   c->dt_host.assign(n_inst, 0.0);
   c->cnt_host.assign((size_t)n_inst * CNT_PER_INST, 0);
   c->it_start.assign(n_inst, 0);
+  c->lcap_host.assign(n_inst, (uint8_t)L);
   c->max_blocks = (int)((g.n[L] + 255) / 256);
 
   mr_status st = MR_OK;
@@ -523,13 +552,20 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
   ALLOC(c->p.lflag, unsigned, MRD_MAXLEV + 1);
   ALLOC(c->p.vel, double, 2 * n_inst);
   if (flame) ALLOC(c->p.vfpart, double, g.comp_first[L + 1]);
+  if (hipHostMalloc((void**)&c->ws_host, sizeof(double) * (size_t)n_inst, hipHostMallocDefault) != hipSuccess) {
+    c->ws_host = nullptr;
+    st = set_err(c, MR_ENOMEM, "pinned host buffer");
+    goto fail;
+  }
   ALLOC(c->p.near, unsigned long long, 2 * NEAR_CAP);
   ALLOC(c->p.near_n, unsigned long long, 1);
   ALLOC(c->iterb_d, long long, 1);
+  ALLOC(c->lcap_d, uint8_t, n_inst);
 #undef ALLOC
   c->p.dt = c->dt_d;
   c->p.eps = c->eps_d;
   c->p.iterb = c->iterb_d;
+  c->p.lcap = c->lcap_d;
   // the zero fills of the allocations are queued on the context's own
   // non-blocking stream, which does not order with the null stream: the
   // upload goes behind them on the same stream (a blocking hipMemcpy could
@@ -537,6 +573,9 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
   st = hip_check(c, hipMemcpyAsync(c->eps_d, c->eps.data(), sizeof(double) * n_inst, hipMemcpyHostToDevice,
                                    c->stream),
                  "eps upload");
+  if (st != MR_OK) goto fail;
+  st = hip_check(c, hipMemcpyAsync(c->lcap_d, c->lcap_host.data(), n_inst, hipMemcpyHostToDevice, c->stream),
+                 "finest level upload");
   if (st != MR_OK) goto fail;
   st = hip_check(c, hipStreamSynchronize(c->stream), "init");
   if (st != MR_OK) goto fail;
@@ -547,8 +586,8 @@ fail:
   return st;
 }
 
-mr_status mr_init(int dim, int L, double eps, const mr_scheme* s, mr_ctx** out) {
-  return mr_init_batch(dim, L, 1, &eps, s, out);
+mr_status mr_init(int dim, int L, double eps, const mr_scheme* s, const mr_alloc* a, mr_ctx** out) {
+  return mr_init_batch(dim, L, 1, &eps, s, a, out);
 }
 
 mr_status mr_set_stream(mr_ctx* c, void* hip_stream) {
@@ -567,8 +606,13 @@ mr_status mr_load_finest(mr_ctx* c, const double* q0, void* hip_stream) {
   if (!c || !q0) return MR_EINVAL;
   if (hip_stream) c->stream = (hipStream_t)hip_stream;
   const Geo& g = c->g;
+  std::fill(c->lcap_host.begin(), c->lcap_host.end(), (uint8_t)g.L);
+  {
+    mr_status su = upload_lcap(c);
+    if (su != MR_OK) return su;
+  }
   for (int lev = g.l0; lev < g.L; lev++) launch_fill_status(g, c->p, lev, ST_INTERNAL, c->stream);
-  launch_load_finest(g, c->p, q0, -1, c->stream);
+  launch_load_finest(g, c->p, q0, -1, g.L, c->stream);
   launch_clear_regs(g, c->p, c->stream);
   refresh_lists(c, g.l0, true);
   HIPCHK(c, hipMemsetAsync(c->p.cnt, 0, sizeof(unsigned long long) * g.B * CNT_PER_INST, c->stream));
@@ -585,12 +629,16 @@ mr_status mr_load_finest(mr_ctx* c, const double* q0, void* hip_stream) {
 
 __global__ void k_reset_counters(unsigned long long* cnt, int inst);
 
-mr_status mr_load_finest_inst(mr_ctx* c, int inst, const double* q0) {
-  if (!c || !q0 || inst < 0 || inst >= c->g.B) return MR_EINVAL;
+static mr_status load_inst_impl(mr_ctx* c, int inst, int Li, const double* q0) {
   if (c->broken) return set_err(c, MR_ESTATE, "context in error state");
   Geo& g = c->g;
-  launch_fill_instance(g, c->p, inst, c->stream);
-  launch_load_finest(g, c->p, q0, inst, c->stream);
+  c->lcap_host[inst] = (uint8_t)Li;
+  {
+    mr_status su = upload_lcap(c);
+    if (su != MR_OK) return su;
+  }
+  launch_fill_instance(g, c->p, inst, Li, c->stream);
+  launch_load_finest(g, c->p, q0, inst, Li, c->stream);
   launch_clear_regs(g, c->p, c->stream);
   k_reset_counters<<<1, 64, 0, c->stream>>>(c->p.cnt, inst);
   refresh_lists(c, g.l0, true);
@@ -615,9 +663,23 @@ mr_status mr_load_finest_inst(mr_ctx* c, int inst, const double* q0) {
   return check_flags(c);
 }
 
+mr_status mr_load_finest_inst(mr_ctx* c, int inst, const double* q0) {
+  if (!c || !q0 || inst < 0 || inst >= c->g.B) return MR_EINVAL;
+  return load_inst_impl(c, inst, c->g.L, q0);
+}
+
+mr_status mr_load_inst(mr_ctx* c, int inst, int L_inst, double eps, const double* q0) {
+  if (!c || !q0 || inst < 0 || inst >= c->g.B) return MR_EINVAL;
+  if (L_inst < c->g.l0 || L_inst > c->g.L) return set_err(c, MR_EINVAL, "instance finest level outside l0..L");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return set_err(c, MR_EINVAL, "eps must be finite and >= 0");
+  c->eps[inst] = eps;
+  HIPCHK(c, hipMemcpyAsync(c->eps_d, c->eps.data(), sizeof(double) * c->g.B, hipMemcpyHostToDevice, c->stream));
+  return load_inst_impl(c, inst, L_inst, q0);
+}
+
 mr_status mr_clear_instance(mr_ctx* c, int inst) {
   if (!c || inst < 0 || inst >= c->g.B) return MR_EINVAL;
-  launch_fill_instance(c->g, c->p, -1 - inst, c->stream);
+  launch_fill_instance(c->g, c->p, -1 - inst, c->g.L, c->stream);
   k_reset_counters<<<1, 64, 0, c->stream>>>(c->p.cnt, inst);
   refresh_lists(c, c->g.l0, true);
   c->t[inst] = 0.0;
@@ -665,7 +727,10 @@ static void macro_begin(mr_ctx* c) {
   if (c->g.flame_speed) launch_flame_speed(c->g, c->p, c->stream);
 }
 
-mr_status mr_lt_step_batch(mr_ctx* c, const double* dt) {
+}  // extern "C"
+
+// queue one macro step (no wait); ctx_step_finish waits and checks the flags
+mr_status ctx_step_enqueue(mr_ctx* c, const double* dt) {
   if (!c || !dt) return MR_EINVAL;
   if (c->broken) return set_err(c, MR_ESTATE, "context in error state: reload or set leaves");
   for (int i = 0; i < c->g.B; i++)
@@ -699,7 +764,44 @@ mr_status mr_lt_step_batch(mr_ctx* c, const double* dt) {
   if (st != MR_OK) return st;
   for (int i = 0; i < c->g.B; i++) c->t[i] = c->t[i] + (double)N * dt[i];
   c->iters += N;
-  return check_flags(c);
+  return MR_OK;
+}
+
+mr_status ctx_step_finish(mr_ctx* c) { return check_flags(c); }
+
+// queue the wave-speed reduction into the pinned buffer; ctx_wavespeed_finish
+// waits and returns it
+mr_status ctx_wavespeed_enqueue(mr_ctx* c) {
+  const Geo& g = c->g;
+  if (g.flame_speed) launch_flame_speed(g, c->p, c->stream);
+  HIPCHK(c, hipMemsetAsync(c->ws_d, 0, sizeof(unsigned long long) * g.B, c->stream));
+  for (int lev = g.l0; lev <= g.L; lev++) launch_wavespeed(g, c->p, lev, c->ws_d, c->stream);
+  HIPCHK(c, hipMemcpyAsync(c->ws_host, c->ws_d, sizeof(double) * g.B, hipMemcpyDeviceToHost, c->stream));
+  return check_launch(c, "max_wavespeed");
+}
+
+mr_status ctx_wavespeed_finish(mr_ctx* c, double* out) {
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  memcpy(out, c->ws_host, sizeof(double) * c->g.B);  // the bits of non-negative doubles
+  return MR_OK;
+}
+
+size_t ctx_footprint(const mr_ctx* c) { return c ? c->bytes : 0; }
+
+int ctx_instances(const mr_ctx* c) { return c ? c->g.B : 0; }
+
+extern "C" {
+
+mr_status mr_lt_step_batch(mr_ctx* c, const double* dt) {
+  mr_status st = ctx_step_enqueue(c, dt);
+  if (st != MR_OK) return st;
+  return ctx_step_finish(c);
+}
+
+mr_status mr_footprint(mr_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return MR_EINVAL;
+  *bytes = c->bytes;
+  return MR_OK;
 }
 
 mr_status mr_lt_step(mr_ctx* c, double dt_L) {
@@ -759,15 +861,9 @@ mr_status mr_flame_speed(mr_ctx* c, double* vf) {
 
 mr_status mr_max_wavespeed(mr_ctx* c, double* out) {
   if (!c || !out) return MR_EINVAL;
-  const Geo& g = c->g;
-  if (g.flame_speed) launch_flame_speed(g, c->p, c->stream);
-  HIPCHK(c, hipMemsetAsync(c->ws_d, 0, sizeof(unsigned long long) * g.B, c->stream));
-  for (int lev = g.l0; lev <= g.L; lev++) launch_wavespeed(g, c->p, lev, c->ws_d, c->stream);
-  std::vector<unsigned long long> bits((size_t)g.B);
-  HIPCHK(c, hipMemcpyAsync(bits.data(), c->ws_d, sizeof(unsigned long long) * g.B, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  for (int i = 0; i < g.B; i++) memcpy(&out[i], &bits[i], sizeof(double));
-  return check_launch(c, "max_wavespeed");
+  mr_status st = ctx_wavespeed_enqueue(c);
+  if (st != MR_OK) return st;
+  return ctx_wavespeed_finish(c, out);
 }
 
 mr_status mr_get_leaves_inst(mr_ctx* c, int inst, uint64_t* keys, double* q, int64_t cap, int64_t* n) {
@@ -783,11 +879,10 @@ mr_status mr_get_leaves_inst(mr_ctx* c, int inst, uint64_t* keys, double* q, int
   *n = tot;
   if (!keys || !q) return MR_OK;
   if (cap < tot) return set_err(c, MR_ECAPACITY, "leaf buffer too small");
-  void* kd = nullptr;
-  void* vd = nullptr;
-  HIPCHK(c, hipMalloc(&kd, sizeof(unsigned long long) * (size_t)(tot + 1)));
-  if (hipMalloc(&vd, sizeof(double) * (size_t)(tot + 1) * g.m) != hipSuccess) {
-    (void)hipFree(kd);
+  void* kd = raw_alloc(c, sizeof(unsigned long long) * (size_t)(tot + 1));
+  void* vd = kd ? raw_alloc(c, sizeof(double) * (size_t)(tot + 1) * g.m) : nullptr;
+  if (!vd) {
+    raw_free(c, kd);
     return set_err(c, MR_ENOMEM, "leaf staging buffer");
   }
   long long base = 0;
@@ -802,8 +897,8 @@ mr_status mr_get_leaves_inst(mr_ctx* c, int inst, uint64_t* keys, double* q, int
   hipError_t e1 = hipMemcpyAsync(keys, kd, sizeof(uint64_t) * (size_t)tot, hipMemcpyDeviceToHost, c->stream);
   hipError_t e2 = hipMemcpyAsync(q, vd, sizeof(double) * (size_t)tot * g.m, hipMemcpyDeviceToHost, c->stream);
   hipError_t e3 = hipStreamSynchronize(c->stream);
-  (void)hipFree(kd);
-  (void)hipFree(vd);
+  raw_free(c, kd);
+  raw_free(c, vd);
   HIPCHK(c, e1);
   HIPCHK(c, e2);
   HIPCHK(c, e3);
@@ -863,11 +958,10 @@ mr_status mr_set_leaves_inst(mr_ctx* c, int inst, const uint64_t* keys, const do
     const int64_t base = g.off[lev] + (int64_t)inst * g.n[lev];
     k_fill_range<<<blocks_for(g.n[lev]), 256, 0, c->stream>>>(c->p.st, base, g.n[lev], ST_ABSENT);
   }
-  void* kd = nullptr;
-  void* vd = nullptr;
-  HIPCHK(c, hipMalloc(&kd, sizeof(uint64_t) * (size_t)(n + 1)));
-  if (hipMalloc(&vd, sizeof(double) * (size_t)(n + 1) * g.m) != hipSuccess) {
-    (void)hipFree(kd);
+  void* kd = raw_alloc(c, sizeof(uint64_t) * (size_t)(n + 1));
+  void* vd = kd ? raw_alloc(c, sizeof(double) * (size_t)(n + 1) * g.m) : nullptr;
+  if (!vd) {
+    raw_free(c, kd);
     return set_err(c, MR_ENOMEM, "leaf staging buffer");
   }
   int herr = 0;
@@ -883,8 +977,8 @@ mr_status mr_set_leaves_inst(mr_ctx* c, int inst, const uint64_t* keys, const do
     e = hipMemcpyAsync(&herr, c->err_d, sizeof(int), hipMemcpyDeviceToHost, c->stream);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  (void)hipFree(kd);
-  (void)hipFree(vd);
+  raw_free(c, kd);
+  raw_free(c, vd);
   HIPCHK(c, e);
   if (herr) {
     char buf[96];
@@ -902,6 +996,12 @@ mr_status mr_set_leaves_inst(mr_ctx* c, int inst, const uint64_t* keys, const do
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->t[inst] = t;
   c->it_start[inst] = c->iters;
+  c->lcap_host[inst] = (uint8_t)g.L;
+  {
+    mr_status su = upload_lcap(c);
+    if (su != MR_OK) return su;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
   c->broken = false;
   c->err.clear();
   return MR_OK;
@@ -960,7 +1060,10 @@ mr_status mr_near_threshold(mr_ctx* c, int inst, int64_t* iter, int32_t* level, 
     const unsigned long long w = raw[2 * j + 1];
     const int64_t it = (int64_t)raw[2 * j];
     if ((int)(w >> 45) != inst || it < c->it_start[inst]) continue;
-    v.push_back(E{it - c->it_start[inst], (int32_t)((w >> 40) & 31u), w & ((1ull << 40) - 1)});
+    // in the instance's own iterations: its finest level takes one
+    // iteration per 2^{L - Li} of the context's
+    const int sh = c->g.L - c->lcap_host[inst];
+    v.push_back(E{(it - c->it_start[inst]) >> sh, (int32_t)((w >> 40) & 31u), w & ((1ull << 40) - 1)});
   }
   std::sort(v.begin(), v.end(), [](const E& a, const E& b) {
     if (a.it != b.it) return a.it < b.it;

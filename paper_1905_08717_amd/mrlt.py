@@ -28,8 +28,11 @@ EXPORTS = [
     "mr_synchronize", "mr_last_error", "mr_destroy", "mr_level_updates", "mr_timing_start",
     "mr_timing_stop", "mr_load_finest_inst", "mr_clear_instance", "mr_instance_flags", "mr_set_eps",
     "mr_stage_items", "mr_flame_speed", "mr_set_launch", "mr_get_launch", "mr_near_threshold",
-    "mr_get_leaves_noalloc",
+    "mr_get_leaves_noalloc", "mr_load_inst", "mr_footprint",
+    "mr_batch_create", "mr_batch_admit", "mr_batch_step", "mr_batch_poll", "mr_batch_slot_info",
+    "mr_batch_get_leaves", "mr_batch_release", "mr_batch_footprint", "mr_batch_last_error", "mr_batch_destroy",
 ]
+SLOT_FREE, SLOT_RUNNING, SLOT_DONE, SLOT_FAILED = 0, 1, 2, 3
 KC = {"stage_finest": 1, "stage": 2, "project": 3, "ghost": 4, "remesh": 5, "finalize": 6, "stage_bulk": 7}
 
 
@@ -46,6 +49,25 @@ class MrScheme(ctypes.Structure):
         ("ze", ctypes.c_double), ("tau", ctypes.c_double), ("lewis", ctypes.c_double),
         ("kappa", ctypes.c_double), ("flame_speed", ctypes.c_int32),
     ]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class MrAlloc(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p)]
+
+
+class MrClassDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("L_max", ctypes.c_int32), ("slots", ctypes.c_int32),
+                ("scheme", MrScheme)]
+
+
+class MrInstanceDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("L", ctypes.c_int32), ("eps", ctypes.c_double),
+                ("t_final", ctypes.c_double), ("cfl", ctypes.c_double), ("dt_max", ctypes.c_double),
+                ("scheme", MrScheme)]
 
 
 class MrLaunch(ctypes.Structure):
@@ -85,8 +107,22 @@ def load_library():
     dp = ctypes.POINTER(ctypes.c_double)
     u64p = ctypes.POINTER(ctypes.c_uint64)
     sp = ctypes.POINTER(MrScheme)
-    L.mr_init.argtypes = [i32, i32, dbl, sp, ctypes.POINTER(vp)]
-    L.mr_init_batch.argtypes = [i32, i32, i32, dp, sp, ctypes.POINTER(vp)]
+    ap = ctypes.POINTER(MrAlloc)
+    L.mr_init.argtypes = [i32, i32, dbl, sp, ap, ctypes.POINTER(vp)]
+    L.mr_init_batch.argtypes = [i32, i32, i32, dp, sp, ap, ctypes.POINTER(vp)]
+    L.mr_footprint.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.mr_batch_create.argtypes = [i32, ctypes.POINTER(MrClassDesc), ctypes.c_size_t, ap, ctypes.POINTER(vp)]
+    L.mr_batch_admit.argtypes = [vp, ctypes.POINTER(MrInstanceDesc), vp, ctypes.POINTER(i32)]
+    L.mr_batch_step.argtypes = [vp]
+    L.mr_batch_poll.argtypes = [vp, ctypes.POINTER(i32), i32, ctypes.POINTER(i32)]
+    L.mr_batch_slot_info.argtypes = [vp, i32, ctypes.POINTER(i32), dp, ctypes.POINTER(i64)]
+    L.mr_batch_get_leaves.argtypes = [vp, i32, u64p, dp, i64, ctypes.POINTER(i64)]
+    L.mr_batch_release.argtypes = [vp, i32]
+    L.mr_batch_footprint.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.mr_batch_last_error.argtypes = [vp]
+    L.mr_batch_last_error.restype = ctypes.c_char_p
+    L.mr_batch_destroy.argtypes = [vp]
+    L.mr_batch_destroy.restype = None
     L.mr_set_stream.argtypes = [vp, vp]
     L.mr_ncomp.argtypes = [vp]
     L.mr_load_finest.argtypes = [vp, vp, vp]
@@ -113,6 +149,7 @@ def load_library():
     L.mr_stage_items.argtypes = [vp, ctypes.POINTER(i64)]
     L.mr_timing_stop.argtypes = [vp, dp, ctypes.POINTER(i64)]
     L.mr_load_finest_inst.argtypes = [vp, i32, vp]
+    L.mr_load_inst.argtypes = [vp, i32, i32, dbl, vp]
     L.mr_clear_instance.argtypes = [vp, i32]
     L.mr_instance_flags.argtypes = [vp, i32, ctypes.POINTER(i32)]
     L.mr_set_eps.argtypes = [vp, i32, dbl]
@@ -121,7 +158,7 @@ def load_library():
     L.mr_destroy.argtypes = [vp]
     L.mr_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("mr_last_error", "mr_destroy", "mr_ncomp"):
+        if name not in ("mr_last_error", "mr_destroy", "mr_ncomp", "mr_batch_last_error", "mr_batch_destroy"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -164,6 +201,29 @@ def make_scheme(cfg: dict) -> MrScheme:
     return s
 
 
+_TORCH_ALLOC = None
+
+
+def torch_allocator() -> MrAlloc:
+    """Device memory from PyTorch's caching allocator (the mr_alloc
+    callbacks of the C ABI); the callback objects live for the process."""
+    global _TORCH_ALLOC
+    if _TORCH_ALLOC is None:
+        import torch
+
+        def _alloc(nbytes, _user):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes))
+            except Exception:   # out of memory: the library reports MR_ENOMEM
+                return None
+
+        def _free(ptr, _user):
+            torch.cuda.caching_allocator_delete(int(ptr))
+
+        _TORCH_ALLOC = MrAlloc(ALLOC_FN(_alloc), FREE_FN(_free), None)
+    return _TORCH_ALLOC
+
+
 def _stream_ptr(stream):
     if stream is None:
         return None
@@ -173,7 +233,7 @@ def _stream_ptr(stream):
 class Solver:
     """A batch of MRLT/NERK3 solves on one GPU (n_inst = 1 for a single solve)."""
 
-    def __init__(self, cfg: dict, n_inst: int = 1, eps=None, stream=None):
+    def __init__(self, cfg: dict, n_inst: int = 1, eps=None, stream=None, alloc: MrAlloc = None):
         import torch
 
         self.torch = torch
@@ -187,7 +247,9 @@ class Solver:
         self._s = make_scheme(cfg)
         h = ctypes.c_void_p()
         self._h = None
-        rc = L.mr_init_batch(self.dim, self.L, n_inst, eps_arr, ctypes.byref(self._s), ctypes.byref(h))
+        self._alloc = alloc
+        rc = L.mr_init_batch(self.dim, self.L, n_inst, eps_arr, ctypes.byref(self._s),
+                             ctypes.byref(alloc) if alloc is not None else None, ctypes.byref(h))
         if rc != OK:
             raise MrError(rc, "mr_init_batch failed")
         self._h = h
@@ -237,6 +299,20 @@ class Solver:
         self._keep_inst = q0
         self._check(load_library().mr_load_finest_inst(self._h, inst, ctypes.c_void_p(q0.data_ptr())),
                     "mr_load_finest_inst")
+
+    def load_inst(self, inst: int, L_inst: int, eps: float, q0):
+        """Load one instance with its own finest level L_inst <= L and
+        threshold eps (q0: [m, 2^{d L_inst}], torch device tensor or numpy);
+        step it with dt_L = 2^{L_inst - L} times its own finest step."""
+        t = self.torch
+        if isinstance(q0, np.ndarray):
+            q0 = t.from_numpy(np.ascontiguousarray(q0, dtype=np.float64)).to("cuda")
+        q0 = q0.contiguous()
+        assert q0.dtype == t.float64 and q0.is_cuda and q0.numel() == self.m * (1 << (self.dim * L_inst))
+        t.cuda.current_stream().synchronize()
+        self._keep_inst = q0
+        self._check(load_library().mr_load_inst(self._h, inst, int(L_inst), float(eps),
+                                                ctypes.c_void_p(q0.data_ptr())), "mr_load_inst")
 
     def clear_instance(self, inst: int):
         self._check(load_library().mr_clear_instance(self._h, inst), "mr_clear_instance")
@@ -358,6 +434,12 @@ class Solver:
                                             ctypes.byref(n)), "mr_near_threshold")
         return [(int(a), int(b), int(c)) for a, b, c in zip(it, lv, ky)]
 
+    def footprint(self) -> int:
+        """Device bytes the context holds."""
+        v = ctypes.c_size_t()
+        self._check(load_library().mr_footprint(self._h, ctypes.byref(v)), "mr_footprint")
+        return v.value
+
     def level_updates(self, inst: int = 0):
         arr = (ctypes.c_int64 * (MAXLEV + 1))()
         self._check(load_library().mr_level_updates(self._h, inst, arr), "mr_level_updates")
@@ -380,3 +462,97 @@ class Solver:
 
     def synchronize(self):
         self._check(load_library().mr_synchronize(self._h), "mr_synchronize")
+
+
+class Batch:
+    """Solves of uneven size under the library's scheduler (mr_batch_*):
+    classes of (scheme, dim, largest finest level, slots), admission by
+    device footprint, per-solve CFL steps, retirement at the final time."""
+
+    def __init__(self, classes, hbm_budget: int, alloc: MrAlloc = None):
+        """classes: list of (cfg, L_max, slots)."""
+        import torch
+
+        self.torch = torch
+        L = load_library()
+        arr = (MrClassDesc * len(classes))()
+        self.ncomp = []
+        for j, (cfg, L_max, slots) in enumerate(classes):
+            arr[j].dim, arr[j].L_max, arr[j].slots = cfg["dim"], int(L_max), int(slots)
+            arr[j].scheme = make_scheme(cfg)
+        self._alloc = alloc
+        h = ctypes.c_void_p()
+        self._h = None
+        rc = L.mr_batch_create(len(classes), arr, int(hbm_budget), ctypes.byref(alloc) if alloc is not None else None,
+                               ctypes.byref(h))
+        if rc != OK:
+            raise MrError(rc, "mr_batch_create failed")
+        self._h = h
+        self.slots = sum(int(c[2]) for c in classes)
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().mr_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc != OK:
+            msg = load_library().mr_batch_last_error(self._h) if self._h else b""
+            raise MrError(rc, f"{what} failed: {msg.decode() if msg else ''}")
+
+    def admit(self, cfg: dict, L: int, eps: float, t_final: float, q0, cfl: float = 0.5, dt_max: float = 0.0):
+        """Admit a solve (q0: [m, 2^{d L}]); its slot, or None when no slot
+        or memory is free (MR_ECAPACITY)."""
+        t = self.torch
+        if isinstance(q0, np.ndarray):
+            q0 = t.from_numpy(np.ascontiguousarray(q0, dtype=np.float64)).to("cuda")
+        q0 = q0.contiguous()
+        t.cuda.current_stream().synchronize()
+        d = MrInstanceDesc(cfg["dim"], int(L), float(eps), float(t_final), float(cfl), float(dt_max), make_scheme(cfg))
+        slot = ctypes.c_int()
+        rc = load_library().mr_batch_admit(self._h, ctypes.byref(d), ctypes.c_void_p(q0.data_ptr()), ctypes.byref(slot))
+        if rc == ECAPACITY:
+            return None
+        self._check(rc, "mr_batch_admit")
+        return slot.value
+
+    def step(self):
+        self._check(load_library().mr_batch_step(self._h), "mr_batch_step")
+
+    def poll(self):
+        arr = (ctypes.c_int * self.slots)()
+        n = ctypes.c_int()
+        self._check(load_library().mr_batch_poll(self._h, arr, self.slots, ctypes.byref(n)), "mr_batch_poll")
+        return list(arr[:n.value])
+
+    def slot_info(self, slot: int):
+        st, tt, ms = ctypes.c_int(), ctypes.c_double(), ctypes.c_int64()
+        self._check(load_library().mr_batch_slot_info(self._h, slot, ctypes.byref(st), ctypes.byref(tt),
+                                                      ctypes.byref(ms)), "mr_batch_slot_info")
+        return {"state": st.value, "t": tt.value, "macro_steps": ms.value}
+
+    def get_leaves(self, slot: int, m: int):
+        L = load_library()
+        n = ctypes.c_int64()
+        self._check(L.mr_batch_get_leaves(self._h, slot, None, None, 0, ctypes.byref(n)), "mr_batch_get_leaves")
+        keys = np.zeros(n.value, dtype=np.uint64)
+        q = np.zeros((m, n.value))
+        self._check(L.mr_batch_get_leaves(self._h, slot, keys.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                          q.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n.value,
+                                          ctypes.byref(n)), "mr_batch_get_leaves")
+        return keys, q
+
+    def release(self, slot: int):
+        self._check(load_library().mr_batch_release(self._h, slot), "mr_batch_release")
+
+    def footprint(self) -> int:
+        v = ctypes.c_size_t()
+        self._check(load_library().mr_batch_footprint(self._h, ctypes.byref(v)), "mr_batch_footprint")
+        return v.value

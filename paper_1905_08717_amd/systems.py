@@ -1,25 +1,22 @@
-"""Systems forms on one GPU: many independent MRLT/NERK3 solves.
+"""Systems forms on one GPU: many independent MRLT/NERK3 solves, driven
+through the library's scheduler (mr_batch_* of the C ABI).
 
 * Batched: uneven solves (different finest level, threshold, initial data)
-  advanced together; solves of one problem class (PDE, dimension, finest
-  level) share a batch context, so every kernel launch of a macro step
-  serves all of them.  Each solve keeps its own CFL step and stops at its
-  own final time; a finished solve's slot is freed (all cells absent), so it
-  drops out of every kernel's work.
-* Served: requests arrive over time (Poisson); a request is admitted into a
-  free slot of its class as soon as one is free and the class's device
-  memory budget allows, is advanced one macro step at a time together with
-  whatever else is resident, and its result is read back when it reaches its
-  final time.  Latency = arrival to result ready.
+  in one class per scheme, whose context has the largest finest level: every
+  kernel launch of a macro step serves all of them.  Each solve keeps its
+  own CFL step and stops at its own final time.
+* Served: requests arrive over time (Poisson) and are admitted as slots and
+  device memory free up; classes (one per scheme and finest level) step on
+  their own streams; results are read back as solves finish.
+* One at a time: the plain form, every request alone in a context of its own
+  finest level.
 
-All numerical work runs in the HIP library through the C ABI; this module
-only schedules.
+All numerical work and the scheduling of slots, steps and memory run in the
+native library; this module only feeds requests and reads results.
 """
 from __future__ import annotations
 
 import dataclasses
-import heapq
-import math
 import sys
 import time
 from typing import Dict, List, Optional, Tuple
@@ -45,232 +42,162 @@ class Request:
 
 
 def class_key(cfg: dict) -> tuple:
-    return (cfg["pde"], cfg["dim"], cfg["L"], cfg.get("l0", 2))
+    """Solves that may share a context: same PDE, dimension, coarsest level
+    and scheme parameters (the finest level may differ)."""
+    skip = ("L", "eps", "name", "t_final")
+    return tuple(sorted((k, repr(v)) for k, v in cfg.items() if k not in skip))
 
 
-def bytes_per_instance(cfg: dict) -> int:
-    """Device bytes of one slot: cell tables of all levels (status, scratch,
-    ghost flag, three int lists, nine FP64 slots of m fields) and the flux
-    registers of the levels below L."""
-    d, L, l0 = cfg["dim"], cfg["L"], cfg.get("l0", 2)
-    m = W.ncomp(cfg)
-    cells = sum(1 << (d * lev) for lev in range(l0, L + 1))
-    coarse = sum(1 << (d * lev) for lev in range(l0, L))
-    regs = coarse * 2 * d * (1 + (1 << (d - 1))) * m * 8
-    return cells * (3 + 12 + 9 * m * 8) + regs
+def _m(cfg: dict) -> int:
+    return W.ncomp(cfg)
 
 
-def step_dt(cfg: dict, ws: float, t: float, t_final: float) -> float:
-    """Finest-level step of one solve for its next macro step: CFL sigma on
-    the finest level (advective and diffusive limits), cut so that the last
-    macro step ends exactly at t_final."""
-    it = W.macro_iters(cfg)
-    dx = (cfg.get("hi", [1.0] * 3)[0] - cfg.get("lo", [0.0] * 3)[0]) / (1 << cfg["L"])
-    sigma = cfg.get("cfl", 0.5)
-    rate = ws / dx
-    if cfg["pde"] in ("burgers", "nagumo", "linear"):
-        rate += 2 * cfg["dim"] * cfg.get("nu", 0.0) / dx ** 2
-    if cfg["pde"] == "nagumo":
-        rate += 0.8 * cfg.get("k_react", 0.0)
-    dt = sigma / rate if rate > 0 else (t_final - t) / it
-    return min(dt, (t_final - t) / it)
-
-
-class SlotPool:
-    """One batch context with `slots` instances for one problem class."""
-
-    def __init__(self, cfg: dict, slots: int, eps: List[float] = None):
-        self.cfg = dict(cfg)
-        self.slots = slots
-        self.solver = mrlt.Solver(cfg, n_inst=slots, eps=eps or [cfg.get("eps", 1e-3)] * slots)
-        self.req: List[Optional[Request]] = [None] * slots
-        self.failed: List[Request] = []
-        self.t = np.zeros(slots)
-
-    def free_slots(self) -> List[int]:
-        return [i for i, r in enumerate(self.req) if r is None]
-
-    def active(self) -> int:
-        return sum(r is not None for r in self.req)
-
-    def admit(self, r: Request, slot: int):
-        self.solver.set_eps(slot, r.eps)
-        self.solver.load_finest_inst(slot, r.q0)
-        self.req[slot] = r
-        self.t[slot] = 0.0
-
-    def load_all(self, reqs: List[Request]):
-        """Admit a full batch at once (one load for all slots)."""
-        assert len(reqs) == self.slots
-        q = np.stack([r.q0 for r in reqs])
-        for i, r in enumerate(reqs):
-            self.solver.set_eps(i, r.eps)
-        self.solver.load_finest(q)
-        self.req = list(reqs)
-        self.t[:] = 0.0
-
-    def step(self) -> int:
-        """One macro step of every resident solve; returns the number stepped."""
-        n = self.active()
-        if n == 0:
-            return 0
-        ws = self.solver.max_wavespeed()
-        dts = np.ones(self.slots)
-        for i, r in enumerate(self.req):
-            if r is not None:
-                dts[i] = step_dt(self.cfg, ws[i], self.t[i], r.t_final)
-        rc = self.solver.lt_step_rc_batch(dts)
-        if rc in (mrlt.ENONFINITE, mrlt.ESTATE):
-            # a failing request fails alone: retire it, keep the others
-            for i, r in enumerate(self.req):
-                if r is not None and self.solver.instance_flags(i):
-                    r.failed = True
-                    r.t_final = self.t[i]
-            for i, r in enumerate(self.req):
-                if r is not None and r.failed:
-                    self.solver.clear_instance(i)
-                    self.failed.append(r)
-                    self.req[i] = None
-        elif rc != mrlt.OK:
-            raise mrlt.MrError(rc, self.solver.last_error())
-        it = W.macro_iters(self.cfg)
-        for i, r in enumerate(self.req):
-            if r is not None:
-                self.t[i] += it * dts[i]
-                r.macro_steps += 1
-        return n
-
-    def poll(self, now: float, keep_result: bool = True) -> List[Request]:
-        """Finished solves: read their leaves, free their slots."""
-        out = []
-        for i, r in enumerate(self.req):
-            if r is not None and self.t[i] >= r.t_final * (1 - 1e-12):
-                if keep_result:
-                    r.result = self.solver.get_leaves(i)
-                r.done_at = now
-                self.solver.clear_instance(i)
-                self.req[i] = None
-                out.append(r)
-        return out
-
-
-class _Progress:
+def _progress(what: str, every: float = 10.0):
     """A line on stderr every `every` seconds (long runs stay visibly alive)."""
+    state = {"t0": time.perf_counter(), "last": time.perf_counter()}
 
-    def __init__(self, what: str, every: float = 10.0):
-        self.what, self.every = what, every
-        self.t0 = self.last = time.perf_counter()
-
-    def __call__(self, msg: str):
+    def tick(msg: str):
         now = time.perf_counter()
-        if now - self.last >= self.every:
-            self.last = now
-            print(f"[{self.what}] {now - self.t0:.1f} s: {msg}", file=sys.stderr, flush=True)
+        if now - state["last"] >= every:
+            state["last"] = now
+            print(f"[{what}] {now - state['t0']:.1f} s: {msg}", file=sys.stderr, flush=True)
+    return tick
 
 
-def run_batched(reqs: List[Request]) -> Dict:
-    """Advance all requests to completion, batched by problem class."""
+def _drain(b: mrlt.Batch, by_slot: Dict[int, Request], now: float) -> Tuple[List[Request], List[Request]]:
+    """Finished and failed solves of the last steps: results read, slots freed."""
+    done, failed = [], []
+    for slot in b.poll():
+        r = by_slot.pop(slot)
+        info = b.slot_info(slot)
+        r.macro_steps = info["macro_steps"]
+        if info["state"] == mrlt.SLOT_DONE:
+            r.result = b.get_leaves(slot, _m(r.cfg))
+            r.done_at = now
+            done.append(r)
+        else:
+            r.failed = True
+            failed.append(r)
+        b.release(slot)
+    return done, failed
+
+
+def run_batched(reqs: List[Request], hbm_budget: int = 200 * 2 ** 30) -> Dict:
+    """All requests in as few contexts as their schemes allow: one class per
+    scheme with the largest finest level of its requests and a slot for each,
+    so solves of uneven finest level share every launch.  Time from the
+    first admission to the last result."""
     groups: Dict[tuple, List[Request]] = {}
     for r in reqs:
         groups.setdefault(class_key(r.cfg), []).append(r)
+    classes = [(rs[0].cfg, max(r.cfg["L"] for r in rs), len(rs)) for rs in groups.values()]
+    b = mrlt.Batch(classes, hbm_budget)
     t0 = time.perf_counter()
-    pools = []
-    for key, rs in groups.items():
-        p = SlotPool(rs[0].cfg, len(rs), eps=[r.eps for r in rs])
-        p.load_all(rs)
-        pools.append(p)
-    done = 0
-    steps = 0
-    prog = _Progress("batched")
-    # a request that fails (non-finite state) is retired alone; it counts as
-    # ended but not as solved
-    while done + sum(len(p.failed) for p in pools) < len(reqs):
-        for p in pools:
-            steps += p.step()
-            done += len(p.poll(time.perf_counter() - t0))
-        prog(f"{done}/{len(reqs)} solves done, {steps} slot macro steps")
+    by_slot: Dict[int, Request] = {}
+    for r in reqs:
+        slot = b.admit(r.cfg, r.cfg["L"], r.eps, r.t_final, r.q0, cfl=r.cfg.get("cfl", 0.5))
+        if slot is None:
+            raise RuntimeError("batched form: the requests do not fit the HBM budget")
+        by_slot[slot] = r
+    done, failed, steps = 0, 0, 0
+    tick = _progress("batched")
+    while by_slot:
+        b.step()
+        steps += 1
+        d, f = _drain(b, by_slot, time.perf_counter() - t0)
+        done += len(d)
+        failed += len(f)
+        tick(f"{done}/{len(reqs)} solves done, {steps} macro steps")
     el = time.perf_counter() - t0
-    failed = sum(len(p.failed) for p in pools)
+    fp = b.footprint()
+    b.close()
     return {"seconds": el, "solves": done, "failed": failed, "solves_per_s": done / el,
-            "slot_macro_steps": steps}
+            "macro_steps": steps, "hbm_bytes": fp}
 
 
-def run_one_at_a_time(reqs: List[Request]) -> Dict:
-    """The plain GPU form: every request alone in a batch of one."""
-    pools: Dict[tuple, SlotPool] = {}
+def run_one_at_a_time(reqs: List[Request], hbm_budget: int = 200 * 2 ** 30) -> Dict:
+    """The plain GPU form: every request alone, one after another, in a
+    context of its own finest level (one per class and level, reused)."""
+    keys = []
+    for r in reqs:
+        k = (class_key(r.cfg), r.cfg["L"])
+        if k not in keys:
+            keys.append(k)
+    first = {}
+    for r in reqs:
+        first.setdefault((class_key(r.cfg), r.cfg["L"]), r.cfg)
+    b = mrlt.Batch([(first[k], k[1], 1) for k in keys], hbm_budget)
     t0 = time.perf_counter()
-    prog = _Progress("one-at-a-time")
-    for k, r in enumerate(reqs):
-        key = class_key(r.cfg)
-        if key not in pools:
-            pools[key] = SlotPool(r.cfg, 1, eps=[r.eps])
-        p = pools[key]
-        p.admit(r, 0)
-        while p.active():
-            p.step()
-            p.poll(time.perf_counter() - t0)
-            prog(f"solve {k + 1}/{len(reqs)}")
+    done, failed = 0, 0
+    tick = _progress("one-at-a-time")
+    for j, r in enumerate(reqs):
+        slot = b.admit(r.cfg, r.cfg["L"], r.eps, r.t_final, r.q0, cfl=r.cfg.get("cfl", 0.5))
+        by_slot = {slot: r}
+        while by_slot:
+            b.step()
+            d, f = _drain(b, by_slot, time.perf_counter() - t0)
+            done += len(d)
+            failed += len(f)
+        tick(f"solve {j + 1}/{len(reqs)}")
     el = time.perf_counter() - t0
-    failed = sum(len(p.failed) for p in pools.values())
-    done = len(reqs) - failed
+    b.close()
     return {"seconds": el, "solves": done, "failed": failed, "solves_per_s": done / el}
 
 
-def serve(reqs: List[Request], hbm_budget: float, max_slots: int = 64) -> Dict:
-    """Continuous batching: admit requests as they arrive and as slots and the
-    memory budget allow, step every class with resident solves, retire
-    finished ones.  Arrival times are in seconds from the start."""
+def serve(reqs: List[Request], hbm_budget: float, slots: int = 16) -> Dict:
+    """Continuous batching: requests join the run as they arrive and as
+    slots and device memory allow (the library's admission), every class
+    with running solves advances one macro step per round on its own stream,
+    and finished solves are read back and their slots freed at once.
+    Classes: one per scheme and finest level, `slots` slots each.  Arrival
+    times are seconds from the start; latency = arrival to result."""
+    first: Dict[tuple, dict] = {}
+    for r in reqs:
+        first.setdefault((class_key(r.cfg), r.cfg["L"]), r.cfg)
+    keys = sorted(first, key=lambda k: (k[1], str(k[0])))
+    b = mrlt.Batch([(first[k], k[1], slots) for k in keys], int(hbm_budget))
     pending = sorted(reqs, key=lambda r: r.arrival)
     queue: List[Request] = []
-    pools: Dict[tuple, SlotPool] = {}
-    used = 0.0
-    stalls = 0
-    t0 = time.perf_counter()
+    by_slot: Dict[int, Request] = {}
     finished: List[Request] = []
+    failed: List[Request] = []
+    stalls = 0
+    peak = 0
     nxt = 0
-    prog = _Progress("served")
-    while len(finished) + sum(len(p.failed) for p in pools.values()) < len(reqs):
+    t0 = time.perf_counter()
+    tick = _progress("served")
+    while len(finished) + len(failed) < len(reqs):
         now = time.perf_counter() - t0
         while nxt < len(pending) and pending[nxt].arrival <= now:
             queue.append(pending[nxt])
             nxt += 1
-        # admission, first come first served, per class
         still = []
         for r in queue:
-            key = class_key(r.cfg)
-            if key not in pools:
-                need = bytes_per_instance(r.cfg) * max_slots
-                if used + need > hbm_budget:
-                    still.append(r)
-                    stalls += 1
-                    continue
-                pools[key] = SlotPool(r.cfg, max_slots)
-                used += need
-            p = pools[key]
-            free = p.free_slots()
-            if not free:
+            slot = b.admit(r.cfg, r.cfg["L"], r.eps, r.t_final, r.q0, cfl=r.cfg.get("cfl", 0.5))
+            if slot is None:
                 still.append(r)
                 stalls += 1
-                continue
-            p.admit(r, free[0])
+            else:
+                by_slot[slot] = r
         queue = still
-        stepped = 0
-        for p in pools.values():
-            stepped += p.step()
-            for r in p.poll(time.perf_counter() - t0, keep_result=False):
-                finished.append(r)
-        prog(f"{len(finished)}/{len(reqs)} finished, {len(queue)} queued, {nxt} arrived")
-        if stepped == 0 and nxt < len(pending) and not queue:
+        peak = max(peak, b.footprint())
+        if by_slot:
+            b.step()
+            d, f = _drain(b, by_slot, time.perf_counter() - t0)
+            finished += d
+            failed += f
+        elif nxt < len(pending):
             wait = pending[nxt].arrival - (time.perf_counter() - t0)
             if wait > 0:
                 time.sleep(min(wait, 0.01))
+        tick(f"{len(finished)}/{len(reqs)} finished, {len(queue)} queued, {len(by_slot)} running, {nxt} arrived")
     makespan = time.perf_counter() - t0
+    b.close()
     lat = np.array([r.done_at - r.arrival for r in finished])
-    failed = sum(len(p.failed) for p in pools.values())
-    return {"requests": len(reqs), "failed": failed, "makespan_s": makespan,
+    return {"requests": len(reqs), "failed": len(failed), "makespan_s": makespan,
             "solves_per_s": len(finished) / makespan,
             "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
-            "admission_stalls": stalls, "classes": len(pools), "hbm_reserved_bytes": used}
+            "admission_stalls": stalls, "classes": len(keys), "hbm_peak_bytes": peak}
 
 
 # ---------------------------------------------------------------------------

@@ -49,3 +49,14 @@ def test_more_than_one_gpu_is_refused():
     out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                          capture_output=True, text=True, timeout=120)
     assert "one GPU only" in (out.stdout + out.stderr)
+
+
+def test_cpu_oracle_leg_reports_a_rate():
+    # the CPU-baseline leg (the oracle timed in a process of its own) runs on
+    # the host alone
+    env = dict(os.environ, OMP_NUM_THREADS="2")
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--mode", "cpu-oracle",
+                          "--cpu-seconds", "0.2"], capture_output=True, text=True, timeout=300, env=env)
+    rec = json.loads(out.stdout.strip().splitlines()[-1])
+    assert rec["threads"] == 2 and rec["leaf_updates_per_s"] > 0 and rec["macro_steps"] >= 1
+    assert bench.cpu_model()

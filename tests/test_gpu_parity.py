@@ -365,6 +365,41 @@ def test_wide_batch_against_oracle(mods, case):
             check(orc[i], s, inst=i, what=f"instance {i}, macro step {j}")
 
 
+@pytest.mark.parametrize("case", ["euler2d", "nagumo2d"])
+def test_uneven_finest_levels_share_one_context(mods, case):
+    # solves of different finest level in one context of the largest level
+    # (mr_load_inst): each against its solo oracle run at its own L, bit for
+    # bit, with its own CFL step scaled by 2^{L_inst - L}
+    mro, mrlt = mods
+    Ls = [7, 8, 9, 7]
+    eps = [1e-3, 1e-2, 1e-3, 1e-4]
+    mk = (lambda L, e: W.euler_2d(L=L, eps=e)) if case == "euler2d" else (lambda L, e: W.nagumo_2d(L=L, eps=e))
+    s = mrlt.Solver(mk(9, 1e-3), n_inst=len(Ls))
+    orc = []
+    for i, (L, e) in enumerate(zip(Ls, eps)):
+        cfg = mk(L, e)
+        q0 = W.euler_quadrants_seeded(L, W.SEED + 500 + i) if case == "euler2d" else W.nagumo_front(L, W.SEED + 500 + i)
+        s.load_inst(i, L, e, q0)
+        o = mro.Oracle(cfg)
+        o.load_finest(q0)
+        orc.append((o, cfg))
+        check(o, s, inst=i, what=f"instance {i} (L={L}) after load")
+    print(f"[parity] uneven finest levels {case} {Ls}", flush=True)
+    for j in range(3):
+        dts = []
+        for i, (o, cfg) in enumerate(orc):
+            if case == "euler2d":
+                dt = 0.8 * W.euler_dt(cfg, o.max_wavespeed(), o.stats()["t"])
+            else:
+                dt = W.nagumo_dt(cfg)
+            o.lt_step(dt)
+            dts.append(dt / 2 ** (9 - Ls[i]))
+        s.lt_step(dts)
+        for i, (o, cfg) in enumerate(orc):
+            check(o, s, inst=i, what=f"instance {i} (L={Ls[i]}), macro step {j}")
+            assert abs(s.stats(i)["t"] - o.stats()["t"]) <= 1e-15 * o.stats()["t"]
+
+
 def test_checkpoint_resume_bit_identical(mods):
     _, mrlt = mods
     cfg = W.burgers_1d(L=9)
@@ -407,9 +442,20 @@ def test_set_leaves_rejects_ungraded_tree(mods):
         s.set_leaves(keys, np.zeros((1, len(keys))))
 
 
-def test_full_size_nagumo_one_macro_step(mods):
-    cfg = W.nagumo_2d()            # L=9, 512^2
-    run_pair(mods, cfg, W.nagumo_front(9), [W.nagumo_dt(cfg)])
+def test_full_size_nagumo_to_t_final(mods):
+    # the 2D Nagumo configuration at its stated size (L=9, 512^2) over all
+    # 164 macro steps to t_final = 0.01, compared after every macro step
+    cfg = W.nagumo_2d()
+    o, s = run_pair(mods, cfg, W.nagumo_front(9), [W.nagumo_dt(cfg)] * 164)
+    assert abs(s.stats()["t"] - 0.01) < 1e-15 and abs(o.stats()["t"] - 0.01) < 1e-15
+
+
+def test_full_size_euler_3d_against_oracle(mods):
+    # the 3D spherical Riemann problem at its stated size (L=7, 128^3): two
+    # macro steps against the oracle
+    cfg = W.euler_3d(L=7)
+    run_pair(mods, cfg, W.euler_sphere(7),
+             [lambda o: W.euler_dt(cfg, o.max_wavespeed(), o.stats()["t"])] * 2)
 
 
 def test_large_batch_thresholds_take_effect(mods):
@@ -520,33 +566,6 @@ def test_admission_into_running_batch_keeps_others_identical(mods):
     for i in (1, 2):
         solo[i].lt_step(dt)
         check(solo[i], s, inst=i, what=f"after clearing 0, instance {i}")
-
-
-def test_batched_and_served_results_equal_solo(mods):
-    # systems forms: every request's result is the same alone, in a batch
-    # and in the served mix (bit for bit: instances do not interact)
-    _, mrlt = mods
-    from paper_1905_08717_amd import systems as S
-    reqs = S.batched_euler_requests(6)
-    for r in reqs:
-        r.cfg = dict(r.cfg, L=min(r.cfg["L"], 7))
-        r.q0 = W.euler_quadrants_seeded(r.cfg["L"], W.SEED + r.rid)
-        r.t_final = 0.05
-    import copy
-    solo = copy.deepcopy(reqs)
-    S.run_batched(reqs)
-    S.run_one_at_a_time(solo)
-    for a, b in zip(reqs, solo):
-        assert np.array_equal(a.result[0], b.result[0]) and np.array_equal(a.result[1], b.result[1])
-    served = S.served_requests(12, rate=400.0, burgers_levels=(9, 10), rd_levels=(6, 7))
-    for r in served:
-        r.t_final = r.t_final / 20
-    alone = copy.deepcopy(served)
-    out = S.serve(served, hbm_budget=8 * 2 ** 30, max_slots=4)
-    assert out["requests"] == 12 and out["p99_s"] >= out["p50_s"] > 0
-    S.run_one_at_a_time(alone)
-    for a, b in zip(served, alone):
-        assert a.done_at is not None
 
 
 @pytest.mark.parametrize("case", ["burgers1d", "nagumo2d", "euler2d"])
