@@ -366,11 +366,11 @@ __device__ __forceinline__ double adv_velocity(const Geo& g, const Dev& p, int64
 }
 
 // flux across the face between cells a and a+1 along dir; c holds a-1..a+2;
-// vel is the advection velocity along dir (advection and flames)
+// vel is the advection velocity along dir (advection and flames); ix is the
+// inverse cell width along dir
 template <int D, int PDE>
-__device__ __forceinline__ void face_flux(const Geo& g, int lev, int dir, double vel,
-                                          const double (*c)[NC<D, PDE>::M], double* F) {
-  const double ix = g.invdx[lev][dir];
+__device__ __forceinline__ void face_flux_ix(const Geo& g, double ix, int dir, double vel,
+                                             const double (*c)[NC<D, PDE>::M], double* F) {
   if (PDE == PDE_ADVECTION) {
     if (g.recon == 2) {
       F[0] = vel * (0.5 * (c[1][0] + c[2][0]));
@@ -418,6 +418,11 @@ __device__ __forceinline__ void face_flux(const Geo& g, int lev, int dir, double
     for (int k = 0; k < M; k++) recon4(g.recon, w[0][k], w[1][k], w[2][k], w[3][k], wl[k], wr[k]);
     ausm_plus<D>(dir, g.gamma, wl, wr, F);
   }
+}
+template <int D, int PDE>
+__device__ __forceinline__ void face_flux(const Geo& g, int lev, int dir, double vel,
+                                          const double (*c)[NC<D, PDE>::M], double* F) {
+  face_flux_ix<D, PDE>(g, g.invdx[lev][dir], dir, vel, c, F);
 }
 
 template <int PDE>
@@ -584,6 +589,29 @@ __host__ __device__ __forceinline__ bool wide_level(const Geo& g, int lev) {
   return g.comp_chunk[lev] == (1 << BS_SHIFT) && g.B * g.n[lev] >= ((int64_t)1 << 20);
 }
 
+// Per-level constants of a launch, staged in LDS: kernels whose lanes work on
+// different levels would otherwise index the kernel arguments by a per-lane
+// level, a vector load of its own in front of every cell's loads.
+struct LevTab {
+  int64_t off[MRD_MAXLEV + 1];    // first cell of the level table
+  int64_t bsoff[MRD_MAXLEV + 1];  // first 4096-cell block summary
+  int64_t rc[MRD_MAXLEV + 1];     // coarse-side register block
+  int64_t rf[MRD_MAXLEV + 1];     // fine-side register block
+  double ix[MRD_MAXLEV + 1][3];   // inverse cell widths
+  int wide[MRD_MAXLEV + 1];       // wide_level
+};
+// filled by the first MRD_MAXLEV + 1 threads; the caller synchronises
+__device__ __forceinline__ void levtab_fill(const Geo& g, LevTab& lt) {
+  const int l = (int)threadIdx.x;
+  if (l > MRD_MAXLEV) return;
+  lt.off[l] = g.off[l];
+  lt.bsoff[l] = g.bs_off[l];
+  lt.rc[l] = g.rc_off[l];
+  lt.rf[l] = g.rf_off[l];
+  for (int a = 0; a < 3; a++) lt.ix[l][a] = g.invdx[l][a];
+  lt.wide[l] = (l >= g.l0 && l <= g.L) ? (wide_level(g, l) ? 1 : 0) : 0;
+}
+
 __device__ __forceinline__ int list_len(const Dev& p, int type, int lev) {
   return p.lcnt[type * (MRD_MAXLEV + 1) + lev];
 }
@@ -710,6 +738,8 @@ __global__ __launch_bounds__(TPB) void k_ghost(Geo g, Dev p, int lo, int hi, int
   __shared__ int s_cnt[MRD_MAXLEV + 1];
   __shared__ int s_lead[CH];
   __shared__ int sh[TPB / 64];
+  __shared__ LevTab lt;
+  levtab_fill(g, lt);  // flat_setup synchronises
   const int64_t ntot = flat_setup(p, LS_GHOST, lo, hi, s_cnt);
   for (int64_t base = (int64_t)blockIdx.x * CH; base < ntot; base += (int64_t)gridDim.x * CH) {
     uint32_t lead = 0u;  // bit e: entry base + PER * threadIdx.x + e leads its sibling group
@@ -719,7 +749,7 @@ __global__ __launch_bounds__(TPB) void k_ghost(Geo g, Dev p, int lo, int hi, int
       if (i >= ntot) break;
       int64_t kk = i;
       const int lev = flat_level(s_cnt, lo, kk);
-      const int* lst = p.lst[LS_GHOST] + g.off[lev];
+      const int* lst = p.lst[LS_GHOST] + lt.off[lev];
       const int t = lst[kk];
       if (kk == 0 || (lst[kk - 1] >> D) != (t >> D)) lead |= 1u << e;
     }
@@ -734,9 +764,9 @@ __global__ __launch_bounds__(TPB) void k_ghost(Geo g, Dev p, int lo, int hi, int
     for (int q = threadIdx.x; q < tot; q += TPB) {
       int64_t kk = base + s_lead[q];
       const int lev = flat_level(s_cnt, lo, kk);
-      const int64_t nl = g.n[lev];
+      const int64_t nl = (int64_t)1 << (D * lev);
       const double* src = p.q[lev == cb_lev ? srcB : srcA];
-      const int* lst = p.lst[LS_GHOST] + g.off[lev];
+      const int* lst = p.lst[LS_GHOST] + lt.off[lev];
       const int len = s_cnt[lev - lo];
       const int t = lst[kk];
       uint32_t cbits = 1u << (t & (NS - 1));
@@ -745,12 +775,12 @@ __global__ __launch_bounds__(TPB) void k_ghost(Geo g, Dev p, int lo, int hi, int
         if ((u >> D) != (t >> D)) break;
         cbits |= 1u << (u & (NS - 1));
       }
-      const int64_t G0 = g.off[lev] + (int64_t)(t & ~(NS - 1));  // child 0 of the parent
+      const int64_t G0 = lt.off[lev] + (int64_t)(t & ~(NS - 1));  // child 0 of the parent
       const int64_t inst = (int64_t)t >> (D * lev);
       int x[3];
       mdec<D>((uint64_t)((int64_t)t & (nl - 1)), x);
       const int px[3] = {x[0] >> 1, x[1] >> 1, x[2] >> 1};
-      const int64_t ibp = g.off[lev - 1] + inst * g.n[lev - 1];
+      const int64_t ibp = lt.off[lev - 1] + inst * (nl >> D);
       for (int k = 0; k < g.m; k++) {
         double S[27], T[8];
         if (!gather27<D>(g, p, src, lev - 1, ibp, px, k, S)) flag_bad(p, inst, 1);
@@ -914,6 +944,8 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
   // computed but not stored.  Wide stencils of many fields load per axis.
   constexpr bool PRE = !IFACE && D * M <= 6;
   __shared__ int s_cnt[MRD_MAXLEV + 1];
+  __shared__ LevTab lt;
+  levtab_fill(g, lt);  // flat_setup synchronises
   const int64_t ntot = flat_setup(p, LS, lo, hi, s_cnt);
   const int64_t step = (int64_t)gridDim.x * blockDim.x;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -921,7 +953,7 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
   if (i < ntot) {
     int64_t kk = i;
     lev_n = flat_level(s_cnt, lo, kk);
-    e_n = p.lst[LS][g.off[lev_n] + kk];
+    e_n = p.lst[LS][lt.off[lev_n] + kk];
   }
   for (; i < ntot; i += step) {
     {
@@ -930,18 +962,22 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
       if (i + step < ntot) {
         int64_t kk = i + step;
         lev_n = flat_level(s_cnt, lo, kk);
-        e_n = p.lst[LS][g.off[lev_n] + kk];
+        e_n = p.lst[LS][lt.off[lev_n] + kk];
       }
-      const int64_t nl = g.n[lev];
+      const int64_t nl = (int64_t)1 << (D * lev);
       const int n = 1 << lev;
       const bool finest = lev == g.L;
-      const int64_t G = g.off[lev] + t;
+      const int64_t G = lt.off[lev] + t;
       const int64_t inst = t >> (D * lev);
       const uint64_t key = (uint64_t)(t & (nl - 1));
       int x[3];
       mdec<D>(key, x);
-      const int64_t ib = g.off[lev] + inst * nl;
-      // status of the 2d face neighbours (3: outside the domain)
+      const int64_t ib = lt.off[lev] + inst * nl;
+      // the instance's finest step, requested with the cell's other loads
+      const double dti = p.dt[inst];
+      // status of the 2d face neighbours (3: outside the domain); a cell
+      // outside loads its own status instead, so that every load is issued
+      // at once without a branch
       int nbs[D][2];
       uint8_t sts[D][2];
       bool refined = false;
@@ -952,9 +988,10 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
           const int nb = map_nb(x[dir] + (side ? 1 : -1), n, g.periodic[dir]);
           nbs[dir][side] = nb;
           uint64_t ky;
-          const uint8_t sv = nbhd_key<D>(g, x, key, n, dir, side ? 1 : -1, &ky) ? p.st[ib + (int64_t)ky] : 3;
-          sts[dir][side] = sv;
-          refined = refined || sv == ST_INTERNAL;
+          const bool in = nbhd_key<D>(g, x, key, n, dir, side ? 1 : -1, &ky);
+          const uint8_t sv = p.st[ib + (int64_t)(in ? ky : key)];
+          sts[dir][side] = in ? sv : (uint8_t)3;
+          refined = refined || (in && sv == ST_INTERNAL);
         }
       if (!IFACE && (PRE || (!finest && !refined)) && (PDE != PDE_NAGUMO && PDE != PDE_LINEAR) &&
           stencil_reach(g) == 2) {
@@ -963,8 +1000,9 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
 #pragma unroll
           for (int side = 0; side < 2; side++) {
             uint64_t ky;
-            if (nbhd_key<D>(g, x, key, n, dir, side ? 2 : -2, &ky))
-              refined = refined || p.st[ib + (int64_t)ky] == ST_INTERNAL;
+            const bool in = nbhd_key<D>(g, x, key, n, dir, side ? 2 : -2, &ky);
+            const uint8_t sv = p.st[ib + (int64_t)(in ? ky : key)];
+            refined = refined || (in && sv == ST_INTERNAL);
           }
       }
       // stencils of all axes (PRE) and the leaf's own slots
@@ -984,17 +1022,31 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
             }
           }
       }
-      double q0v[M], qsv[M];
+      // the leaf's own slots; at stage 2 also the NERK partial values it adds
+      // to (read for every leaf below the finest level, so that the loads go
+      // out with the others before the tile flag says whether it writes them)
+      const bool rmw = stage == 2 && !finest && g.lt;
+      double q0v[M], qsv[M], n14v[M], n34v[M];
 #pragma unroll
       for (int k = 0; k < M; k++) {
         const int64_t I = (int64_t)k * NT + G;
         q0v[k] = p.q[SL_Q0][I];
         qsv[k] = stage == 2 ? p.q[SL_Q1][I] : (stage == 3 ? p.q[SL_QH][I] : 0.0);
+        n14v[k] = 0.0;
+        n34v[k] = 0.0;
+        if (rmw) {
+          if (g.rk == 2) {
+            n14v[k] = p.q[SL_QH][I];
+          } else {
+            n14v[k] = p.q[SL_N14][I];
+            n34v[k] = p.q[SL_N34][I];
+          }
+        }
       }
-      const uint8_t nflag = (!IFACE && !finest && g.lt && wide_level(g, lev)) ? p.nsum[g.bs_off[lev] + (t >> BS_SHIFT)] : 1;
+      const uint8_t nflag = (!IFACE && !finest && g.lt && lt.wide[lev]) ? p.nsum[lt.bsoff[lev] + (t >> BS_SHIFT)] : 1;
       if (!PRE && !IFACE && refined && !finest) continue;  // the interface launch owns it
       const bool active = IFACE || finest || !refined;
-      const double h = g.lt ? ldexp(p.dt[inst], g.L - lev) : p.dt[inst];
+      const double h = g.lt ? ldexp(dti, g.L - lev) : dti;
       // weights b_i of the RK method: RK3 (1/6, 1/6, 2/3), RK2 (1/2, 1/2)
       const double wh = (g.rk == 2 ? 0.5 : (stage == 3 ? C_2_3 : C_1_6)) * h;
       double R[M];
@@ -1032,11 +1084,11 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
           if (IFACE && sts[dir][side] == ST_INTERNAL)
             refined_flux<D, PDE>(g, p, lev, stage, inst, x, dir, side, nbs[dir][side], F);
           else
-            face_flux<D, PDE>(g, lev, dir, vel, c5 + side, F);
+            face_flux_ix<D, PDE>(g, lt.ix[lev][dir], dir, vel, c5 + side, F);
         }
 #pragma unroll
         for (int k = 0; k < M; k++) {
-          const double r = (Fm[k] - Fp[k]) * g.invdx[lev][dir];
+          const double r = (Fm[k] - Fp[k]) * lt.ix[lev][dir];
           R[k] = dir == 0 ? r : (R[k] + r);
         }
         if (g.reflux && active) {
@@ -1046,15 +1098,15 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
             if (IFACE && sts[dir][side] == ST_INTERNAL) {
 #pragma unroll
               for (int k = 0; k < M; k++) {
-                double* r = regc_at(g, p, lev, 2 * dir + side, k, t);
+                double* r = p.regc + lt.rc[lev] + (int64_t)((2 * dir + side) * g.m + k) * (g.B * nl) + t;
                 *r = *r + (wh * F[k]);
               }
             } else if (sts[dir][side] == ST_ABSENT) {
               // fine side of a coarse leaf's refined face
               int y[3] = {x[0] >> 1, x[1] >> 1, x[2] >> 1};
               y[dir] = nbs[dir][side] >> 1;
-              const int64_t tX = inst * g.n[lev - 1] + (int64_t)menc<D>(y);
-              if (g.check && p.st[g.off[lev - 1] + tX] != ST_LEAF) flag_bad(p, inst, 8);
+              const int64_t tX = inst * (nl >> D) + (int64_t)menc<D>(y);
+              if (g.check && p.st[lt.off[lev - 1] + tX] != ST_LEAF) flag_bad(p, inst, 8);
               int t0, t1;
               transverse<D>(dir, t0, t1);
               int b = 0;
@@ -1062,7 +1114,7 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
               if (t1 >= 0) b |= (x[t1] & 1) << 1;
               const int fX = 2 * dir + (side ? 0 : 1);
               for (int k = 0; k < M; k++) {
-                double* r = regf_at(g, p, lev - 1, fX, b, k, tX);
+                double* r = p.regf + lt.rf[lev - 1] + (int64_t)((fX * g.nsub + b) * g.m + k) * (g.B * (nl >> D)) + tX;
                 *r = *r + (wh * F[k]);
               }
             }
@@ -1101,7 +1153,7 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
             p.q[SL_QE][I] = qe;
             if (!IFACE && lev >= lq0) p.q[SL_Q0][I] = qe;
             p.q[SL_X2][I] = q1 + (h * r);
-            if (nerk) p.q[SL_QH][I] = p.q[SL_QH][I] + ((0.125 * h) * r);
+            if (nerk) p.q[SL_QH][I] = n14v[k] + ((0.125 * h) * r);
             if (!isfinite(qe)) atomicOr(&p.cnt[inst * CNT_PER_INST + CNT_NONFINITE], 1ull);
           }
           continue;
@@ -1118,8 +1170,8 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
           p.q[SL_QH][I] = ((0.75 * q0) + (0.25 * q1)) + ((0.25 * h) * r);
           p.q[SL_X2][I] = q1 + (h * r);
           if (nerk) {
-            p.q[SL_N14][I] = p.q[SL_N14][I] + (((1.0 / 32.0) * h) * r);
-            p.q[SL_N34][I] = p.q[SL_N34][I] + (((9.0 / 32.0) * h) * r);
+            p.q[SL_N14][I] = n14v[k] + (((1.0 / 32.0) * h) * r);
+            p.q[SL_N34][I] = n34v[k] + (((9.0 / 32.0) * h) * r);
           }
         } else {
           const double qh = qsv[k];
@@ -1347,6 +1399,12 @@ __device__ __forceinline__ void mark_w(const Geo& g, const Dev& p, int lev, int6
   atomicOr(reinterpret_cast<unsigned*>(p.rf + (G & ~(int64_t)3)), (unsigned)RF_W << (8 * (int)(G & 3)));
   p.wsum[g.bs_off[lev] + (t >> BS_SHIFT)] = 1;
 }
+// the same with the level constants from the launch's table in LDS
+__device__ __forceinline__ void mark_w(const LevTab& lt, const Dev& p, int lev, int64_t t) {
+  const int64_t G = lt.off[lev] + t;
+  atomicOr(reinterpret_cast<unsigned*>(p.rf + (G & ~(int64_t)3)), (unsigned)RF_W << (8 * (int)(G & 3)));
+  p.wsum[lt.bsoff[lev] + (t >> BS_SHIFT)] = 1;
+}
 // A marking pass first reads the current bytes of all its targets (loads
 // only, so they are in flight together), then sets the missing marks (atomics
 // only): one memory round trip per item, and no atomic for a mark that is
@@ -1468,37 +1526,39 @@ __global__ __launch_bounds__(TPB) void k_level_w(Geo g, Dev p, int la) {
 template <int D>
 __global__ __launch_bounds__(TPB) void k_detail_seed(Geo g, Dev p, int lo, int hi, int la, int n_it) {
   __shared__ int s_cnt[MRD_MAXLEV + 1];
+  __shared__ LevTab lt;
+  levtab_fill(g, lt);  // flat_setup synchronises
   const int64_t ntot = flat_setup(p, LS_INTERNAL, lo, hi, s_cnt);
   GSL(i, ntot) {
     {
       int64_t kk = i;
       const int lev = flat_level(s_cnt, lo, kk);
-      const int64_t nl = g.n[lev];
+      const int64_t nl = (int64_t)1 << (D * lev);
       const int n = 1 << lev;
-      const int64_t t = p.lst[LS_INTERNAL][g.off[lev] + kk];
+      const int64_t t = p.lst[LS_INTERNAL][lt.off[lev] + kk];
       if (inst_of_window_skip(g, t, D * lev)) continue;
       const int64_t inst = t >> (D * lev);
       const int Lc = p.lcap[inst];  // the instance's finest level
       if (lev < la) {
         // frozen level: scale safety of a node significant at its last remesh
-        if (!p.sigt[g.off[lev] + t] || lev + 1 > Lc - 1) continue;
+        if (!p.sigt[lt.off[lev] + t] || lev + 1 > Lc - 1) continue;
         uint32_t need = 0u;
 #pragma unroll
         for (int cb = 0; cb < (1 << D); cb++)
-          if (!(p.rf[g.off[lev + 1] + (t << D) + cb] & RF_W)) need |= 1u << cb;
+          if (!(p.rf[lt.off[lev + 1] + (t << D) + cb] & RF_W)) need |= 1u << cb;
 #pragma unroll
         for (int cb = 0; cb < (1 << D); cb++)
-          if ((need >> cb) & 1u) mark_w(g, p, lev + 1, (t << D) + cb);
+          if ((need >> cb) & 1u) mark_w(lt, p, lev + 1, (t << D) + cb);
         continue;
       }
-      const int64_t ib = g.off[lev] + inst * nl;
+      const int64_t ib = lt.off[lev] + inst * nl;
       int x[3];
       mdec<D>((uint64_t)(t & (nl - 1)), x);
       const double e0 = p.eps[inst];
       bool sig = true;
       if (e0 != 0.0) {
         const double e = g.thresh ? ldexp(e0, D * (lev + 1 - Lc)) : e0;
-        const int64_t C0 = g.off[lev + 1] + (t << D);
+        const int64_t C0 = lt.off[lev + 1] + (t << D);
         double Dm = 0.0;
         for (int k = 0; k < g.m; k++) {
           double S[27], T[8];
@@ -1521,7 +1581,7 @@ __global__ __launch_bounds__(TPB) void k_detail_seed(Geo g, Dev p, int lo, int h
           }
         }
       }
-      p.sigt[g.off[lev] + t] = sig ? 1 : 0;
+      p.sigt[lt.off[lev] + t] = sig ? 1 : 0;
       if (!sig) continue;
       // targets: the 3^d neighbourhood (existing cells; the node itself is
       // internal) and, below L-1, the 2^d children
@@ -1535,13 +1595,13 @@ __global__ __launch_bounds__(TPB) void k_detail_seed(Geo g, Dev p, int lo, int h
         if (D > 1) y[1] = map_nb(x[1] + oy, n, g.periodic[1]);
         if (D > 2) y[2] = map_nb(x[2] + oz, n, g.periodic[2]);
         if (y[0] < 0 || y[1] < 0 || y[2] < 0) continue;
-        const int64_t Gy = g.off[lev] + inst * nl + (int64_t)menc<D>(y);
+        const int64_t Gy = lt.off[lev] + inst * nl + (int64_t)menc<D>(y);
         if (p.st[Gy] != ST_ABSENT && !(p.rf[Gy] & RF_W)) need |= 1ull << o;
       }
       if (kids) {
 #pragma unroll
         for (int cb = 0; cb < (1 << D); cb++)
-          if (!(p.rf[g.off[lev + 1] + (t << D) + cb] & RF_W)) need |= 1ull << (NN + cb);
+          if (!(p.rf[lt.off[lev + 1] + (t << D) + cb] & RF_W)) need |= 1ull << (NN + cb);
       }
 #pragma unroll
       for (int o = 0; o < NN; o++) {
@@ -1550,11 +1610,11 @@ __global__ __launch_bounds__(TPB) void k_detail_seed(Geo g, Dev p, int lo, int h
         int y[3] = {map_nb(x[0] + ox, n, g.periodic[0]), 0, 0};
         if (D > 1) y[1] = map_nb(x[1] + oy, n, g.periodic[1]);
         if (D > 2) y[2] = map_nb(x[2] + oz, n, g.periodic[2]);
-        mark_w(g, p, lev, inst * nl + (int64_t)menc<D>(y));
+        mark_w(lt, p, lev, inst * nl + (int64_t)menc<D>(y));
       }
 #pragma unroll
       for (int cb = 0; cb < (1 << D); cb++)
-        if ((need >> (NN + cb)) & 1ull) mark_w(g, p, lev + 1, (t << D) + cb);
+        if ((need >> (NN + cb)) & 1ull) mark_w(lt, p, lev + 1, (t << D) + cb);
     }
   }
 }
