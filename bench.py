@@ -445,7 +445,7 @@ def main():
                     help="skip the 3D Euler, batched and served legs of the default line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", choices=["throughput", "batched", "served", "copycal", "traffic", "paper",
-                                       "flames", "cpu-oracle"],
+                                       "flames", "cpu-oracle", "euler3d"],
                     default="throughput")
     ap.add_argument("--levels", default="8,9,10", help="paper mode: finest levels")
     ap.add_argument("--flame-levels", default="11,12", help="flames mode: finest levels of the 1D flame")
@@ -468,6 +468,9 @@ def main():
 
     if args.mode == "cpu-oracle":
         cpu_oracle_leg(args.cpu_seconds)
+        return
+    if args.mode == "euler3d":
+        print(json.dumps(euler3d_single(args)), flush=True)
         return
     if args.mode == "copycal":
         copy_calibration()

@@ -949,19 +949,36 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
   const int64_t ntot = flat_setup(p, LS, lo, hi, s_cnt);
   const int64_t step = (int64_t)gridDim.x * blockDim.x;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // a lane's list positions only grow: its level and the offset of that
+  // level in the flat index space are advanced, not searched again
+  int lev_c = lo;
+  int64_t base_c = 0;
+  auto locate = [&](int64_t idx, int64_t& kk) {
+    while (idx - base_c >= s_cnt[lev_c - lo]) {
+      base_c += s_cnt[lev_c - lo];
+      lev_c++;
+    }
+    kk = idx - base_c;
+    return lev_c;
+  };
   int lev_n = lo, e_n = 0;
   if (i < ntot) {
-    int64_t kk = i;
-    lev_n = flat_level(s_cnt, lo, kk);
+    int64_t kk;
+    lev_n = locate(i, kk);
     e_n = p.lst[LS][lt.off[lev_n] + kk];
   }
+  // Nagumo and linear diffusion read only the face neighbours: their bulk
+  // leaves find them from the key bits (edge tests and dilated steps)
+  // without decoding the coordinates, and use one key per neighbour for its
+  // status and its value
+  constexpr bool FAST = !IFACE && (PDE == PDE_NAGUMO || PDE == PDE_LINEAR);
   for (; i < ntot; i += step) {
     {
       const int lev = lev_n;
       const int64_t t = e_n;
       if (i + step < ntot) {
-        int64_t kk = i + step;
-        lev_n = flat_level(s_cnt, lo, kk);
+        int64_t kk;
+        lev_n = locate(i + step, kk);
         e_n = p.lst[LS][lt.off[lev_n] + kk];
       }
       const int64_t nl = (int64_t)1 << (D * lev);
@@ -970,8 +987,8 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
       const int64_t G = lt.off[lev] + t;
       const int64_t inst = t >> (D * lev);
       const uint64_t key = (uint64_t)(t & (nl - 1));
-      int x[3];
-      mdec<D>(key, x);
+      int x[3] = {0, 0, 0};
+      if (!FAST) mdec<D>(key, x);
       const int64_t ib = lt.off[lev] + inst * nl;
       // the instance's finest step, requested with the cell's other loads
       const double dti = p.dt[inst];
@@ -980,19 +997,49 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
       // at once without a branch
       int nbs[D][2];
       uint8_t sts[D][2];
+      uint64_t fkey[D][2];  // FAST: key of the face neighbour's value
+      bool fflip[D][2];     // FAST: Dirichlet sign of that value
       bool refined = false;
+      if (FAST) {
+        const uint32_t k32 = (uint32_t)key;
+        const uint32_t lvm = (D * lev >= 32) ? ~0u : ((1u << (D * lev)) - 1u);
 #pragma unroll
-      for (int dir = 0; dir < D; dir++)
+        for (int dir = 0; dir < D; dir++) {
+          const uint32_t ma = axis_mask<D>(dir) & lvm;
+          const uint32_t bits = k32 & ma;
 #pragma unroll
-        for (int side = 0; side < 2; side++) {
-          const int nb = map_nb(x[dir] + (side ? 1 : -1), n, g.periodic[dir]);
-          nbs[dir][side] = nb;
-          uint64_t ky;
-          const bool in = nbhd_key<D>(g, x, key, n, dir, side ? 1 : -1, &ky);
-          const uint8_t sv = p.st[ib + (int64_t)(in ? ky : key)];
-          sts[dir][side] = in ? sv : (uint8_t)3;
-          refined = refined || (in && sv == ST_INTERNAL);
+          for (int side = 0; side < 2; side++) {
+            const bool edge = side ? bits == ma : bits == 0u;
+            const bool per = g.periodic[dir] != 0;
+            uint64_t ky;
+            if (!edge) ky = morton_step<D>(key, dir, side ? 1 : -1);
+            else if (per) ky = (uint64_t)(side ? (k32 & ~ma) : ((k32 & ~ma) | ma));
+            else ky = key;  // even or odd mirror: the cell itself
+            const bool in = !edge || per;
+            fkey[dir][side] = ky;
+            fflip[dir][side] = edge && !per && ((g.dirichlet[dir] >> side) & 1);
+            const uint8_t sv = p.st[ib + (int64_t)ky];
+            sts[dir][side] = in ? sv : (uint8_t)3;
+            nbs[dir][side] = in ? 0 : -1;  // coordinates only where needed (below)
+            refined = refined || (in && sv == ST_INTERNAL);
+          }
         }
+      } else {
+#pragma unroll
+        for (int dir = 0; dir < D; dir++)
+#pragma unroll
+          for (int side = 0; side < 2; side++) {
+            const int nb = map_nb(x[dir] + (side ? 1 : -1), n, g.periodic[dir]);
+            nbs[dir][side] = nb;
+            uint64_t ky;
+            const bool in = nbhd_key<D>(g, x, key, n, dir, side ? 1 : -1, &ky);
+            const uint8_t sv = p.st[ib + (int64_t)(in ? ky : key)];
+            sts[dir][side] = in ? sv : (uint8_t)3;
+            fkey[dir][side] = in ? ky : key;
+            fflip[dir][side] = false;
+            refined = refined || (in && sv == ST_INTERNAL);
+          }
+      }
       if (!IFACE && (PRE || (!finest && !refined)) && (PDE != PDE_NAGUMO && PDE != PDE_LINEAR) &&
           stencil_reach(g) == 2) {
 #pragma unroll
@@ -1014,7 +1061,15 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
           for (int o = -2; o <= 2; o++) {
             if (two_point<PDE>(g) && (o == -2 || o == 2)) continue;
             bool fl = false;
-            const int64_t Gy = o == 0 ? G : ib + (int64_t)stencil_key<D>(g, x, key, n, dir, o, &fl);
+            int64_t Gy;
+            if (o == 0) {
+              Gy = G;
+            } else if (FAST) {
+              Gy = ib + (int64_t)fkey[dir][o > 0];
+              fl = fflip[dir][o > 0];
+            } else {
+              Gy = ib + (int64_t)stencil_key<D>(g, x, key, n, dir, o, &fl);
+            }
 #pragma unroll
             for (int k = 0; k < M; k++) {
               const double v = cur[(int64_t)k * NT + Gy];
@@ -1103,8 +1158,10 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
               }
             } else if (sts[dir][side] == ST_ABSENT) {
               // fine side of a coarse leaf's refined face
+              if (FAST) mdec<D>(key, x);
+              const int nb = FAST ? map_nb(x[dir] + (side ? 1 : -1), n, g.periodic[dir]) : nbs[dir][side];
               int y[3] = {x[0] >> 1, x[1] >> 1, x[2] >> 1};
-              y[dir] = nbs[dir][side] >> 1;
+              y[dir] = nb >> 1;
               const int64_t tX = inst * (nl >> D) + (int64_t)menc<D>(y);
               if (g.check && p.st[lt.off[lev - 1] + tX] != ST_LEAF) flag_bad(p, inst, 8);
               int t0, t1;
