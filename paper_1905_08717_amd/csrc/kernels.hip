@@ -17,6 +17,9 @@
 
 static constexpr int TPB = 256;
 
+// s_waitcnt vmcnt(0) alone (expcnt and lgkmcnt at their no-wait maxima)
+__device__ __forceinline__ void vm_wait_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 int blocks_for(int64_t n) {
   int64_t b = (n + TPB - 1) / TPB;
   if (b < 1) b = 1;
@@ -637,42 +640,83 @@ __device__ __forceinline__ int flat_level(const int* s_cnt, int lo, int64_t& k) 
 }
 
 // the mode is a template argument, so each mode loads only what it uses;
-// the next list entry is fetched while a node is processed
-template <int mode>
+// the next list entry is fetched while a node is processed, and a node's
+// loads (children of every field, its own values the mode combines) are all
+// issued before the first is used: one memory round trip per node, two where
+// the mode selects a child's slot by the child's status
+template <int D, int mode>
 __global__ __launch_bounds__(TPB) void k_project(Geo g, Dev p, int lev) {
-  const int nch = 1 << g.d;
-  const double sc = g.d == 1 ? 0.5 : (g.d == 2 ? 0.25 : 0.125);
+  constexpr int NCH = 1 << D;
+  constexpr int MF = D + 2;  // most fields of any PDE in D dimensions
+  constexpr double sc = D == 1 ? 0.5 : (D == 2 ? 0.25 : 0.125);
+  constexpr bool NEED_ST = mode == PJ_REF2;
   const int64_t NT = g.Ntot;
+  const int m = g.m;
   const int n = list_len(p, LS_INTERNAL, lev);
   const int* lst = p.lst[LS_INTERNAL] + g.off[lev];
-  constexpr bool NEED_ST = mode == PJ_REF2 || mode == PJ_RK2;
   const int step = (int)(gridDim.x * blockDim.x);
   int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   int t_next = i < n ? lst[i] : 0;
+  // wait for the first entry here: the loop then needs no wait at its top,
+  // where one would also cover the previous pass's stores (the vector memory
+  // counter counts loads and stores in issue order) and put a store round
+  // trip before every pass's loads
+  vm_wait_all();
   for (; i < n; i += step) {
     const int64_t t = t_next;
     if (i + step < n) t_next = lst[i + step];
     const int64_t G = g.off[lev] + t;
-    const int64_t C0 = g.off[lev + 1] + (t << g.d);
-    uint8_t cs[8];
-    if (NEED_ST)
-      for (int cb = 0; cb < nch; cb++) cs[cb] = p.st[C0 + cb];
-    for (int k = 0; k < g.m; k++) {
+    const int64_t C0 = g.off[lev + 1] + (t << D);
+    bool leaf[NCH];
+#pragma unroll
+    for (int cb = 0; cb < NCH; cb++) leaf[cb] = NEED_ST ? p.st[C0 + cb] == ST_LEAF : true;
+    double v[MF][NCH], o0[MF], o1[MF], o2[MF];
+#pragma unroll
+    for (int k = 0; k < MF; k++) {
+      if (k >= m) break;
       const int64_t kk = (int64_t)k * NT;
-      double s = 0.0;
-      for (int cb = 0; cb < nch; cb++) {
+#pragma unroll
+      for (int cb = 0; cb < NCH; cb++) {
         const int64_t C = kk + C0 + cb;
-        double v;
-        if (mode == PJ_Q0 || mode == PJ_CASEB) v = p.q[SL_Q0][C];
-        else if (mode == PJ_REF2) v = cs[cb] == ST_LEAF ? p.q[SL_Q1][C] : p.q[SL_Q1REF][C];
-        else if (mode == PJ_RK2) v = cs[cb] == ST_LEAF ? p.q[SL_X2][C] : (2.0 * p.q[SL_Q1][C]) - p.q[SL_Q0][C];
-        else if (mode == PJ_REF3 || mode == PJ_ST3) v = p.q[SL_QH][C];
-        else if (mode == PJ_ST2) v = p.q[SL_Q1][C];
-        else v = p.q[SL_QE][C];
-        s = (cb == 0) ? v : (s + v);
+        double x;
+        if (mode == PJ_Q0 || mode == PJ_CASEB) {
+          x = p.q[SL_Q0][C];
+        } else if (mode == PJ_REF2) {
+          x = (leaf[cb] ? p.q[SL_Q1] : p.q[SL_Q1REF])[C];
+        } else if (mode == PJ_RK2) {
+          // a leaf child's X2 is its stage-2 Euler value; an internal
+          // child's X2 was set to 2 Q1 - Q0 by its own level's pass
+          x = p.q[SL_X2][C];
+        } else if (mode == PJ_REF3 || mode == PJ_ST3) {
+          x = p.q[SL_QH][C];
+        } else if (mode == PJ_ST2) {
+          x = p.q[SL_Q1][C];
+        } else {
+          x = p.q[SL_QE][C];
+        }
+        v[k][cb] = x;
       }
-      s = s * sc;
       const int64_t I = kk + G;
+      o0[k] = o1[k] = o2[k] = 0.0;
+      if (mode == PJ_CASEB || mode == PJ_REF3) {
+        o0[k] = p.q[SL_Q0][I];
+        o1[k] = p.q[SL_Q1REF][I];
+      } else if (mode == PJ_REF2 || mode == PJ_RK2) {
+        o0[k] = p.q[SL_Q0][I];
+      } else if (mode == PJ_RK3) {
+        o0[k] = p.q[SL_Q0][I];
+        o1[k] = p.q[SL_N34][I];
+        o2[k] = p.q[SL_N14][I];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < MF; k++) {
+      if (k >= m) break;
+      double s = v[k][0];
+#pragma unroll
+      for (int cb = 1; cb < NCH; cb++) s = s + v[k][cb];
+      s = s * sc;
+      const int64_t I = (int64_t)k * NT + G;
       if (mode == PJ_ST2) {
         p.q[SL_Q1][I] = s;          // global step: stage-2 state of the node
       } else if (mode == PJ_ST3) {
@@ -681,38 +725,48 @@ __global__ __launch_bounds__(TPB) void k_project(Geo g, Dev p, int lev) {
         p.q[SL_Q0][I] = s;
       } else if (mode == PJ_CASEB) {
         p.q[SL_QH][I] = s;
-        p.q[SL_QE][I] = ((-2.0 * p.q[SL_Q0][I]) - p.q[SL_Q1REF][I]) + (4.0 * s);
+        p.q[SL_QE][I] = ((-2.0 * o0[k]) - o1[k]) + (4.0 * s);
       } else if (mode == PJ_REF2) {
         p.q[SL_H1][I] = s;
-        p.q[SL_Q1REF][I] = (2.0 * s) - p.q[SL_Q0][I];
+        p.q[SL_Q1REF][I] = (2.0 * s) - o0[k];
       } else if (mode == PJ_RK2) {
+        // the node's stage-2 value: its Q1, and 2 Q1 - Q0 in its X2 for the
+        // coarser level's pass and the refined faces of coarser leaves
         p.q[SL_Q1][I] = s;
+        p.q[SL_X2][I] = (2.0 * s) - o0[k];
       } else if (mode == PJ_REF3) {
-        const double q0 = p.q[SL_Q0][I], qs = p.q[SL_Q1REF][I];
+        const double q0 = o0[k], qs = o1[k];
         p.q[SL_N14][I] = s;
         p.q[SL_N34][I] = ((-6.5 * q0) - (1.5 * qs)) + (9.0 * s);
         p.q[SL_QH][I] = ((-5.5 * q0) - (1.5 * qs)) + (8.0 * s);
       } else {
         p.q[SL_QH][I] = s;
-        p.q[SL_QE][I] = p.q[SL_Q0][I] + (2.0 * (p.q[SL_N34][I] - p.q[SL_N14][I]));
+        p.q[SL_QE][I] = o0[k] + (2.0 * (o1[k] - o2[k]));
       }
     }
+  }
+}
+
+template <int D>
+static void project_d(const Geo& g, const Dev& p, int lev, int mode, int nb, hipStream_t s) {
+  switch (mode) {
+    case PJ_Q0: k_project<D, PJ_Q0><<<nb, TPB, 0, s>>>(g, p, lev); break;
+    case PJ_CASEB: k_project<D, PJ_CASEB><<<nb, TPB, 0, s>>>(g, p, lev); break;
+    case PJ_REF2: k_project<D, PJ_REF2><<<nb, TPB, 0, s>>>(g, p, lev); break;
+    case PJ_RK2: k_project<D, PJ_RK2><<<nb, TPB, 0, s>>>(g, p, lev); break;
+    case PJ_REF3: k_project<D, PJ_REF3><<<nb, TPB, 0, s>>>(g, p, lev); break;
+    case PJ_RK3: k_project<D, PJ_RK3><<<nb, TPB, 0, s>>>(g, p, lev); break;
+    case PJ_ST2: k_project<D, PJ_ST2><<<nb, TPB, 0, s>>>(g, p, lev); break;
+    default: k_project<D, PJ_ST3><<<nb, TPB, 0, s>>>(g, p, lev); break;
   }
 }
 
 void launch_project(const Geo& g, const Dev& p, int lev, int mode, hipStream_t s) {
   const int64_t n = g.B * g.n[lev];
   const int nb = list_blocks(g, n);
-  switch (mode) {
-    case PJ_Q0: k_project<PJ_Q0><<<nb, TPB, 0, s>>>(g, p, lev); break;
-    case PJ_CASEB: k_project<PJ_CASEB><<<nb, TPB, 0, s>>>(g, p, lev); break;
-    case PJ_REF2: k_project<PJ_REF2><<<nb, TPB, 0, s>>>(g, p, lev); break;
-    case PJ_RK2: k_project<PJ_RK2><<<nb, TPB, 0, s>>>(g, p, lev); break;
-    case PJ_REF3: k_project<PJ_REF3><<<nb, TPB, 0, s>>>(g, p, lev); break;
-    case PJ_RK3: k_project<PJ_RK3><<<nb, TPB, 0, s>>>(g, p, lev); break;
-    case PJ_ST2: k_project<PJ_ST2><<<nb, TPB, 0, s>>>(g, p, lev); break;
-    default: k_project<PJ_ST3><<<nb, TPB, 0, s>>>(g, p, lev); break;
-  }
+  if (g.d == 1) project_d<1>(g, p, lev, mode, nb, s);
+  else if (g.d == 2) project_d<2>(g, p, lev, mode, nb, s);
+  else project_d<3>(g, p, lev, mode, nb, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -737,12 +791,19 @@ __global__ __launch_bounds__(TPB) void k_ghost(Geo g, Dev p, int lo, int hi, int
   constexpr int PER = 4, CH = TPB * PER, NS = 1 << D;
   __shared__ int s_cnt[MRD_MAXLEV + 1];
   __shared__ int s_lead[CH];
+  __shared__ int s_t[CH];  // the block's list entries, read again by the leaders
   __shared__ int sh[TPB / 64];
   __shared__ LevTab lt;
   levtab_fill(g, lt);  // flat_setup synchronises
   const int64_t ntot = flat_setup(p, LS_GHOST, lo, hi, s_cnt);
   for (int64_t base = (int64_t)blockIdx.x * CH; base < ntot; base += (int64_t)gridDim.x * CH) {
-    uint32_t lead = 0u;  // bit e: entry base + PER * threadIdx.x + e leads its sibling group
+    // the lane's entries (and, for the block's first, the entry before it)
+    int tv[PER], kv[PER], prev0 = 0;
+#pragma unroll
+    for (int e = 0; e < PER; e++) {
+      tv[e] = 0;
+      kv[e] = -1;
+    }
 #pragma unroll
     for (int e = 0; e < PER; e++) {
       const int64_t i = base + PER * (int64_t)threadIdx.x + e;
@@ -750,8 +811,20 @@ __global__ __launch_bounds__(TPB) void k_ghost(Geo g, Dev p, int lo, int hi, int
       int64_t kk = i;
       const int lev = flat_level(s_cnt, lo, kk);
       const int* lst = p.lst[LS_GHOST] + lt.off[lev];
-      const int t = lst[kk];
-      if (kk == 0 || (lst[kk - 1] >> D) != (t >> D)) lead |= 1u << e;
+      tv[e] = lst[kk];
+      kv[e] = (int)kk;
+      if (e == 0 && threadIdx.x == 0 && kk > 0) prev0 = lst[kk - 1];
+    }
+#pragma unroll
+    for (int e = 0; e < PER; e++) s_t[PER * threadIdx.x + e] = tv[e];
+    __syncthreads();
+    uint32_t lead = 0u;  // bit e: entry base + PER * threadIdx.x + e leads its sibling group
+#pragma unroll
+    for (int e = 0; e < PER; e++) {
+      if (kv[e] < 0) break;
+      const int q = PER * (int)threadIdx.x + e;
+      const int pt = q > 0 ? s_t[q - 1] : prev0;
+      if (kv[e] == 0 || (pt >> D) != (tv[e] >> D)) lead |= 1u << e;
     }
     int tot;
     int pos = block_exscan<int>(__popc(lead), sh, &tot);
@@ -762,16 +835,18 @@ __global__ __launch_bounds__(TPB) void k_ghost(Geo g, Dev p, int lo, int hi, int
     }
     __syncthreads();
     for (int q = threadIdx.x; q < tot; q += TPB) {
-      int64_t kk = base + s_lead[q];
+      const int ql = s_lead[q];
+      int64_t kk = base + ql;
       const int lev = flat_level(s_cnt, lo, kk);
       const int64_t nl = (int64_t)1 << (D * lev);
       const double* src = p.q[lev == cb_lev ? srcB : srcA];
-      const int* lst = p.lst[LS_GHOST] + lt.off[lev];
       const int len = s_cnt[lev - lo];
-      const int t = lst[kk];
+      const int t = s_t[ql];
+      // the group's listed siblings follow it in the list (from the block's
+      // entries; past the block's last entry, from the list itself)
       uint32_t cbits = 1u << (t & (NS - 1));
       for (int e = 1; e < NS && kk + e < len; e++) {
-        const int u = lst[kk + e];
+        const int u = ql + e < CH ? s_t[ql + e] : p.lst[LS_GHOST][lt.off[lev] + kk + e];
         if ((u >> D) != (t >> D)) break;
         cbits |= 1u << (u & (NS - 1));
       }
@@ -870,16 +945,16 @@ __device__ __forceinline__ void refined_flux(const Geo& g, const Dev& p, int lev
       int y[3] = {fy[0], fy[1], fy[2]};
       y[dir] = 2 * nbx + e;
       const int64_t Gf = ibf + (int64_t)menc<D>(y);
-      // the finer cell's status selects its stage-2 value under local time
-      // stepping; otherwise it is read only to verify that the cell exists
-      const uint8_t sf = (g.check || (g.lt && stage == 2)) ? p.st[Gf] : (uint8_t)ST_LEAF;
+      // the finer cell's status is read only to verify that the cell exists
+      // (its stage-2 value is in its X2 slot whether it is a leaf or not)
+      const uint8_t sf = g.check ? p.st[Gf] : (uint8_t)ST_LEAF;
       if (g.check && sf == ST_ABSENT) flag_bad(p, inst, 4);
 #pragma unroll
       for (int k = 0; k < M; k++) {
         const int64_t I = (int64_t)k * g.Ntot + Gf;
         if (!g.lt) fin[e][k] = cur[I];
         else if (stage == 1) fin[e][k] = p.q[SL_Q0][I];
-        else if (stage == 2) fin[e][k] = sf == ST_LEAF ? p.q[SL_X2][I] : (2.0 * p.q[SL_Q1][I]) - p.q[SL_Q0][I];
+        else if (stage == 2) fin[e][k] = p.q[SL_X2][I];
         else fin[e][k] = p.q[SL_QE][I];
       }
     }
@@ -990,7 +1065,12 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
       int x[3] = {0, 0, 0};
       if (!FAST) mdec<D>(key, x);
       const int64_t ib = lt.off[lev] + inst * nl;
-      // the instance's finest step, requested with the cell's other loads
+      // the instance's finest step, requested with the cell's other loads;
+      // first the tile flag that says whether the leaf keeps NERK values
+      // (its reply arrives while the stencil loads are in flight)
+      const bool tiled = !IFACE && !finest && g.lt && lt.wide[lev];
+      const uint8_t nsv = p.nsum[tiled ? lt.bsoff[lev] + (t >> BS_SHIFT) : (int64_t)0];  // no branch around the load
+      const uint8_t nflag = tiled ? nsv : (uint8_t)1;
       const double dti = p.dt[inst];
       // status of the 2d face neighbours (3: outside the domain); a cell
       // outside loads its own status instead, so that every load is issued
@@ -1078,27 +1158,30 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
           }
       }
       // the leaf's own slots; at stage 2 also the NERK partial values it adds
-      // to (read for every leaf below the finest level, so that the loads go
-      // out with the others before the tile flag says whether it writes them)
-      const bool rmw = stage == 2 && !finest && g.lt;
+      // to where it keeps them (elsewhere the same loads read its own q^n
+      // again, a cache hit: no branch, and the loads that do not wait for the
+      // tile flag go first)
       double q0v[M], qsv[M], n14v[M], n34v[M];
 #pragma unroll
       for (int k = 0; k < M; k++) {
         const int64_t I = (int64_t)k * NT + G;
         q0v[k] = p.q[SL_Q0][I];
         qsv[k] = stage == 2 ? p.q[SL_Q1][I] : (stage == 3 ? p.q[SL_QH][I] : 0.0);
-        n14v[k] = 0.0;
-        n34v[k] = 0.0;
-        if (rmw) {
-          if (g.rk == 2) {
-            n14v[k] = p.q[SL_QH][I];
-          } else {
-            n14v[k] = p.q[SL_N14][I];
-            n34v[k] = p.q[SL_N34][I];
-          }
-        }
       }
-      const uint8_t nflag = (!IFACE && !finest && g.lt && lt.wide[lev]) ? p.nsum[lt.bsoff[lev] + (t >> BS_SHIFT)] : 1;
+      if (PRE && stage == 2 && g.lt) {
+        const bool keep = !finest && nflag != 0;
+        const double* a14 = keep ? p.q[g.rk == 2 ? SL_QH : SL_N14] : p.q[SL_Q0];
+        const double* a34 = keep ? p.q[SL_N34] : p.q[SL_Q0];
+#pragma unroll
+        for (int k = 0; k < M; k++) {
+          const int64_t I = (int64_t)k * NT + G;
+          n14v[k] = a14[I];
+          n34v[k] = g.rk == 2 ? 0.0 : a34[I];
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < M; k++) n14v[k] = n34v[k] = 0.0;
+      }
       if (!PRE && !IFACE && refined && !finest) continue;  // the interface launch owns it
       const bool active = IFACE || finest || !refined;
       const double h = g.lt ? ldexp(dti, g.L - lev) : dti;
@@ -1210,7 +1293,7 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
             p.q[SL_QE][I] = qe;
             if (!IFACE && lev >= lq0) p.q[SL_Q0][I] = qe;
             p.q[SL_X2][I] = q1 + (h * r);
-            if (nerk) p.q[SL_QH][I] = n14v[k] + ((0.125 * h) * r);
+            if (nerk) p.q[SL_QH][I] = (PRE ? n14v[k] : p.q[SL_QH][I]) + ((0.125 * h) * r);
             if (!isfinite(qe)) atomicOr(&p.cnt[inst * CNT_PER_INST + CNT_NONFINITE], 1ull);
           }
           continue;
@@ -1227,8 +1310,12 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
           p.q[SL_QH][I] = ((0.75 * q0) + (0.25 * q1)) + ((0.25 * h) * r);
           p.q[SL_X2][I] = q1 + (h * r);
           if (nerk) {
-            p.q[SL_N14][I] = n14v[k] + (((1.0 / 32.0) * h) * r);
-            p.q[SL_N34][I] = n34v[k] + (((9.0 / 32.0) * h) * r);
+            // with few fields the partials were loaded with the stencil;
+            // with many they are read here (registers)
+            const double a14 = PRE ? n14v[k] : p.q[SL_N14][I];
+            const double a34 = PRE ? n34v[k] : p.q[SL_N34][I];
+            p.q[SL_N14][I] = a14 + (((1.0 / 32.0) * h) * r);
+            p.q[SL_N34][I] = a34 + (((9.0 / 32.0) * h) * r);
           }
         } else {
           const double qh = qsv[k];
@@ -1298,48 +1385,89 @@ void launch_stage(const Geo& g, const Dev& p, int lo, int hi, int stage, int par
 template <int D>
 __global__ __launch_bounds__(TPB) void k_finalize(Geo g, Dev p, int lo, int hi, int list, int reflux) {
   const double sc = D == 1 ? 1.0 : (D == 2 ? 0.5 : 0.25);
+  constexpr int MF = D + 2;
   __shared__ int s_cnt[MRD_MAXLEV + 1];
+  __shared__ LevTab lt;
+  levtab_fill(g, lt);  // flat_setup synchronises
   const int64_t ntot = flat_setup(p, list, lo, hi, s_cnt);
-  GSL(i, ntot) {
-    {
-      int64_t kk = i;
-      const int lev = flat_level(s_cnt, lo, kk);
-      const int64_t nl = g.n[lev];
-      const int n = 1 << lev;
-      const int64_t t = p.lst[list][g.off[lev] + kk];
-      const int64_t G = g.off[lev] + t;
-      double q[5];
-      for (int k = 0; k < g.m; k++) q[k] = p.q[SL_QE][(int64_t)k * g.Ntot + G];
-      if (reflux && g.reflux && lev < g.L) {
-        const int64_t inst = t >> (D * lev);
-        const int64_t ib = g.off[lev] + inst * nl;
-        int x[3];
-        mdec<D>((uint64_t)(t & (nl - 1)), x);
-        for (int dir = 0; dir < D; dir++)
-          for (int side = 0; side < 2; side++) {
-            const int nb = map_nb(x[dir] + (side ? 1 : -1), n, g.periodic[dir]);
-            if (nb < 0) continue;
-            int y[3] = {x[0], x[1], x[2]};
-            y[dir] = nb;
-            if (p.st[ib + (int64_t)menc<D>(y)] != ST_INTERNAL) continue;
-            const int f = 2 * dir + side;
-            for (int k = 0; k < g.m; k++) {
-              double af = 0.0;
-              for (int b = 0; b < (1 << (D - 1)); b++) {
-                double* r = regf_at(g, p, lev, f, b, k, t);
-                af = (b == 0) ? *r : (af + *r);
-                *r = 0.0;
-              }
-              af = af * sc;
-              double* rc = regc_at(g, p, lev, f, k, t);
-              const double Dd = (*rc - af) * g.invdx[lev][dir];
-              *rc = 0.0;
-              q[k] = side ? q[k] + Dd : q[k] - Dd;
-            }
-          }
-      }
-      for (int k = 0; k < g.m; k++) p.q[SL_Q0][(int64_t)k * g.Ntot + G] = q[k];
+  const int64_t step = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool regs_on = reflux && g.reflux;
+  // the next list entry is fetched while a leaf is processed (a lane's list
+  // positions only grow, so its level is advanced, not searched again)
+  int lev_c = lo;
+  int64_t base_c = 0;
+  auto locate = [&](int64_t idx) {
+    while (idx - base_c >= s_cnt[lev_c - lo]) {
+      base_c += s_cnt[lev_c - lo];
+      lev_c++;
     }
+    return idx - base_c;
+  };
+  int lev_n = lo, t_n = 0;
+  if (i < ntot) {
+    const int64_t kk = locate(i);
+    lev_n = lev_c;
+    t_n = p.lst[list][lt.off[lev_n] + kk];
+  }
+  vm_wait_all();  // the first entry: no wait at the loop's top (see k_project)
+  for (; i < ntot; i += step) {
+    const int lev = lev_n;
+    const int64_t t = t_n;
+    if (i + step < ntot) {
+      const int64_t kk = locate(i + step);
+      lev_n = lev_c;
+      t_n = p.lst[list][lt.off[lev_n] + kk];
+    }
+    const int64_t G = lt.off[lev] + t;
+    double q[MF];
+#pragma unroll
+    for (int k = 0; k < MF; k++)
+      if (k < g.m) q[k] = p.q[SL_QE][(int64_t)k * g.Ntot + G];
+    if (regs_on && lev < g.L) {
+      // the statuses of the 2d face neighbours, requested with the end
+      // values (a neighbour outside the domain reads the leaf's own status)
+      const int64_t nl = (int64_t)1 << (D * lev), Nl = g.B * nl;
+      const int n = 1 << lev;
+      int x[3] = {0, 0, 0};
+      mdec<D>((uint64_t)(t & (nl - 1)), x);
+      const int64_t ib = lt.off[lev] + (t >> (D * lev)) * nl;
+      uint8_t sn[D][2];
+#pragma unroll
+      for (int dir = 0; dir < D; dir++)
+#pragma unroll
+        for (int side = 0; side < 2; side++) {
+          const int nb = map_nb(x[dir] + (side ? 1 : -1), n, g.periodic[dir]);
+          int y[3] = {x[0], x[1], x[2]};
+          if (nb >= 0) y[dir] = nb;
+          sn[dir][side] = p.st[ib + (int64_t)menc<D>(y)];
+        }
+#pragma unroll
+      for (int dir = 0; dir < D; dir++)
+#pragma unroll
+        for (int side = 0; side < 2; side++) {
+          if (sn[dir][side] != ST_INTERNAL) continue;  // the leaf itself, or no refined face
+          const int f = 2 * dir + side;
+#pragma unroll
+          for (int k = 0; k < MF; k++) {
+            if (k >= g.m) break;
+            double af = 0.0;
+            for (int b = 0; b < (1 << (D - 1)); b++) {
+              double* r = p.regf + lt.rf[lev] + (int64_t)((f * g.nsub + b) * g.m + k) * Nl + t;
+              af = (b == 0) ? *r : (af + *r);
+              *r = 0.0;
+            }
+            af = af * sc;
+            double* rc = p.regc + lt.rc[lev] + (int64_t)(f * g.m + k) * Nl + t;
+            const double Dd = (*rc - af) * lt.ix[lev][dir];
+            *rc = 0.0;
+            q[k] = side ? q[k] + Dd : q[k] - Dd;
+          }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < MF; k++)
+      if (k < g.m) p.q[SL_Q0][(int64_t)k * g.Ntot + G] = q[k];
   }
 }
 
@@ -2625,12 +2753,22 @@ void launch_validate(const Geo& g, const Dev& p, int lev, int* err, hipStream_t 
 
 template <int D>
 __global__ void k_wavespeed(Geo g, Dev p, int lev, unsigned long long* out) {
+  // the maximum is taken over each wave first (it is exact and
+  // order-independent), so that one atomic per wave and instance reaches
+  // memory instead of one per leaf
   const int64_t nl = g.n[lev], N = g.B * nl;
-  GSL(t, N) {
-    const int64_t G = g.off[lev] + t;
-    if (p.st[G] != ST_LEAF) continue;
-    const int64_t inst = t >> (D * lev);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t start = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // every lane of a wave runs the same number of rounds (the wave votes)
+  const int64_t rounds = (N + stride - 1) / stride;
+  for (int64_t r = 0; r < rounds; r++) {
+    const int64_t t = start + r * stride;
+    const bool in = t < N;
+    const int64_t G = g.off[lev] + (in ? t : 0);
+    const bool leaf = in && p.st[G] == ST_LEAF;
+    const int64_t inst = in ? t >> (D * lev) : -1;
     double q[5], v = 0.0;
+    if (leaf) {
     for (int k = 0; k < g.m; k++) q[k] = p.q[SL_Q0][(int64_t)k * g.Ntot + G];
     if (g.pde == PDE_BURGERS) {
       // f_i(u) = u^2/2 in every direction: sum_i |f_i'(u)|
@@ -2647,7 +2785,21 @@ __global__ void k_wavespeed(Geo g, Dev p, int lev, unsigned long long* out) {
       else
         for (int j = 0; j < D; j++) v = v + fabs(g.adv[j]);
     }
-    atomicMax(&out[inst], (unsigned long long)__double_as_longlong(v));
+    }
+    // non-negative doubles order like their bit patterns
+    unsigned long long bits = leaf ? (unsigned long long)__double_as_longlong(v) : 0ull;
+    const int64_t i0 = __shfl(inst, 0);
+    const bool one_inst = __all(!leaf || inst == i0);
+    const bool any_leaf = __any(leaf);
+    if (one_inst) {
+      for (int o = 32; o >= 1; o >>= 1) {
+        const unsigned long long u = __shfl_xor(bits, o);
+        bits = u > bits ? u : bits;
+      }
+      if ((threadIdx.x & 63) == 0 && any_leaf) atomicMax(&out[i0], bits);
+    } else if (leaf) {
+      atomicMax(&out[inst], bits);
+    }
   }
 }
 
