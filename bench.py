@@ -382,15 +382,87 @@ def euler3d_single(args):
     alg = int(items[0]) * 16 * m + int(items[1]) * 24 * m + int(items[2]) * 24 * m
     ach = alg / (ms * 1e-3) / 1e9
     leaves = int(sum(s.stats()["leaves"]))
+    items_run = [int(x) for x in s.stage_items()]
     s.close()
     print(f"[bench] 3D Euler L=7: {upd / el:.3e} leaf-updates/s", file=sys.stderr, flush=True)
+    # the FP64 roofline of the same launches: FP64 operations per leaf-stage
+    # update from the committed instruction-counter run of this mode, when it
+    # was taken on the current kernel source
+    valu = None
+    fp = euler_fp64_record()
+    if fp:
+        flop = sum(int(items[j]) * fp["flop_per_leaf_stage"][j] for j in range(3))
+        tf = flop / (ms * 1e-3) / 1e12
+        valu = {"bound": "alu", "achieved": round(tf, 3), "peak": 78.6, "unit": "TFLOP/s",
+                "frac": round(tf / 78.6, 5), "flop_per_leaf_stage": fp["flop_per_leaf_stage"],
+                "flop_per_byte": round(flop / alg, 2)}
     return {"workload": "euler3d_L7_128^3 spherical Riemann problem, eps=1e-3, one solve, macro steps 2-3 from t=0",
             "leaf_updates_per_s": round(upd / el, 1), "ms_per_macro_step": round(el / 2 * 1e3, 2),
             "leaves": leaves,
             "roofline": {"bound": "hbm", "achieved": round(ach, 2), "peak": 8000.0, "unit": "GB/s",
                          "frac": round(ach / 8000.0, 5), "kernel": "k_stage<3, 3, false, 1|2|3>",
                          "launches": launches, "avg_launch_us": round(ms * 1e3 / max(launches, 1), 3),
-                         "alg_bytes_per_leaf_stage": [16 * m, 24 * m, 24 * m]}}
+                         "alg_bytes_per_leaf_stage": [16 * m, 24 * m, 24 * m]},
+            "valu_roofline": valu, "bulk_items_run": items_run}
+
+
+def kernels_digest():
+    here = os.path.dirname(os.path.abspath(__file__))
+    with open(os.path.join(here, "paper_1905_08717_amd", "csrc", "kernels.hip"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def euler_fp64_record():
+    """FP64 operations per leaf-stage update of the 3D Euler bulk stage
+    kernel (profiles/euler3d_bulk_fp64.json), if taken on the current kernel
+    source; otherwise None."""
+    here = os.path.dirname(os.path.abspath(__file__))
+    try:
+        with open(os.path.join(here, "profiles", "euler3d_bulk_fp64.json")) as f:
+            rec = json.load(f)
+        if rec.get("kernels_hip_sha256") != kernels_digest():
+            return None
+        return rec
+    except (OSError, ValueError):
+        return None
+
+
+def fp64_record(args):
+    """FP64 operations per leaf-stage update of the 3D Euler bulk stage kernel
+    from a rocprofv3 run of `--mode euler3d` with the FP64 instruction counters
+    (folder pmc_eul under --pmc-dir, its log pmc_eul.log): (ADD + MUL + TRANS
+    + 2 FMA) wave instructions x 64 lanes over all bulk launches of the run,
+    divided by the run's leaf-stage updates (an upper bound: lanes outside a
+    wave's active mask are counted).  Written to
+    profiles/euler3d_bulk_fp64.json."""
+    import csv
+    d = args.pmc_dir
+    if not d:
+        raise SystemExit("--mode fp64 needs --pmc-dir")
+    tot = [dict(), dict(), dict()]
+    with open(os.path.join(d, "pmc_eul", "eul_counter_collection.csv")) as f:
+        for r in csv.DictReader(f):
+            k = r["Kernel_Name"]
+            if not k.startswith("void k_stage<3, 3, false, "):
+                continue
+            j = int(k.split(",")[3].split(">")[0]) - 1
+            tot[j][r["Counter_Name"]] = tot[j].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    with open(os.path.join(d, "pmc_eul.log")) as fh:
+        line = [ln for ln in fh if ln.startswith("{")][-1]
+    items = json.loads(line)["bulk_items_run"]
+    flop = []
+    for j in range(3):
+        c = tot[j]
+        ops = (c["SQ_INSTS_VALU_ADD_F64"] + c["SQ_INSTS_VALU_MUL_F64"] + c["SQ_INSTS_VALU_TRANS_F64"]
+               + 2.0 * c["SQ_INSTS_VALU_FMA_F64"]) * 64.0
+        flop.append(round(ops / items[j], 1))
+    rec = {"kernel": "k_stage<3, 3, false, 1|2|3>", "workload": "bench.py --mode euler3d",
+           "counters": [{k: int(v) for k, v in c.items()} for c in tot], "bulk_items_run": items,
+           "flop_per_leaf_stage": flop, "kernels_hip_sha256": kernels_digest()}
+    here = os.path.dirname(os.path.abspath(__file__))
+    with open(os.path.join(here, "profiles", "euler3d_bulk_fp64.json"), "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec), flush=True)
 
 
 def batched_leg(args):
@@ -445,7 +517,7 @@ def main():
                     help="skip the 3D Euler, batched and served legs of the default line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", choices=["throughput", "batched", "served", "copycal", "traffic", "paper",
-                                       "flames", "cpu-oracle", "euler3d"],
+                                       "flames", "cpu-oracle", "euler3d", "fp64"],
                     default="throughput")
     ap.add_argument("--levels", default="8,9,10", help="paper mode: finest levels")
     ap.add_argument("--flame-levels", default="11,12", help="flames mode: finest levels of the 1D flame")
@@ -468,6 +540,9 @@ def main():
 
     if args.mode == "cpu-oracle":
         cpu_oracle_leg(args.cpu_seconds)
+        return
+    if args.mode == "fp64":
+        fp64_record(args)
         return
     if args.mode == "euler3d":
         print(json.dumps(euler3d_single(args)), flush=True)
