@@ -1534,12 +1534,11 @@ __device__ __forceinline__ bool inst_of_window_skip(const Geo& g, int64_t t, int
 // bytes of cells [t0, t0+16) of a level table (zero past the level end);
 // level tables start at multiples of 256 cells, so the load is aligned
 __device__ __forceinline__ uint4 ld16(const uint8_t* base, int64_t t0, int64_t N) {
-  if (t0 + 16 <= N) return *reinterpret_cast<const uint4*>(base + t0);
-  uint32_t w[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-  for (int j = 0; j < 16; j++)
-    if (t0 + j < N) w[j >> 2] |= (uint32_t)base[t0 + j] << (8 * (j & 3));
-  return make_uint4(w[0], w[1], w[2], w[3]);
+  // 16-cell groups are used on levels of at least 4096 cells per instance
+  // (wide levels), so N and t0 are multiples of 16: a group is whole or
+  // past the end.  No partial-group path: its branch would make the
+  // compiler wait for the group's load where the two paths join.
+  return t0 < N ? *reinterpret_cast<const uint4*>(base + t0) : make_uint4(0u, 0u, 0u, 0u);
 }
 // G = 16: ld16; G = 1: the one byte of cell t0 (zero past the level end)
 template <int G>
@@ -1560,16 +1559,11 @@ template <int D, int G = 16>
 __device__ __forceinline__ uint64_t ld_parents(const uint8_t* stp, int64_t t0, int64_t N) {
   const int64_t p0 = t0 >> D;
   if (G == 1) return t0 < N ? (uint64_t)stp[p0] : 0ull;
-  if (t0 + 16 <= N) {
-    if (D == 1) return *reinterpret_cast<const uint64_t*>(stp + p0);
-    if (D == 2) return *reinterpret_cast<const uint32_t*>(stp + p0);
-    return *reinterpret_cast<const uint16_t*>(stp + p0);
-  }
-  uint64_t r = 0ull;
-  const int64_t pl = (N - 1) >> D;
-  for (int k = 0; k < (16 >> D); k++)
-    if (p0 + k <= pl) r |= (uint64_t)stp[p0 + k] << (8 * k);
-  return r;
+  // whole groups only (see ld16)
+  if (t0 >= N) return 0ull;
+  if (D == 1) return *reinterpret_cast<const uint64_t*>(stp + p0);
+  if (D == 2) return *reinterpret_cast<const uint32_t*>(stp + p0);
+  return *reinterpret_cast<const uint16_t*>(stp + p0);
 }
 
 // block summary of a wide level; unknown (all bits) elsewhere
@@ -1941,23 +1935,44 @@ __global__ __launch_bounds__(TPB) void k_apply(Geo g, Dev p, int lev, int la) {
   }
   if (threadIdx.x == 0) bor = 0u;
   __syncthreads();
+  // block summaries of the level and, where it keeps them, of the parent
+  // level (else the level's own are read again and ignored, and every
+  // block is visited); on the frozen level la no parent can turn a cell
+  // into existence
+  const bool pw = lev > la && wide_level(g, lev - 1);
+  const uint8_t* bs_lev = p.bsum + (G == 16 ? g.bs_off[lev] : 0);
+  const uint8_t* bs_up = pw ? p.bsum + g.bs_off[lev - 1] : bs_lev;
+  const int bs_up_shift = pw ? D : 0;
+  const unsigned bs_up_mask = pw ? (unsigned)BS_INT : 0u;
+  const unsigned bs_visit = (lev > la && !pw) ? 1u : 0u;  // parent level unknown: always visit
   for (int64_t tb = (int64_t)blockIdx.x * (TPB * G); tb < N; tb += (int64_t)gridDim.x * (TPB * G)) {
     // nothing exists in the block and no parent is internal: it stays absent
     const int64_t sb = tb >> BS_SHIFT;
-    if (!(bsum_of(g, p, lev, sb) & BS_EXIST) && (lev == la || !(bsum_of(g, p, lev - 1, sb >> D) & BS_INT)))
-      continue;
+    bool skip;
+    if (G == 16) {
+      // a wide level: both summaries in one round trip (where the parent
+      // level keeps none, the own one is read again and "unknown" taken)
+      const unsigned b_own = bs_lev[sb];
+      const unsigned b_par = bs_up[sb >> bs_up_shift];
+      skip = ((b_own & BS_EXIST) | (b_par & bs_up_mask) | bs_visit) == 0u;
+    } else {
+      skip = !(bsum_of(g, p, lev, sb) & BS_EXIST) && (lev == la || !(bsum_of(g, p, lev - 1, sb >> D) & BS_INT));
+    }
+    if (skip) continue;
     const int64_t t0 = tb + (int64_t)threadIdx.x * G;
     uint32_t mask = 0u;
     if (t0 < N) {
       const uint4 so = ldg<G>(stl, t0, N);
       const uint64_t par = lev > la ? ld_parents<D, G>(stp, t0, N) : 0ull;
+      // the W marks, requested with the statuses (a group that turns out to
+      // stay absent has read 16 bytes for nothing; one round trip saved)
+      const uint4 wv = lev <= g.L - 1 ? ldg<G>(p.rf + g.off[lev], t0, N) : make_uint4(0u, 0u, 0u, 0u);
       // a parent that is internal after the update has all its children
       bool par_int = false;
 #pragma unroll
       for (int k = 0; k < (G == 1 ? 1 : (16 >> D)); k++) par_int = par_int || ((par >> (8 * k)) & 0xff) == ST_INTERNAL;
       // nothing exists and nothing will: the group stays absent
       if (any16(so, 0xffffffffu) || par_int) {
-        const uint4 wv = lev <= g.L - 1 ? ldg<G>(p.rf + g.off[lev], t0, N) : make_uint4(0u, 0u, 0u, 0u);
         uint64_t nlo = 0ull, nhi = 0ull;  // new statuses of cells 0-7, 8-15
         if (G == 16 && t0 + 16 <= N) {
           // four cells per 32-bit word (statuses 0, 1, 2 and the W bit add
