@@ -630,9 +630,12 @@ def main():
                 "alg_bytes_per_leaf_stage": [16 * m, 24 * m, 24 * m]}
 
     # single-solve reference (one instance), same work per macro step
-    single = None
+    single, stored1 = None, None
     if not args.no_single:
         s1 = mrlt.Solver(cfg, n_inst=1)
+        stored1 = autotune.lookup(autotune.nagumo_key(cfg["L"], 1))
+        if stored1 and not args.no_tune:
+            s1.set_launch(**stored1)
         s1.load_finest(torch.from_numpy(q0[:1]).to("cuda"))
         s1.lt_step(dt)
         a = total_updates(s1)
@@ -657,6 +660,7 @@ def main():
         "launch_source": source,
         "autotune": tuned,
         "single_solve_leaf_updates_per_s": single,
+        "single_solve_launch": (stored1 if (single is not None and stored1 and not args.no_tune) else None),
         "solves_macro_steps_per_s": round(B * args.steps / el, 2),
     }
     del s
