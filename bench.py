@@ -656,6 +656,11 @@ def main():
                    "dim": 2, "L": 9, "l0": 2, "eps": 1e-3, "batch": B, "dt_L": dt,
                    "leaves_per_level_total": [int(x) for x in leaves[:10]]},
         "roofline": roofline,
+        # the whole macro step against the same floor: 64m algorithmic bytes
+        # per leaf-update (16m + 24m + 24m over the three stages)
+        "whole_step": {"bound": "hbm", "achieved": round(upd * 64 * s.m / el / 1e9, 2), "peak": 8000.0,
+                       "unit": "GB/s", "frac": round(upd * 64 * s.m / el / 1e9 / 8000.0, 5),
+                       "alg_bytes_per_leaf_update": 64 * s.m},
         "launch": s.get_launch(),
         "launch_source": source,
         "autotune": tuned,
