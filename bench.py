@@ -351,9 +351,13 @@ def euler3d_single(args):
     import torch
     from paper_1905_08717_amd import mrlt
     from paper_1905_08717_amd import workloads as W
+    from paper_1905_08717_amd import autotune
     cfg = W.euler_3d(L=7)
     q0 = torch.from_numpy(W.euler_sphere(7)[None]).to("cuda")
     s = mrlt.Solver(cfg)
+    stored = None if getattr(args, "no_tune", False) else autotune.lookup(autotune.euler3d_key(7))
+    if stored:
+        s.set_launch(**stored)
 
     def run(k, t):
         for _ in range(k):
@@ -403,7 +407,8 @@ def euler3d_single(args):
                          "frac": round(ach / 8000.0, 5), "kernel": "k_stage<3, 3, false, 1|2|3>",
                          "launches": launches, "avg_launch_us": round(ms * 1e3 / max(launches, 1), 3),
                          "alg_bytes_per_leaf_stage": [16 * m, 24 * m, 24 * m]},
-            "valu_roofline": valu, "bulk_items_run": items_run}
+            "valu_roofline": valu, "bulk_items_run": items_run,
+            "launch": stored, "launch_source": "paper_1905_08717_amd/tuned_launch.json" if stored else "library default"}
 
 
 def kernels_digest():

@@ -117,6 +117,10 @@ def nagumo_key(L: int, batch: int) -> str:
     return f"nagumo2d_L{L}_b{batch}"
 
 
+def euler3d_key(L: int) -> str:
+    return f"euler3d_L{L}_b1"
+
+
 def main():
     import argparse
     import sys
@@ -127,22 +131,38 @@ def main():
     from paper_1905_08717_amd import mrlt
     from paper_1905_08717_amd import workloads as W
 
-    ap = argparse.ArgumentParser(description="tune the launch knobs for a batch of 2D Nagumo fronts")
+    ap = argparse.ArgumentParser(description="tune the launch knobs for a batch of 2D Nagumo fronts, "
+                                             "or for the 3D Euler spherical Riemann problem")
+    ap.add_argument("--workload", choices=["nagumo2d", "euler3d"], default="nagumo2d")
     ap.add_argument("--batch", type=int, default=512)
-    ap.add_argument("--L", type=int, default=9)
+    ap.add_argument("--L", type=int, default=0, help="finest level (default 9 for nagumo2d, 7 for euler3d)")
     ap.add_argument("--out", default="")
     ap.add_argument("--passes", type=int, default=2)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--record", action="store_true", help="store the result in tuned_launch.json")
     ap.add_argument("--record-path", default=RECORD_PATH)
     args = ap.parse_args()
-    cfg = W.nagumo_2d(L=args.L)
-    q0 = torch.from_numpy(np.stack([W.nagumo_front(args.L, W.SEED + i) for i in range(args.batch)])).to("cuda")
-    s = mrlt.Solver(cfg, n_inst=args.batch)
-    r = tune(s, q0, W.nagumo_dt(cfg), steps=args.steps, passes=args.passes,
+    if args.workload == "euler3d":
+        # one solve; the step of the first macro step (CFL from the initial
+        # wave speeds) is held for every trial
+        L = args.L or 7
+        cfg = W.euler_3d(L=L)
+        q0 = torch.from_numpy(W.euler_sphere(L)[None]).to("cuda")
+        s = mrlt.Solver(cfg)
+        s.load_finest(q0)
+        dt = W.euler_dt(cfg, s.max_wavespeed()[0], 0.0)
+        key = euler3d_key(L)
+    else:
+        L = args.L or 9
+        cfg = W.nagumo_2d(L=L)
+        q0 = torch.from_numpy(np.stack([W.nagumo_front(L, W.SEED + i) for i in range(args.batch)])).to("cuda")
+        s = mrlt.Solver(cfg, n_inst=args.batch)
+        dt = W.nagumo_dt(cfg)
+        key = nagumo_key(L, args.batch)
+    r = tune(s, q0, dt, steps=args.steps, passes=args.passes,
              log=lambda m: print(m, file=sys.stderr, flush=True))
     if args.record:
-        record(nagumo_key(args.L, args.batch), r,
+        record(key, r,
                f"coordinate descent, {args.passes} passes, 1 warm-up and {args.steps} timed macro steps per trial",
                path=args.record_path)
     text = json.dumps(r, indent=1)
