@@ -1018,6 +1018,10 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
   // while a leaf is processed; a leaf found to be an interface leaf is
   // computed but not stored.  Wide stencils of many fields load per axis.
   constexpr bool PRE = !IFACE && D * M <= 6;
+  // many fields: the refined faces of the interface leaves were evaluated
+  // by k_rface, one lane per face (inline, their registers would add to the
+  // leaf's and leave one wave per SIMD)
+  constexpr bool RSPLIT = IFACE && M >= 4;
   __shared__ int s_cnt[MRD_MAXLEV + 1];
   __shared__ LevTab lt;
   levtab_fill(g, lt);  // flat_setup synchronises
@@ -1219,8 +1223,15 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
 #pragma unroll
         for (int side = 0; side < 2; side++) {
           double* F = side ? Fp : Fm;
-          if (IFACE && sts[dir][side] == ST_INTERNAL)
-            refined_flux<D, PDE>(g, p, lev, stage, inst, x, dir, side, nbs[dir][side], F);
+          if (IFACE && sts[dir][side] == ST_INTERNAL) {
+            if (RSPLIT) {
+#pragma unroll
+              for (int k = 0; k < M; k++)
+                F[k] = p.rflux[lt.rc[lev] + (int64_t)((2 * dir + side) * M + k) * (g.B * nl) + t];
+            } else {
+              refined_flux<D, PDE>(g, p, lev, stage, inst, x, dir, side, nbs[dir][side], F);
+            }
+          }
           else
             face_flux_ix<D, PDE>(g, lt.ix[lev][dir], dir, vel, c5 + side, F);
         }
@@ -1329,6 +1340,42 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
   }
 }
 
+// Refined faces of the interface leaves of levels lo..hi (PDEs of four or
+// more fields): one work item per (listed leaf, face); where the face
+// neighbour is internal, the face flux (the mean of the 2^{d-1} subface
+// fluxes, Sec. 2) is stored for the stage kernel, which reads it in place of
+// evaluating it.  Same function, same arguments: the values are identical.
+template <int D, int PDE, int stage>
+__global__ __launch_bounds__(TPB) void k_rface(Geo g, Dev p, int lo, int hi) {
+  constexpr int M = NC<D, PDE>::M;
+  constexpr int NF = 2 * D;
+  __shared__ int s_cnt[MRD_MAXLEV + 1];
+  __shared__ LevTab lt;
+  levtab_fill(g, lt);  // flat_setup synchronises
+  const int64_t nitem = flat_setup(p, LS_IFACE, lo, hi, s_cnt) * NF;
+  GSL(it, nitem) {
+    int64_t kk = it / NF;
+    const int f = (int)(it - kk * NF);
+    const int lev = flat_level(s_cnt, lo, kk);
+    const int64_t t = p.lst[LS_IFACE][lt.off[lev] + kk];
+    const int64_t nl = (int64_t)1 << (D * lev);
+    const int n = 1 << lev;
+    const int64_t inst = t >> (D * lev);
+    const uint64_t key = (uint64_t)(t & (nl - 1));
+    int x[3] = {0, 0, 0};
+    mdec<D>(key, x);
+    const int dir = f >> 1, side = f & 1;
+    uint64_t ky;
+    if (!nbhd_key<D>(g, x, key, n, dir, side ? 1 : -1, &ky)) continue;
+    if (p.st[lt.off[lev] + inst * nl + (int64_t)ky] != ST_INTERNAL) continue;
+    const int nb = map_nb(x[dir] + (side ? 1 : -1), n, g.periodic[dir]);
+    double F[M];
+    refined_flux<D, PDE>(g, p, lev, stage, inst, x, dir, side, nb, F);
+#pragma unroll
+    for (int k = 0; k < M; k++) p.rflux[lt.rc[lev] + (int64_t)(f * M + k) * (g.B * nl) + t] = F[k];
+  }
+}
+
 // the stage is a template argument: the stage arrays a leaf reads and
 // writes are known at compile time (its own value is loaded once)
 template <int D, int PDE, bool IFACE>
@@ -1349,6 +1396,13 @@ static void stage_dp(const Geo& g, const Dev& p, int lo, int hi, int stage, int 
   // interface leaves lie along refinement boundaries: a small fraction
   int nb = blocks_for(g.B * g.n[hif]);
   if (nb > g.iface_grid) nb = g.iface_grid;
+  if constexpr (NC<D, PDE>::M >= 4) {
+    int nbf = blocks_for(g.B * g.n[hif] * 2 * D);
+    if (nbf > g.iface_grid) nbf = g.iface_grid;
+    if (stage == 1) k_rface<D, PDE, 1><<<nbf, TPB, 0, s>>>(g, p, lo, hif);
+    else if (stage == 2) k_rface<D, PDE, 2><<<nbf, TPB, 0, s>>>(g, p, lo, hif);
+    else k_rface<D, PDE, 3><<<nbf, TPB, 0, s>>>(g, p, lo, hif);
+  }
   stage_launch_st<D, PDE, true>(stage, nb, g, p, lo, hif, MRD_MAXLEV + 1, s);
 }
 

@@ -96,6 +96,8 @@ struct Dev {
   double* q[SL_COUNT];
   double* regc;    // [level block][2d][m][B n_l]
   double* regf;    // [level block][2d][nsub][m][B n_l]
+  double* rflux;   // [level block][2d][m][B n_l] refined-face fluxes of the interface leaves in the
+                   // current stage (PDEs of four or more fields only; else null)
   const double* dt;   // [B] dt of the finest level
   const double* eps;  // [B]
   unsigned long long* cnt;  // [B][CNT_PER_INST]

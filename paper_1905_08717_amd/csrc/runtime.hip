@@ -534,6 +534,8 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
   for (int sl = 0; sl < SL_COUNT; sl++) ALLOC(c->p.q[sl], double, (int64_t)g.m * g.Ntot);
   ALLOC(c->p.regc, double, g.rc_off[L]);
   ALLOC(c->p.regf, double, g.rf_off[L]);
+  c->p.rflux = nullptr;
+  if (g.m >= 4) ALLOC(c->p.rflux, double, g.rc_off[L]);
   ALLOC(c->dt_d, double, n_inst);
   ALLOC(c->eps_d, double, n_inst);
   ALLOC(c->p.cnt, unsigned long long, (int64_t)n_inst * CNT_PER_INST);
