@@ -791,11 +791,15 @@ __global__ __launch_bounds__(TPB) void k_ghost(Geo g, Dev p, int lo, int hi, int
   constexpr int PER = 4, CH = TPB * PER, NS = 1 << D;
   __shared__ int s_cnt[MRD_MAXLEV + 1];
   __shared__ int s_lead[CH];
-  __shared__ int s_t[CH];  // the block's list entries, read again by the leaders
+  __shared__ int s_t[CH + NS - 1];  // the block's list entries and the next NS - 1, read again by the leaders
   __shared__ int sh[TPB / 64];
   __shared__ LevTab lt;
   levtab_fill(g, lt);  // flat_setup synchronises
   const int64_t ntot = flat_setup(p, LS_GHOST, lo, hi, s_cnt);
+  // the two source slots, selected per lane by level below (the slot array
+  // indexed by a per-lane value would be a vector load of its own)
+  const double* qA = p.q[srcA];
+  const double* qB = p.q[srcB];
   for (int64_t base = (int64_t)blockIdx.x * CH; base < ntot; base += (int64_t)gridDim.x * CH) {
     // the lane's entries (and, for the block's first, the entry before it)
     int tv[PER], kv[PER], prev0 = 0;
@@ -817,6 +821,16 @@ __global__ __launch_bounds__(TPB) void k_ghost(Geo g, Dev p, int lo, int hi, int
     }
 #pragma unroll
     for (int e = 0; e < PER; e++) s_t[PER * threadIdx.x + e] = tv[e];
+    // the entries just past the block, for the groups that straddle its end
+    if (threadIdx.x < NS - 1) {
+      int64_t kk = base + CH + threadIdx.x;
+      int u = 0;
+      if (kk < ntot) {
+        const int lev = flat_level(s_cnt, lo, kk);
+        u = p.lst[LS_GHOST][lt.off[lev] + kk];
+      }
+      s_t[CH + threadIdx.x] = u;
+    }
     __syncthreads();
     uint32_t lead = 0u;  // bit e: entry base + PER * threadIdx.x + e leads its sibling group
 #pragma unroll
@@ -839,14 +853,14 @@ __global__ __launch_bounds__(TPB) void k_ghost(Geo g, Dev p, int lo, int hi, int
       int64_t kk = base + ql;
       const int lev = flat_level(s_cnt, lo, kk);
       const int64_t nl = (int64_t)1 << (D * lev);
-      const double* src = p.q[lev == cb_lev ? srcB : srcA];
+      const double* src = lev == cb_lev ? qB : qA;
       const int len = s_cnt[lev - lo];
       const int t = s_t[ql];
-      // the group's listed siblings follow it in the list (from the block's
-      // entries; past the block's last entry, from the list itself)
+      // the group's listed siblings follow it in the list (the block's
+      // entries and the NS - 1 after them, all in LDS)
       uint32_t cbits = 1u << (t & (NS - 1));
       for (int e = 1; e < NS && kk + e < len; e++) {
-        const int u = ql + e < CH ? s_t[ql + e] : p.lst[LS_GHOST][lt.off[lev] + kk + e];
+        const int u = s_t[ql + e];
         if ((u >> D) != (t >> D)) break;
         cbits |= 1u << (u & (NS - 1));
       }
