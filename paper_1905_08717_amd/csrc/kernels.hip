@@ -1365,28 +1365,62 @@ __global__ __launch_bounds__(TPB) void k_rface(Geo g, Dev p, int lo, int hi) {
   constexpr int NF = 2 * D;
   __shared__ int s_cnt[MRD_MAXLEV + 1];
   __shared__ LevTab lt;
+  __shared__ int s_t[TPB], s_lev[TPB];  // the chunk's entries and their levels
+  __shared__ int s_q[TPB * NF];         // its refined faces: lane << 3 | face
+  __shared__ int s_n;
   levtab_fill(g, lt);  // flat_setup synchronises
-  const int64_t nitem = flat_setup(p, LS_IFACE, lo, hi, s_cnt) * NF;
-  GSL(it, nitem) {
-    int64_t kk = it / NF;
-    const int f = (int)(it - kk * NF);
-    const int lev = flat_level(s_cnt, lo, kk);
-    const int64_t t = p.lst[LS_IFACE][lt.off[lev] + kk];
-    const int64_t nl = (int64_t)1 << (D * lev);
-    const int n = 1 << lev;
-    const int64_t inst = t >> (D * lev);
-    const uint64_t key = (uint64_t)(t & (nl - 1));
-    int x[3] = {0, 0, 0};
-    mdec<D>(key, x);
-    const int dir = f >> 1, side = f & 1;
-    uint64_t ky;
-    if (!nbhd_key<D>(g, x, key, n, dir, side ? 1 : -1, &ky)) continue;
-    if (p.st[lt.off[lev] + inst * nl + (int64_t)ky] != ST_INTERNAL) continue;
-    const int nb = map_nb(x[dir] + (side ? 1 : -1), n, g.periodic[dir]);
-    double F[M];
-    refined_flux<D, PDE>(g, p, lev, stage, inst, x, dir, side, nb, F);
+  const int64_t ntot = flat_setup(p, LS_IFACE, lo, hi, s_cnt);
+  // a chunk of TPB listed leaves per pass: each lane tests its leaf's faces
+  // and queues the refined ones in LDS, then the lanes evaluate the queue
+  // densely (few faces of an interface leaf are refined)
+  for (int64_t base = (int64_t)blockIdx.x * TPB; base < ntot; base += (int64_t)gridDim.x * TPB) {
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
+    const int64_t i = base + threadIdx.x;
+    if (i < ntot) {
+      int64_t kk = i;
+      const int lev = flat_level(s_cnt, lo, kk);
+      const int t = p.lst[LS_IFACE][lt.off[lev] + kk];
+      s_t[threadIdx.x] = t;
+      s_lev[threadIdx.x] = lev;
+      const int64_t nl = (int64_t)1 << (D * lev);
+      const int n = 1 << lev;
+      const uint64_t key = (uint64_t)((int64_t)t & (nl - 1));
+      int x[3] = {0, 0, 0};
+      mdec<D>(key, x);
+      const int64_t ib = lt.off[lev] + ((int64_t)t >> (D * lev)) * nl;
+      uint8_t sv[NF];
+      bool in[NF];
 #pragma unroll
-    for (int k = 0; k < M; k++) p.rflux[lt.rc[lev] + (int64_t)(f * M + k) * (g.B * nl) + t] = F[k];
+      for (int f = 0; f < NF; f++) {
+        uint64_t ky;
+        in[f] = nbhd_key<D>(g, x, key, n, f >> 1, (f & 1) ? 1 : -1, &ky);
+        sv[f] = p.st[ib + (int64_t)(in[f] ? ky : key)];
+      }
+#pragma unroll
+      for (int f = 0; f < NF; f++)
+        if (in[f] && sv[f] == ST_INTERNAL) s_q[atomicAdd(&s_n, 1)] = ((int)threadIdx.x << 3) | f;
+    }
+    __syncthreads();
+    const int nq = s_n;
+    for (int q = threadIdx.x; q < nq; q += TPB) {
+      const int e = s_q[q];
+      const int f = e & 7, ln = e >> 3;
+      const int64_t t = s_t[ln];
+      const int lev = s_lev[ln];
+      const int64_t nl = (int64_t)1 << (D * lev);
+      const int n = 1 << lev;
+      const int64_t inst = t >> (D * lev);
+      int x[3] = {0, 0, 0};
+      mdec<D>((uint64_t)(t & (nl - 1)), x);
+      const int dir = f >> 1, side = f & 1;
+      const int nb = map_nb(x[dir] + (side ? 1 : -1), n, g.periodic[dir]);
+      double F[M];
+      refined_flux<D, PDE>(g, p, lev, stage, inst, x, dir, side, nb, F);
+#pragma unroll
+      for (int k = 0; k < M; k++) p.rflux[lt.rc[lev] + (int64_t)(f * M + k) * (g.B * nl) + t] = F[k];
+    }
+    __syncthreads();  // s_t, s_q and s_n are rewritten by the next chunk
   }
 }
 
@@ -1411,8 +1445,7 @@ static void stage_dp(const Geo& g, const Dev& p, int lo, int hi, int stage, int 
   int nb = blocks_for(g.B * g.n[hif]);
   if (nb > g.iface_grid) nb = g.iface_grid;
   if constexpr (NC<D, PDE>::M >= 4) {
-    int nbf = blocks_for(g.B * g.n[hif] * 2 * D);
-    if (nbf > g.iface_grid) nbf = g.iface_grid;
+    const int nbf = nb;
     if (stage == 1) k_rface<D, PDE, 1><<<nbf, TPB, 0, s>>>(g, p, lo, hif);
     else if (stage == 2) k_rface<D, PDE, 2><<<nbf, TPB, 0, s>>>(g, p, lo, hif);
     else k_rface<D, PDE, 3><<<nbf, TPB, 0, s>>>(g, p, lo, hif);
