@@ -1867,21 +1867,33 @@ __global__ __launch_bounds__(TPB) void k_detail_seed(Geo g, Dev p, int lo, int h
       // internal) and, below L-1, the 2^d children
       constexpr int NN = D == 1 ? 3 : (D == 2 ? 9 : 27);
       const bool kids = lev + 1 <= Lc - 1;
-      uint64_t need = 0ull;
+      // the targets' statuses and marks are requested together (a target
+      // outside the domain reads the node's own bytes, masked; the children's
+      // marks are read whether or not they are targets)
+      uint8_t sv[NN], rv[NN], rk[1 << D];
+      bool inb[NN];
 #pragma unroll
       for (int o = 0; o < NN; o++) {
         const int ox = o % 3 - 1, oy = D > 1 ? (o / 3) % 3 - 1 : 0, oz = D > 2 ? o / 9 - 1 : 0;
         int y[3] = {map_nb(x[0] + ox, n, g.periodic[0]), 0, 0};
         if (D > 1) y[1] = map_nb(x[1] + oy, n, g.periodic[1]);
         if (D > 2) y[2] = map_nb(x[2] + oz, n, g.periodic[2]);
-        if (y[0] < 0 || y[1] < 0 || y[2] < 0) continue;
-        const int64_t Gy = lt.off[lev] + inst * nl + (int64_t)menc<D>(y);
-        if (p.st[Gy] != ST_ABSENT && !(p.rf[Gy] & RF_W)) need |= 1ull << o;
+        inb[o] = y[0] >= 0 && y[1] >= 0 && y[2] >= 0;
+        const int yc[3] = {y[0] < 0 ? 0 : y[0], y[1] < 0 ? 0 : y[1], y[2] < 0 ? 0 : y[2]};
+        const int64_t Gy = inb[o] ? ib + (int64_t)menc<D>(yc) : lt.off[lev] + t;
+        sv[o] = p.st[Gy];
+        rv[o] = p.rf[Gy];
       }
+#pragma unroll
+      for (int cb = 0; cb < (1 << D); cb++) rk[cb] = p.rf[lt.off[lev + 1] + (t << D) + cb];
+      uint64_t need = 0ull;
+#pragma unroll
+      for (int o = 0; o < NN; o++)
+        if (inb[o] && sv[o] != ST_ABSENT && !(rv[o] & RF_W)) need |= 1ull << o;
       if (kids) {
 #pragma unroll
         for (int cb = 0; cb < (1 << D); cb++)
-          if (!(p.rf[lt.off[lev + 1] + (t << D) + cb] & RF_W)) need |= 1ull << (NN + cb);
+          if (!(rk[cb] & RF_W)) need |= 1ull << (NN + cb);
       }
 #pragma unroll
       for (int o = 0; o < NN; o++) {
@@ -1940,16 +1952,24 @@ __global__ __launch_bounds__(TPB) void k_close(Geo g, Dev p, int lev) {
       int y[3];
       mdec<D>((uint64_t)(t & (nf - 1)), y);
       constexpr int NN = D == 1 ? 3 : (D == 2 ? 9 : 27);
-      uint32_t need = 0u;
+      // the targets' marks are requested together (a target outside the
+      // domain reads the parent's own byte, masked)
+      const int yp[3] = {y[0] >> 1, y[1] >> 1, y[2] >> 1};
+      uint8_t rv[NN];
+      bool inb[NN];
 #pragma unroll
       for (int o = 0; o < NN; o++) {
         const int ox = o % 3 - 1, oy = D > 1 ? (o / 3) % 3 - 1 : 0, oz = D > 2 ? o / 9 - 1 : 0;
-        int X[3] = {map_nb((y[0] >> 1) + ox, nc, g.periodic[0]), 0, 0};
-        if (D > 1) X[1] = map_nb((y[1] >> 1) + oy, nc, g.periodic[1]);
-        if (D > 2) X[2] = map_nb((y[2] >> 1) + oz, nc, g.periodic[2]);
-        if (X[0] < 0 || X[1] < 0 || X[2] < 0) continue;
-        if (!(p.rf[g.off[lev] + ibc + (int64_t)menc<D>(X)] & RF_W)) need |= 1u << o;
+        int X[3] = {map_nb(yp[0] + ox, nc, g.periodic[0]), 0, 0};
+        if (D > 1) X[1] = map_nb(yp[1] + oy, nc, g.periodic[1]);
+        if (D > 2) X[2] = map_nb(yp[2] + oz, nc, g.periodic[2]);
+        inb[o] = X[0] >= 0 && X[1] >= 0 && X[2] >= 0;
+        rv[o] = p.rf[g.off[lev] + ibc + (int64_t)menc<D>(inb[o] ? X : yp)];
       }
+      uint32_t need = 0u;
+#pragma unroll
+      for (int o = 0; o < NN; o++)
+        if (inb[o] && !(rv[o] & RF_W)) need |= 1u << o;
 #pragma unroll
       for (int o = 0; o < NN; o++) {
         if (!((need >> o) & 1u)) continue;
@@ -1987,21 +2007,27 @@ __global__ __launch_bounds__(TPB) void k_prune(Geo g, Dev p, int lev, int la) {
       mdec<D>((uint64_t)(t & (nl - 1)), x);
       const int px[3] = {x[0] >> 1, x[1] >> 1, x[2] >> 1};
       const int64_t ibp = g.off[lev - 1] + inst * g.n[lev - 1];
+      // the parent neighbourhood's bytes are requested together (outside
+      // the domain: the parent's own byte, masked); above la the W marks,
+      // on the frozen level the statuses
+      const bool wl = lev - 1 >= la;
+      const uint8_t* tab = wl ? p.rf : p.st;
+      constexpr int NN = D == 1 ? 3 : (D == 2 ? 9 : 27);
+      uint8_t v[NN];
+      bool inb[NN];
+#pragma unroll
+      for (int o = 0; o < NN; o++) {
+        const int ox = o % 3 - 1, oy = D > 1 ? (o / 3) % 3 - 1 : 0, oz = D > 2 ? o / 9 - 1 : 0;
+        int y[3] = {map_nb(px[0] + ox, np, g.periodic[0]), 0, 0};
+        if (D > 1) y[1] = map_nb(px[1] + oy, np, g.periodic[1]);
+        if (D > 2) y[2] = map_nb(px[2] + oz, np, g.periodic[2]);
+        inb[o] = y[0] >= 0 && y[1] >= 0 && y[2] >= 0;
+        v[o] = tab[ibp + (int64_t)menc<D>(inb[o] ? y : px)];
+      }
       bool ok = true;
 #pragma unroll
-      for (int oz = (D > 2 ? -1 : 0); oz <= (D > 2 ? 1 : 0); oz++)
-#pragma unroll
-        for (int oy = (D > 1 ? -1 : 0); oy <= (D > 1 ? 1 : 0); oy++)
-#pragma unroll
-          for (int ox = -1; ox <= 1; ox++) {
-            int y[3] = {map_nb(px[0] + ox, np, g.periodic[0]), 0, 0};
-            if (D > 1) y[1] = map_nb(px[1] + oy, np, g.periodic[1]);
-            if (D > 2) y[2] = map_nb(px[2] + oz, np, g.periodic[2]);
-            if (y[0] < 0 || y[1] < 0 || y[2] < 0) continue;
-            const int64_t Gp = ibp + (int64_t)menc<D>(y);
-            const bool in = (lev - 1 >= la) ? ((p.rf[Gp] & RF_W) != 0) : (p.st[Gp] == ST_INTERNAL);
-            ok = ok && in;
-          }
+      for (int o = 0; o < NN; o++)
+        if (inb[o]) ok = ok & (wl ? ((v[o] & RF_W) != 0) : (v[o] == ST_INTERNAL));
       if (!ok) {
 #pragma unroll
         for (int cb = 0; cb < (1 << D); cb++)
