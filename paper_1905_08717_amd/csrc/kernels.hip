@@ -928,12 +928,13 @@ __device__ __forceinline__ void transverse(int dir, int& t0, int& t1) {
 // own stage state) and the neighbour's children (finer-side values: S1 q^n,
 // S2 eq. projleaf / projnode, S3 stage-3 or eq. rk3proj values).
 template <int D, int PDE>
-__device__ __forceinline__ void refined_flux(const Geo& g, const Dev& p, int lev, int stage, int64_t inst,
-                                             const int* x, int dir, int side, int nbx, double* F) {
+__device__ __forceinline__ void refined_flux(const Geo& g, const LevTab& lt, const Dev& p, int lev, int stage,
+                                             int64_t inst, const int* x, int dir, int side, int nbx, double* F) {
   constexpr int M = NC<D, PDE>::M;
   const double* cur = p.q[stage == 1 ? SL_Q0 : (stage == 2 ? SL_Q1 : SL_QH)];
-  const int64_t ib = g.off[lev] + inst * g.n[lev];
-  const int64_t ibf = g.off[lev + 1] + inst * g.n[lev + 1];
+  // level constants from the launch's LDS table (lev differs per lane)
+  const int64_t ib = lt.off[lev] + inst * ((int64_t)1 << (D * lev));
+  const int64_t ibf = lt.off[lev + 1] + inst * ((int64_t)1 << (D * (lev + 1)));
   double T[M][8];
 #pragma unroll
   for (int k = 0; k < M; k++) {
@@ -981,7 +982,7 @@ __device__ __forceinline__ void refined_flux(const Geo& g, const Dev& p, int lev
         c[0][k] = fin[0][k]; c[1][k] = fin[1][k]; c[2][k] = own[0][k]; c[3][k] = own[1][k];
       }
     }
-    face_flux<D, PDE>(g, lev + 1, dir, adv_velocity<PDE>(g, p, inst, dir), c, Fb);
+    face_flux_ix<D, PDE>(g, lt.ix[lev + 1][dir], dir, adv_velocity<PDE>(g, p, inst, dir), c, Fb);
 #pragma unroll
     for (int k = 0; k < M; k++) Fs[k] = (b == 0) ? Fb[k] : (Fs[k] + Fb[k]);
   }
@@ -1243,7 +1244,7 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
               for (int k = 0; k < M; k++)
                 F[k] = p.rflux[lt.rc[lev] + (int64_t)((2 * dir + side) * M + k) * (g.B * nl) + t];
             } else {
-              refined_flux<D, PDE>(g, p, lev, stage, inst, x, dir, side, nbs[dir][side], F);
+              refined_flux<D, PDE>(g, lt, p, lev, stage, inst, x, dir, side, nbs[dir][side], F);
             }
           }
           else
@@ -1416,7 +1417,7 @@ __global__ __launch_bounds__(TPB) void k_rface(Geo g, Dev p, int lo, int hi) {
       const int dir = f >> 1, side = f & 1;
       const int nb = map_nb(x[dir] + (side ? 1 : -1), n, g.periodic[dir]);
       double F[M];
-      refined_flux<D, PDE>(g, p, lev, stage, inst, x, dir, side, nb, F);
+      refined_flux<D, PDE>(g, lt, p, lev, stage, inst, x, dir, side, nb, F);
 #pragma unroll
       for (int k = 0; k < M; k++) p.rflux[lt.rc[lev] + (int64_t)(f * M + k) * (g.B * nl) + t] = F[k];
     }
