@@ -213,12 +213,16 @@ mr_status mr_max_wavespeed(mr_ctx* c, double* out);
 /* Launch configuration of a context: the most workgroups given to the
  * list-driven kernels (stage, ghost values, projections, end of step;
  * default 2048), to the interface-leaf stage launches (512) and to the
- * list compaction (8192); the kernels loop over the rest.  A tuning knob
- * only: results are identical for every setting.  A value of 0 keeps the
- * current one; values outside 0..65535 give MR_EINVAL.  Setting it drops
- * the captured macro-step graph (recaptured by the next mr_lt_step).     */
+ * list compaction (8192); the kernels loop over the rest.  bulk_levels is
+ * the block-to-level schedule of the bulk stage kernel: 1 (default) one
+ * launch per stage whose workgroups take the leaves of all levels of the
+ * stage as one list, 2 one launch per level.  Tuning knobs only: results
+ * are identical for every setting.  A value of 0 keeps the current one;
+ * grids outside 0..65535 and bulk_levels outside 0..2 give MR_EINVAL.
+ * Setting it drops the captured macro-step graph (recaptured by the next
+ * mr_lt_step).                                                            */
 typedef struct {
-  int32_t list_grid, iface_grid, comp_grid;
+  int32_t list_grid, iface_grid, comp_grid, bulk_levels;
 } mr_launch;
 mr_status mr_set_launch(mr_ctx* c, const mr_launch* l);
 mr_status mr_get_launch(mr_ctx* c, mr_launch* l);   /* l: host struct, filled */

@@ -3,7 +3,8 @@ measuring macro steps of the actual workload.
 
 The knobs (``mr_set_launch``) are the most workgroups given to the
 list-driven kernels, to the interface-leaf stage launches and to the list
-compaction.  They change no result -- every kernel loops over whatever its
+compaction, and the block-to-level schedule of the bulk stage kernel (one
+launch over all levels of a stage, or one per level).  They change no result -- every kernel loops over whatever its
 grid does not cover -- only how the work is spread over the 256 compute
 units: a grid just above the number of resident workgroups leaves a second,
 mostly idle round; a much larger one adds per-workgroup set-up.  The right
@@ -29,6 +30,9 @@ CANDIDATES = {
     "list_grid": (128, 256, 512, 1024, 1536, 2048, 3072, 4096, 6144, 8192),
     "iface_grid": (64, 128, 256, 512, 1024, 2048),
     "comp_grid": (256, 512, 1024, 2048, 4096, 8192, 16384),
+    # block-to-level schedule of the bulk stage kernel: one launch over all
+    # levels of a stage, or one per level
+    "bulk_levels": (1, 2),
 }
 
 
@@ -95,7 +99,8 @@ def lookup(key: str, path: str = RECORD_PATH):
         return None
     if not rec:
         return None
-    return {k: int(rec[k]) for k in CANDIDATES}
+    # records taken before a knob existed keep its default (omitted here)
+    return {k: int(rec[k]) for k in CANDIDATES if k in rec}
 
 
 def record(key: str, result: dict, note: str, path: str = RECORD_PATH):

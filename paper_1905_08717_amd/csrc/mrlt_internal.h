@@ -73,6 +73,7 @@ struct Geo {
   // launch knobs (no effect on results): grid caps of the list-driven
   // kernels, of the interface-leaf stage launches and of the compaction
   int list_grid, iface_grid, comp_grid;
+  int bulk_split;  // 1: the bulk stage kernel is launched once per level (mr_launch.bulk_levels = 2)
   // verify tree invariants the grading guarantees (stencil cells exist, the
   // coarse side of a refined face is a leaf) as the kernels read them; a
   // violation is reported as MR_ESTATE (environment MRLT_CHECK at init)

@@ -212,8 +212,16 @@ void stage_launch(mr_ctx* c, int lo, int hi, int st, bool bulk, bool iface, int 
   const Geo& g = c->g;
   hipStream_t s = c->stream;
   const int cls = lo == g.L ? MR_KC_STAGE_FINEST : MR_KC_STAGE;
-  if (bulk)
-    timed(c, cls, [&] { timed(c, MR_KC_STAGE_BULK, [&] { launch_stage(g, c->p, lo, hi, st, 0, s, lq0); }); });
+  if (bulk) {
+    // block-to-level schedule: all levels of the stage in one launch, or
+    // one launch per level (the bulk leaves read only their own level)
+    if (g.bulk_split) {
+      for (int lev = lo; lev <= hi; lev++)
+        timed(c, cls, [&] { timed(c, MR_KC_STAGE_BULK, [&] { launch_stage(g, c->p, lev, lev, st, 0, s, lq0); }); });
+    } else {
+      timed(c, cls, [&] { timed(c, MR_KC_STAGE_BULK, [&] { launch_stage(g, c->p, lo, hi, st, 0, s, lq0); }); });
+    }
+  }
   if (iface && lo <= g.L - 1)
     timed(c, cls, [&] { launch_stage(g, c->p, lo, hi < g.L ? hi : g.L - 1, st, 1, s); });
 }
@@ -486,6 +494,7 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
       }
   }
   g.list_grid = 2048;
+  g.bulk_split = 0;
   g.iface_grid = 512;
   g.comp_grid = 8192;
   g.check = getenv("MRLT_CHECK") != nullptr ? 1 : 0;
@@ -830,9 +839,11 @@ mr_status mr_set_launch(mr_ctx* c, const mr_launch* l) {
   const int32_t v[3] = {l->list_grid, l->iface_grid, l->comp_grid};
   for (int j = 0; j < 3; j++)
     if (v[j] < 0 || v[j] > 65535) return set_err(c, MR_EINVAL, "launch grid outside 0..65535");
+  if (l->bulk_levels < 0 || l->bulk_levels > 2) return set_err(c, MR_EINVAL, "bulk_levels outside 0..2");
   if (l->list_grid) c->g.list_grid = l->list_grid;
   if (l->iface_grid) c->g.iface_grid = l->iface_grid;
   if (l->comp_grid) c->g.comp_grid = l->comp_grid;
+  if (l->bulk_levels) c->g.bulk_split = l->bulk_levels == 2 ? 1 : 0;
   // the captured macro step holds the old grids (destroyed once no replay
   // of it is in flight)
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -848,6 +859,7 @@ mr_status mr_get_launch(mr_ctx* c, mr_launch* l) {
   l->list_grid = c->g.list_grid;
   l->iface_grid = c->g.iface_grid;
   l->comp_grid = c->g.comp_grid;
+  l->bulk_levels = c->g.bulk_split ? 2 : 1;
   return MR_OK;
 }
 

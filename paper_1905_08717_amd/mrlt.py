@@ -71,7 +71,8 @@ class MrInstanceDesc(ctypes.Structure):
 
 
 class MrLaunch(ctypes.Structure):
-    _fields_ = [("list_grid", ctypes.c_int32), ("iface_grid", ctypes.c_int32), ("comp_grid", ctypes.c_int32)]
+    _fields_ = [("list_grid", ctypes.c_int32), ("iface_grid", ctypes.c_int32), ("comp_grid", ctypes.c_int32),
+                ("bulk_levels", ctypes.c_int32)]
 
 
 class MrStats(ctypes.Structure):
@@ -357,17 +358,19 @@ class Solver:
         self._check(load_library().mr_max_wavespeed(self._h, arr), "mr_max_wavespeed")
         return np.array(arr[:])
 
-    def set_launch(self, list_grid: int = 0, iface_grid: int = 0, comp_grid: int = 0):
+    def set_launch(self, list_grid: int = 0, iface_grid: int = 0, comp_grid: int = 0, bulk_levels: int = 0):
         """Grid caps of the list-driven kernels, the interface-leaf stage
-        launches and the compaction (0 keeps a value); results do not
-        depend on them."""
-        lc = MrLaunch(int(list_grid), int(iface_grid), int(comp_grid))
+        launches and the compaction, and the bulk stage kernel's
+        block-to-level schedule (1: one launch over all levels of a stage,
+        2: one per level); 0 keeps a value; results do not depend on them."""
+        lc = MrLaunch(int(list_grid), int(iface_grid), int(comp_grid), int(bulk_levels))
         self._check(load_library().mr_set_launch(self._h, ctypes.byref(lc)), "mr_set_launch")
 
     def get_launch(self) -> dict:
         lc = MrLaunch()
         self._check(load_library().mr_get_launch(self._h, ctypes.byref(lc)), "mr_get_launch")
-        return {"list_grid": lc.list_grid, "iface_grid": lc.iface_grid, "comp_grid": lc.comp_grid}
+        return {"list_grid": lc.list_grid, "iface_grid": lc.iface_grid, "comp_grid": lc.comp_grid,
+                "bulk_levels": lc.bulk_levels}
 
     def flame_speed(self):
         """v_f of every instance from its current leaves (flame problems)."""

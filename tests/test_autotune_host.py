@@ -7,7 +7,7 @@ from paper_1905_08717_amd import autotune as A
 
 class FakeSolver:
     def __init__(self):
-        self.knobs = {"list_grid": 2048, "iface_grid": 512, "comp_grid": 8192}
+        self.knobs = {"list_grid": 2048, "iface_grid": 512, "comp_grid": 8192, "bulk_levels": 1}
 
     def set_launch(self, **kw):
         self.knobs.update({k: v for k, v in kw.items() if v})
@@ -24,7 +24,7 @@ def _model(best):
 
 
 def test_descent_finds_the_separable_optimum(monkeypatch):
-    target = {"list_grid": 3072, "iface_grid": 1024, "comp_grid": 4096}
+    target = {"list_grid": 3072, "iface_grid": 1024, "comp_grid": 4096, "bulk_levels": 2}
     model = _model(target)
     calls = []
 
@@ -40,7 +40,7 @@ def test_descent_finds_the_separable_optimum(monkeypatch):
     assert r["seconds_per_step"] == 1.0 and r["default"] > 1.0
     assert len(r["trials"]) == len(calls)
     # the first trial times the context's current setting
-    assert calls[0] == {"list_grid": 2048, "iface_grid": 512, "comp_grid": 8192}
+    assert calls[0] == {"list_grid": 2048, "iface_grid": 512, "comp_grid": 8192, "bulk_levels": 1}
 
 
 def test_margin_keeps_the_incumbent_on_small_gains(monkeypatch):
@@ -78,4 +78,7 @@ def test_stored_records_name_every_knob():
         return
     for key, rec in data.items():
         for k in A.CANDIDATES:
-            assert 1 <= int(rec[k]) <= 65535, (key, k)
+            if k == "bulk_levels":
+                assert int(rec.get(k, 1)) in (1, 2), (key, k)
+            else:
+                assert 1 <= int(rec[k]) <= 65535, (key, k)

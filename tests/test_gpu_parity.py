@@ -706,7 +706,8 @@ def test_launch_knobs_do_not_change_results(mods):
     q = np.stack([W.nagumo_front(8, W.SEED + 300 + i) for i in range(B)])
     dt = W.nagumo_dt(cfg)
     runs = []
-    for knobs in ({}, {"list_grid": 3, "iface_grid": 1, "comp_grid": 5}, {"list_grid": 60000, "comp_grid": 60000}):
+    for knobs in ({}, {"list_grid": 3, "iface_grid": 1, "comp_grid": 5}, {"list_grid": 60000, "comp_grid": 60000},
+                  {"bulk_levels": 2}):
         s = mrlt.Solver(cfg, n_inst=B)
         s.set_launch(**knobs)
         assert all(s.get_launch()[k] == v for k, v in knobs.items())
@@ -723,6 +724,8 @@ def test_launch_knobs_do_not_change_results(mods):
         s.set_launch(list_grid=-1)
     with pytest.raises(mrlt.MrError):
         s.set_launch(comp_grid=70000)
+    with pytest.raises(mrlt.MrError):
+        s.set_launch(bulk_levels=3)
 
 
 @pytest.mark.parametrize("case", ["nagumo2d", "euler3d"])
