@@ -592,6 +592,33 @@ __host__ __device__ __forceinline__ bool wide_level(const Geo& g, int lev) {
   return g.comp_chunk[lev] == (1 << BS_SHIFT) && g.B * g.n[lev] >= ((int64_t)1 << 20);
 }
 
+// Wave-uniform values: the first active lane's value, and loads through the
+// scalar data cache of memory that no kernel writes while it runs (the
+// address must be wave-uniform).  The load waits for its reply in the same
+// asm block; being opaque, it also keeps the compiler from turning it back
+// into a per-lane load where it can prove the lane's own index equal.  A
+// byte is read as the aligned 32-bit word that holds it (same page).
+__device__ __forceinline__ int64_t rfl64(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+// b[j] and d[k] in one round trip
+__device__ __forceinline__ void uload_u8_f64(const uint8_t* b, int64_t j, const double* d, int64_t k, uint8_t* bv,
+                                             double* dv) {
+  const uintptr_t ab = (uintptr_t)(b + j);
+  const uint32_t* w = (const uint32_t*)(ab & ~(uintptr_t)3);
+  const double* ad = d + k;
+  uint32_t wv;
+  double v;
+  asm volatile("s_load_dword %0, %2, 0x0\n\ts_load_dwordx2 %1, %3, 0x0\n\ts_waitcnt lgkmcnt(0)"
+               : "=&s"(wv), "=&s"(v)
+               : "s"(w), "s"(ad)
+               : "memory");
+  *bv = (uint8_t)(wv >> (8 * (int)(ab & 3)));
+  *dv = v;
+}
+
 // Per-level constants of a launch, staged in LDS: kernels whose lanes work on
 // different levels would otherwise index the kernel arguments by a per-lane
 // level, a vector load of its own in front of every cell's loads.
@@ -1084,19 +1111,32 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
       int x[3] = {0, 0, 0};
       if (!FAST) mdec<D>(key, x);
       const int64_t ib = lt.off[lev] + inst * nl;
-      // the instance's finest step, requested with the cell's other loads;
-      // first the tile flag that says whether the leaf keeps NERK values
-      // (its reply arrives while the stencil loads are in flight)
+      // the tile flag that says whether the leaf keeps NERK values and the
+      // instance's finest step, through the scalar data cache: each pass
+      // serves the lanes that share the first pending lane's 4096-cell tile
+      // and instance (one pass for most waves), so these values take no
+      // vector memory instruction
       const bool tiled = !IFACE && !finest && g.lt && lt.wide[lev];
-      const uint8_t nsv = p.nsum[tiled ? lt.bsoff[lev] + (t >> BS_SHIFT) : (int64_t)0];  // no branch around the load
+      const int64_t tix = tiled ? lt.bsoff[lev] + (t >> BS_SHIFT) : (int64_t)0;
+      uint8_t nsv = 0;
+      double dti = 0.0;
+      for (bool pend = true; pend;) {
+        const int64_t tix0 = rfl64(tix), inst0 = rfl64(inst);
+        uint8_t ns;
+        double dv;
+        uload_u8_f64(p.nsum, tix0, p.dt, inst0, &ns, &dv);
+        const bool mine = tix == tix0 && inst == inst0;
+        nsv = mine ? ns : nsv;
+        dti = mine ? dv : dti;
+        pend = !mine;
+      }
       const uint8_t nflag = tiled ? nsv : (uint8_t)1;
-      const double dti = p.dt[inst];
       // status of the 2d face neighbours (3: outside the domain); a cell
       // outside loads its own status instead, so that every load is issued
       // at once without a branch
       int nbs[D][2];
       uint8_t sts[D][2];
-      uint64_t fkey[D][2];  // FAST: key of the face neighbour's value
+      uint64_t fkey[D][2];  // key of the face neighbour (the cell itself outside the domain)
       bool fflip[D][2];     // FAST: Dirichlet sign of that value
       bool refined = false;
       if (FAST) {
@@ -1177,9 +1217,8 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
           }
       }
       // the leaf's own slots; at stage 2 also the NERK partial values it adds
-      // to where it keeps them (elsewhere the same loads read its own q^n
-      // again, a cache hit: no branch, and the loads that do not wait for the
-      // tile flag go first)
+      // to where it keeps them (the loads that do not wait for the tile flag
+      // go first)
       double q0v[M], qsv[M], n14v[M], n34v[M];
 #pragma unroll
       for (int k = 0; k < M; k++) {
@@ -1187,19 +1226,18 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
         q0v[k] = p.q[SL_Q0][I];
         qsv[k] = stage == 2 ? p.q[SL_Q1][I] : (stage == 3 ? p.q[SL_QH][I] : 0.0);
       }
-      if (PRE && stage == 2 && g.lt) {
-        const bool keep = !finest && nflag != 0;
-        const double* a14 = keep ? p.q[g.rk == 2 ? SL_QH : SL_N14] : p.q[SL_Q0];
-        const double* a34 = keep ? p.q[SL_N34] : p.q[SL_Q0];
+#pragma unroll
+      for (int k = 0; k < M; k++) n14v[k] = n34v[k] = 0.0;
+      if (PRE && stage == 2 && g.lt && !finest && nflag != 0) {
+        // only the leaves that keep NERK values read their partials: the
+        // flag is per 4096-cell tile, so the branch is uniform over most
+        // waves, and a load that is not issued costs no cache access
 #pragma unroll
         for (int k = 0; k < M; k++) {
           const int64_t I = (int64_t)k * NT + G;
-          n14v[k] = a14[I];
-          n34v[k] = g.rk == 2 ? 0.0 : a34[I];
+          n14v[k] = p.q[g.rk == 2 ? SL_QH : SL_N14][I];
+          n34v[k] = g.rk == 2 ? 0.0 : p.q[SL_N34][I];
         }
-      } else {
-#pragma unroll
-        for (int k = 0; k < M; k++) n14v[k] = n34v[k] = 0.0;
       }
       if (!PRE && !IFACE && refined && !finest) continue;  // the interface launch owns it
       const bool active = IFACE || finest || !refined;
@@ -1266,18 +1304,17 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
                 *r = *r + (wh * F[k]);
               }
             } else if (sts[dir][side] == ST_ABSENT) {
-              // fine side of a coarse leaf's refined face
-              if (FAST) mdec<D>(key, x);
-              const int nb = FAST ? map_nb(x[dir] + (side ? 1 : -1), n, g.periodic[dir]) : nbs[dir][side];
-              int y[3] = {x[0] >> 1, x[1] >> 1, x[2] >> 1};
-              y[dir] = nb >> 1;
-              const int64_t tX = inst * (nl >> D) + (int64_t)menc<D>(y);
+              // fine side of a coarse leaf's refined face: the coarse leaf is
+              // the parent of the absent neighbour (its key shifted by d
+              // bits), and the subface is the leaf's position within its own
+              // parent along the transverse axes (bit a of the key: x_a & 1)
+              const int64_t tX = inst * (nl >> D) + (int64_t)(fkey[dir][side] >> D);
               if (g.check && p.st[lt.off[lev - 1] + tX] != ST_LEAF) flag_bad(p, inst, 8);
               int t0, t1;
               transverse<D>(dir, t0, t1);
               int b = 0;
-              if (t0 >= 0) b |= x[t0] & 1;
-              if (t1 >= 0) b |= (x[t1] & 1) << 1;
+              if (t0 >= 0) b |= (int)((key >> t0) & 1u);
+              if (t1 >= 0) b |= (int)((key >> t1) & 1u) << 1;
               const int fX = 2 * dir + (side ? 0 : 1);
               for (int k = 0; k < M; k++) {
                 double* r = p.regf + lt.rf[lev - 1] + (int64_t)((fX * g.nsub + b) * g.m + k) * (g.B * (nl >> D)) + tX;
