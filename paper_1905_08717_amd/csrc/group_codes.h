@@ -16,8 +16,14 @@
 // instead of a branch per cell and neighbour.
 //
 // Status bytes: 0 absent, 1 leaf, 2 internal; a neighbour group outside the
-// domain is passed as all zeros.  Codes: 1 leaf, 2 internal, 4 interface
-// leaf, 8 virtual cell (one byte per cell, Morton order).
+// domain is passed as all zeros, with its bit set in `outside`.  Codes (one
+// byte per cell, Morton order): 1 leaf, 2 internal, 4 interface leaf, 8
+// virtual cell; in 1D and 2D also bit 4 + 2a + s: a leaf whose face
+// neighbour along axis a (s = 0 below, 1 above) is absent and inside the
+// domain, i.e. the fine side of a refined face (the neighbour is a virtual
+// cell whose parent is a coarser leaf).  The face bits mark no list; the
+// stage kernels read them instead of the neighbours' statuses (3D has six
+// faces, more than the byte holds, and its kernels read the statuses).
 #pragma once
 #include <stdint.h>
 
@@ -99,15 +105,17 @@ GC_HD constexpr uint32_t parent_cells(int k) {
 }
 
 // c: the group's four status words; m[a], p[a]: the adjacent groups below /
-// above along axis a; par: the 16 >> D parent status bytes (0 on the
+// above along axis a; outside: bit 2a (2a + 1) set when m[a] (p[a]) lies
+// outside the domain; par: the 16 >> D parent status bytes (0 on the
 // coarsest level); reach: stencil reach of a leaf (1 or 2).  Writes the 16
 // code bytes to out[4]; returns the counts of the four lists (leaf,
 // internal, interface, virtual), 16 bits each.
 template <int D>
-GC_HD uint64_t codes16(const uint32_t* c, const uint32_t (*m)[4], const uint32_t (*p)[4], uint64_t par, int reach,
-                       uint32_t* out) {
+GC_HD uint64_t codes16(const uint32_t* c, const uint32_t (*m)[4], const uint32_t (*p)[4], uint32_t outside,
+                       uint64_t par, int reach, uint32_t* out) {
   const uint32_t Lc = status_mask<D>(c, 0), Ic = status_mask<D>(c, 1);
   uint32_t near_int = 0u, near_leaf = 0u;
+  uint32_t Af[4] = {0u, 0u, 0u, 0u};  // leaves whose face neighbour (axis a, side s) is absent: Af[2a + s]
 #pragma unroll
   for (int a = 0; a < D; a++) {
     const uint32_t Lm = status_mask<D>(m[a], 0), Lp = status_mask<D>(p[a], 0);
@@ -118,6 +126,13 @@ GC_HD uint64_t codes16(const uint32_t* c, const uint32_t (*m)[4], const uint32_t
       near_leaf |= shifted<D>(Lc, Lm, Lp, a, o);
       if (o == -1 || o == 1 || reach == 2) near_int |= shifted<D>(Ic, Im, Ip, a, o);
     }
+    if (D <= 2) {
+      // present cells (leaf or internal); outside the domain counts as present
+      const uint32_t Pm = ((outside >> (2 * a)) & 1u) ? 0xFFFFu : (Lm | Im);
+      const uint32_t Pp = ((outside >> (2 * a + 1)) & 1u) ? 0xFFFFu : (Lp | Ip);
+#pragma unroll
+      for (int sd = 0; sd < 2; sd++) Af[(2 * a + sd) & 3] = Lc & ~shifted<D>(Lc | Ic, Pm, Pp, a, sd ? 1 : -1) & 0xFFFFu;
+    }
   }
   uint32_t pleaf = 0u;
 #pragma unroll
@@ -126,9 +141,12 @@ GC_HD uint64_t codes16(const uint32_t* c, const uint32_t (*m)[4], const uint32_t
   const uint32_t F = Lc & near_int;
   const uint32_t V = ~(Lc | Ic) & 0xFFFFu & pleaf & near_leaf;
 #pragma unroll
-  for (int q = 0; q < 4; q++)
+  for (int q = 0; q < 4; q++) {
     out[q] = spread(nibble<D>(Lc, q)) | (spread(nibble<D>(Ic, q)) << 1) | (spread(nibble<D>(F, q)) << 2) |
              (spread(nibble<D>(V, q)) << 3);
+#pragma unroll
+    for (int f = 0; f < 2 * D && D <= 2; f++) out[q] |= spread(nibble<D>(Af[f & 3], q)) << (4 + f);
+  }
   return (uint64_t)__builtin_popcount(Lc) | ((uint64_t)__builtin_popcount(Ic) << 16) |
          ((uint64_t)__builtin_popcount(F) << 32) | ((uint64_t)__builtin_popcount(V) << 48);
 }

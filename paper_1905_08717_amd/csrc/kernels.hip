@@ -619,6 +619,11 @@ __device__ __forceinline__ void uload_u8_f64(const uint8_t* b, int64_t j, const 
   *dv = v;
 }
 
+// list codes per cell (group_codes.h), written by the compaction's count
+// pass; in 1D and 2D, bit CODE_FACE0 << (2 a + s): the face neighbour of a
+// leaf along axis a (side s) is absent and inside the domain
+static constexpr uint32_t CODE_LEAF = 1u, CODE_INT = 2u, CODE_IFACE = 4u, CODE_GHOST = 8u, CODE_FACE0 = 16u;
+
 // Per-level constants of a launch, staged in LDS: kernels whose lanes work on
 // different levels would otherwise index the kernel arguments by a per-lane
 // level, a vector load of its own in front of every cell's loads.
@@ -1133,7 +1138,14 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
       const uint8_t nflag = tiled ? nsv : (uint8_t)1;
       // status of the 2d face neighbours (3: outside the domain); a cell
       // outside loads its own status instead, so that every load is issued
-      // at once without a branch
+      // at once without a branch.  Bulk leaves in 1D and 2D read their list
+      // code instead (one byte of their own, written by the compaction): it
+      // says whether the stencil reaches an internal cell (the interface
+      // launch owns the leaf) and which face neighbours are absent (the
+      // fine side of a refined face); the other face neighbours of a bulk
+      // leaf are leaves or virtual cells, which it reads alike.
+      constexpr bool CODED = !IFACE && D <= 2;
+      const uint8_t code = CODED ? p.ccode[G] : (uint8_t)0;
       int nbs[D][2];
       uint8_t sts[D][2];
       uint64_t fkey[D][2];  // key of the face neighbour (the cell itself outside the domain)
@@ -1157,7 +1169,8 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
             const bool in = !edge || per;
             fkey[dir][side] = ky;
             fflip[dir][side] = edge && !per && ((g.dirichlet[dir] >> side) & 1);
-            const uint8_t sv = p.st[ib + (int64_t)ky];
+            const uint8_t sv = CODED ? (((code >> (4 + 2 * dir + side)) & 1u) ? (uint8_t)ST_ABSENT : (uint8_t)ST_LEAF)
+                                     : p.st[ib + (int64_t)ky];
             sts[dir][side] = in ? sv : (uint8_t)3;
             nbs[dir][side] = in ? 0 : -1;  // coordinates only where needed (below)
             refined = refined || (in && sv == ST_INTERNAL);
@@ -1172,14 +1185,16 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
             nbs[dir][side] = nb;
             uint64_t ky;
             const bool in = nbhd_key<D>(g, x, key, n, dir, side ? 1 : -1, &ky);
-            const uint8_t sv = p.st[ib + (int64_t)(in ? ky : key)];
+            const uint8_t sv = CODED ? (((code >> (4 + 2 * dir + side)) & 1u) ? (uint8_t)ST_ABSENT : (uint8_t)ST_LEAF)
+                                     : p.st[ib + (int64_t)(in ? ky : key)];
             sts[dir][side] = in ? sv : (uint8_t)3;
             fkey[dir][side] = in ? ky : key;
             fflip[dir][side] = false;
             refined = refined || (in && sv == ST_INTERNAL);
           }
       }
-      if (!IFACE && (PRE || (!finest && !refined)) && (PDE != PDE_NAGUMO && PDE != PDE_LINEAR) &&
+      if (CODED) refined = (code & CODE_IFACE) != 0;
+      if (!IFACE && !CODED && (PRE || (!finest && !refined)) && (PDE != PDE_NAGUMO && PDE != PDE_LINEAR) &&
           stencil_reach(g) == 2) {
 #pragma unroll
         for (int dir = 0; dir < D; dir++)
@@ -2288,7 +2303,6 @@ __device__ __forceinline__ uint64_t code_count(uint32_t c) {
   return (uint64_t)(c & 1u) | ((uint64_t)((c >> 1) & 1u) << 16) | ((uint64_t)((c >> 2) & 1u) << 32) |
          ((uint64_t)((c >> 3) & 1u) << 48);
 }
-static constexpr uint32_t CODE_LEAF = 1u, CODE_INT = 2u, CODE_IFACE = 4u, CODE_GHOST = 8u;
 
 // one cell, direct loads
 template <int D>
@@ -2297,13 +2311,13 @@ __device__ __forceinline__ uint32_t cell_code(const Geo& g, const Dev& p, int le
   const uint8_t st = p.st[g.off[lev] + t];
   if (st == ST_INTERNAL) return CODE_INT;
   const bool leaf = st == ST_LEAF;
-  if (leaf && lev == g.L) return CODE_LEAF;
   if (!leaf && (lev == g.l0 || p.st[g.off[lev - 1] + (t >> D)] != ST_LEAF)) return 0u;
   const int n = 1 << lev;
   const int64_t ib = g.off[lev] + (t >> (D * lev)) * nl;
   int x[3];
   mdec<D>((uint64_t)(t & (nl - 1)), x);
   bool hit = false;
+  uint32_t faces = 0u;
 #pragma unroll
   for (int dir = 0; dir < D; dir++)
 #pragma unroll
@@ -2313,9 +2327,11 @@ __device__ __forceinline__ uint32_t cell_code(const Geo& g, const Dev& p, int le
       if (u < 0) continue;
       int y[3] = {x[0], x[1], x[2]};
       y[dir] = u;
-      hit = hit || p.st[ib + (int64_t)menc<D>(y)] == (leaf ? ST_INTERNAL : ST_LEAF);
+      const uint8_t sy = p.st[ib + (int64_t)menc<D>(y)];
+      hit = hit || sy == (leaf ? ST_INTERNAL : ST_LEAF);
+      if (D <= 2 && leaf && (o == -1 || o == 1) && sy == ST_ABSENT) faces |= CODE_FACE0 << (2 * dir + (o > 0));
     }
-  if (leaf) return hit ? (CODE_LEAF | CODE_IFACE) : CODE_LEAF;
+  if (leaf) return CODE_LEAF | (hit ? CODE_IFACE : 0u) | faces;
   return hit ? CODE_GHOST : 0u;
 }
 
@@ -2335,6 +2351,7 @@ __device__ __forceinline__ uint64_t group_codes(const Geo& g, const Dev& p, int 
   int x0[3];
   mdec<D>((uint64_t)(t0 & (nl - 1)), x0);
   uint32_t m[3][4], q[3][4];
+  uint32_t outside = 0u;
 #pragma unroll
   for (int a = 0; a < 3; a++) {
 #pragma unroll
@@ -2346,6 +2363,8 @@ __device__ __forceinline__ uint64_t group_codes(const Geo& g, const Dev& p, int 
           int y[3] = {x0[0], x0[1], x0[2]};
           y[a] = u;
           v = *reinterpret_cast<const uint4*>(p.st + ib + (int64_t)menc<D>(y));
+        } else {
+          outside |= 1u << (2 * a + s);
         }
       }
       uint32_t* w = s ? q[a] : m[a];
@@ -2353,7 +2372,7 @@ __device__ __forceinline__ uint64_t group_codes(const Geo& g, const Dev& p, int 
     }
   }
   const uint32_t cw[4] = {c.x, c.y, c.z, c.w};
-  return gcodes::codes16<D>(cw, m, q, par, stencil_reach(g), out);
+  return gcodes::codes16<D>(cw, m, q, outside, par, stencil_reach(g), out);
 }
 
 // per-lane cell range of block b: [t0, t0 + cpt)

@@ -5,8 +5,10 @@ the definitions, on random status neighbourhoods in 1D, 2D and 3D.
 Leaf: every leaf; internal: every internal node; interface leaf: a leaf
 with an internal cell at offset +-1 (and +-2 when the stencil reaches two
 cells) along an axis; virtual cell: an absent cell whose parent is a leaf
-and that has a leaf at offset +-1 or +-2 along an axis (Fig. 1, Sec. 2).
-Cells outside the domain count as neither."""
+and that has a leaf at offset +-1 or +-2 along an axis (Fig. 1, Sec. 2);
+in 1D and 2D, bit 16 << (2a + s) of a leaf: its face neighbour along axis
+a (s = 0 below, 1 above) is absent, the fine side of a refined face (no
+list).  Cells outside the domain count as none of these."""
 import os
 import shutil
 import subprocess
@@ -56,7 +58,13 @@ def reference(D, reach, c, m, p, par):
                 elif st == 1:
                     offs = (-2, -1, 1, 2) if reach == 2 else (-1, 1)
                     iface = any(nb(a, o) == 2 for a in range(D) for o in offs)
-                    codes[j] = 1 | (4 if iface else 0)
+                    faces = 0
+                    if D <= 2:
+                        for a in range(D):
+                            for sd, o in enumerate((-1, 1)):
+                                if nb(a, o) == 0:
+                                    faces |= 16 << (2 * a + sd)
+                    codes[j] = 1 | (4 if iface else 0) | faces
                 else:
                     pleaf = par[j >> D] == 1
                     near = any(nb(a, o) == 1 for a in range(D) for o in (-2, -1, 1, 2))
@@ -98,6 +106,8 @@ def test_bit_parallel_codes_match_the_definitions(driver, D):
             line += ["%x" % v for v in words(m[a] or [0] * 16)]
         for a in range(D):
             line += ["%x" % v for v in words(p[a] or [0] * 16)]
+        outside = sum((1 << (2 * a)) * (m[a] is None) + (1 << (2 * a + 1)) * (p[a] is None) for a in range(D))
+        line.append("%x" % outside)
         line.append("%x" % sum(int(s) << (8 * k) for k, s in enumerate(par)))
         cases.append(" ".join(line))
         refs.append(reference(D, reach, c, m, p, par))
@@ -116,3 +126,6 @@ def test_bit_parallel_codes_match_the_definitions(driver, D):
         assert [(cnt >> (16 * k)) & 0xFFFF for k in range(4)] == want
         seen.update(ref)
     assert {0, 1, 2, 5, 8} <= seen
+    if D <= 2:  # every face bit occurs, with and without the interface bit
+        assert all(any(r & (16 << f) for r in seen) for f in range(2 * D))
+        assert any(r & 4 and r & 0xF0 for r in seen)
