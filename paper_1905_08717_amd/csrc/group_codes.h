@@ -123,15 +123,19 @@ GC_HD uint64_t codes16(const uint32_t* c, const uint32_t (*m)[4], const uint32_t
 #pragma unroll
     for (int o = -2; o <= 2; o++) {
       if (o == 0) continue;
-      near_leaf |= shifted<D>(Lc, Lm, Lp, a, o);
-      if (o == -1 || o == 1 || reach == 2) near_int |= shifted<D>(Ic, Im, Ip, a, o);
-    }
-    if (D <= 2) {
-      // present cells (leaf or internal); outside the domain counts as present
-      const uint32_t Pm = ((outside >> (2 * a)) & 1u) ? 0xFFFFu : (Lm | Im);
-      const uint32_t Pp = ((outside >> (2 * a + 1)) & 1u) ? 0xFFFFu : (Lp | Ip);
-#pragma unroll
-      for (int sd = 0; sd < 2; sd++) Af[(2 * a + sd) & 3] = Lc & ~shifted<D>(Lc | Ic, Pm, Pp, a, sd ? 1 : -1) & 0xFFFFu;
+      const uint32_t sL = shifted<D>(Lc, Lm, Lp, a, o);
+      near_leaf |= sL;
+      if (o == -1 || o == 1 || reach == 2) {
+        const uint32_t sI = shifted<D>(Ic, Im, Ip, a, o);
+        near_int |= sI;
+        if (D <= 2 && (o == -1 || o == 1)) {
+          // the face neighbour is a leaf, internal, or outside the domain
+          // (the edge row of the group next to an outside group): else absent
+          const uint32_t edge = o < 0 ? (((outside >> (2 * a)) & 1u) ? below<D>(a, 1) : 0u)
+                                      : (((outside >> (2 * a + 1)) & 1u) ? (~below<D>(a, width<D>(a) - 1) & 0xFFFFu) : 0u);
+          Af[(2 * a + (o > 0)) & 3] = Lc & ~(sL | sI | edge) & 0xFFFFu;
+        }
+      }
     }
   }
   uint32_t pleaf = 0u;
