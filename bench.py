@@ -186,7 +186,7 @@ def traffic_record(args):
     rec = {"kernel": kern, "batch": args.batch, "steps": args.steps, "warmup": args.warmup,
            "launches_averaged": len(f), "fetch_scale": round(sf, 4), "write_scale": round(sw, 4),
            "fetch_bytes_per_launch": round(fetch), "write_bytes_per_launch": round(write),
-           "hbm_bytes_per_launch": round(fetch + write), "kernels_hip_sha256": digest, "launch": launch}
+           "hbm_bytes_per_launch": round(fetch) + round(write), "kernels_hip_sha256": digest, "launch": launch}
     with open(os.path.join(here, "profiles", "stage_bulk_traffic.json"), "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec), flush=True)
