@@ -27,7 +27,7 @@ import os
 import time
 
 CANDIDATES = {
-    "list_grid": (128, 256, 512, 1024, 1536, 2048, 3072, 4096, 6144, 8192),
+    "list_grid": (128, 256, 512, 1024, 1536, 1792, 2048, 3072, 4096, 6144, 8192),
     "iface_grid": (64, 128, 256, 512, 1024, 2048),
     "comp_grid": (256, 512, 1024, 2048, 4096, 8192, 16384),
     # block-to-level schedule of the bulk stage kernel: one launch over all
