@@ -212,7 +212,7 @@ mr_status mr_max_wavespeed(mr_ctx* c, double* out);
 
 /* Launch configuration of a context: the most workgroups given to the
  * list-driven kernels (stage, ghost values, projections, end of step;
- * default 2048), to the interface-leaf stage launches (512) and to the
+ * default 1536), to the interface-leaf stage launches (512) and to the
  * list compaction (8192); the kernels loop over the rest.  bulk_levels is
  * the block-to-level schedule of the bulk stage kernel: 1 (default) one
  * launch per stage whose workgroups take the leaves of all levels of the

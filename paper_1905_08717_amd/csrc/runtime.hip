@@ -493,7 +493,7 @@ mr_status mr_init_batch(int dim, int L, int n_inst, const double* eps, const mr_
         return MR_EINVAL;
       }
   }
-  g.list_grid = 2048;
+  g.list_grid = 1536;  // six resident 4-wave workgroups per CU
   g.bulk_split = 0;
   g.iface_grid = 512;
   g.comp_grid = 8192;
