@@ -1074,11 +1074,16 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
   levtab_fill(g, lt);  // flat_setup synchronises
   const int64_t ntot = flat_setup(p, LS, lo, hi, s_cnt);
   const int64_t step = (int64_t)gridDim.x * blockDim.x;
-  // bulk launches: workgroups are placed on the eight XCDs in turn, so the
-  // workgroups of one XCD take one contiguous run of the pass's chunks (the
-  // stencil lines that neighbouring chunks share then meet in one L2)
+  // bulk launches: workgroups are placed on the eight XCDs in turn; here the
+  // workgroups of one XCD take runs of 16 consecutive chunks of a pass (the
+  // stencil lines that neighbouring chunks share then meet in one L2), and
+  // the runs go to the XCDs in turn, so that a short list still spreads
+  // over all of them
   int bx = (int)blockIdx.x;
-  if (!IFACE && (gridDim.x & 7u) == 0u) bx = (bx & 7) * (int)(gridDim.x >> 3) + (bx >> 3);
+  if (!IFACE && gridDim.x % 128u == 0u) {
+    const int x = bx & 7, j = bx >> 3;
+    bx = (((j >> 4) << 3) + x) * 16 + (j & 15);
+  }
   int64_t i = (int64_t)bx * blockDim.x + threadIdx.x;
   // a lane's list positions only grow: its level and the offset of that
   // level in the flat index space are advanced, not searched again
