@@ -603,6 +603,21 @@ __device__ __forceinline__ int64_t rfl64(int64_t v) {
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
+// Workgroups are placed on the eight XCDs in turn.  For a grid of a
+// multiple of 128 workgroups this numbering gives the workgroups of one XCD
+// runs of 16 consecutive chunks of a pass, the runs handed to the XCDs in
+// turn: list entries that share cache lines (neighbouring chunks of a
+// Morton-ordered list) then meet in one L2, and a short list still spreads
+// over all XCDs.  Other grids keep the hardware's order.
+__device__ __forceinline__ int xcd_run_block() {
+  int bx = (int)blockIdx.x;
+  if (gridDim.x % 128u == 0u) {
+    const int x = bx & 7, j = bx >> 3;
+    bx = (((j >> 4) << 3) + x) * 16 + (j & 15);
+  }
+  return bx;
+}
+
 // b[j] and d[k] in one round trip
 __device__ __forceinline__ void uload_u8_f64(const uint8_t* b, int64_t j, const double* d, int64_t k, uint8_t* bv,
                                              double* dv) {
@@ -832,7 +847,8 @@ __global__ __launch_bounds__(TPB) void k_ghost(Geo g, Dev p, int lo, int hi, int
   // indexed by a per-lane value would be a vector load of its own)
   const double* qA = p.q[srcA];
   const double* qB = p.q[srcB];
-  for (int64_t base = (int64_t)blockIdx.x * CH; base < ntot; base += (int64_t)gridDim.x * CH) {
+  // runs of chunks per XCD: neighbouring virtual cells share parent stencils
+  for (int64_t base = (int64_t)xcd_run_block() * CH; base < ntot; base += (int64_t)gridDim.x * CH) {
     // the lane's entries (and, for the block's first, the entry before it)
     int tv[PER], kv[PER], prev0 = 0;
 #pragma unroll
@@ -1074,16 +1090,9 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
   levtab_fill(g, lt);  // flat_setup synchronises
   const int64_t ntot = flat_setup(p, LS, lo, hi, s_cnt);
   const int64_t step = (int64_t)gridDim.x * blockDim.x;
-  // bulk launches: workgroups are placed on the eight XCDs in turn; here the
-  // workgroups of one XCD take runs of 16 consecutive chunks of a pass (the
-  // stencil lines that neighbouring chunks share then meet in one L2), and
-  // the runs go to the XCDs in turn, so that a short list still spreads
-  // over all of them
-  int bx = (int)blockIdx.x;
-  if (!IFACE && gridDim.x % 128u == 0u) {
-    const int x = bx & 7, j = bx >> 3;
-    bx = (((j >> 4) << 3) + x) * 16 + (j & 15);
-  }
+  // bulk launches: runs of chunks per XCD (the stencil lines that
+  // neighbouring chunks share then meet in one L2)
+  const int bx = IFACE ? (int)blockIdx.x : xcd_run_block();
   int64_t i = (int64_t)bx * blockDim.x + threadIdx.x;
   // a lane's list positions only grow: its level and the offset of that
   // level in the flat index space are advanced, not searched again
