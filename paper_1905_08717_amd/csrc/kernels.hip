@@ -1164,7 +1164,9 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
       // fine side of a refined face); the other face neighbours of a bulk
       // leaf are leaves or virtual cells, which it reads alike.
       constexpr bool CODED = !IFACE && D <= 2;
-      const uint8_t code = CODED ? p.ccode[G] : (uint8_t)0;
+      // (3D leaves take from it whether their stencil reaches an internal
+      // cell, the reach-2 test included, and load the face statuses)
+      const uint8_t code = IFACE ? (uint8_t)0 : p.ccode[G];
       int nbs[D][2];
       uint8_t sts[D][2];
       uint64_t fkey[D][2];  // key of the face neighbour (the cell itself outside the domain)
@@ -1212,19 +1214,7 @@ __global__ __launch_bounds__(TPB) void k_stage(Geo g, Dev p, int lo, int hi, int
             refined = refined || (in && sv == ST_INTERNAL);
           }
       }
-      if (CODED) refined = (code & CODE_IFACE) != 0;
-      if (!IFACE && !CODED && (PRE || (!finest && !refined)) && (PDE != PDE_NAGUMO && PDE != PDE_LINEAR) &&
-          stencil_reach(g) == 2) {
-#pragma unroll
-        for (int dir = 0; dir < D; dir++)
-#pragma unroll
-          for (int side = 0; side < 2; side++) {
-            uint64_t ky;
-            const bool in = nbhd_key<D>(g, x, key, n, dir, side ? 2 : -2, &ky);
-            const uint8_t sv = p.st[ib + (int64_t)(in ? ky : key)];
-            refined = refined || (in && sv == ST_INTERNAL);
-          }
-      }
+      if (!IFACE) refined = (code & CODE_IFACE) != 0;
       // stencils of all axes (PRE) and the leaf's own slots
       double c5a[PRE ? D : 1][5][M];
       if (PRE) {
